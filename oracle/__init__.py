@@ -1,0 +1,199 @@
+"""Python access to the FP64 CPU oracle (test infrastructure only).
+
+The oracle is a plain C implementation of the compact gas-kinetic scheme for the two-layer shallow
+water equations, written from the paper independently of the HIP library.  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark use it.  ``build()`` compiles it with gcc;
+``load()`` returns the ctypes handle, building on first use if the shared object is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gks_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int)]
+
+
+def build() -> str:
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    lib.om_mesh_new.restype = ctypes.c_void_p
+    lib.om_mesh_new.argtypes = [_dp, ctypes.c_int, _ip, ctypes.c_int, _dp, ctypes.c_int,
+                                ctypes.c_double, ctypes.c_double]
+    lib.om_mesh_free.argtypes = [ctypes.c_void_p]
+    lib.om_mesh_n_edges.argtypes = [ctypes.c_void_p]
+    lib.om_mesh_n_edges.restype = ctypes.c_int
+    lib.om_stencil.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip, _dp]
+    lib.om_lsq_matrix.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
+    lib.om_reconstruct_cell.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, _dp]
+    lib.om_gks_point.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.om_gks_point_integrated.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
+    lib.om_moments.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp]
+    lib.om_time_integrals.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
+    lib.om_dt.restype = ctypes.c_double
+    lib.om_dt.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp]
+    lib.om_operator.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, _dp, _dp,
+                                _dp, _dp, _dp, _dp]
+    lib.om_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, ctypes.c_int,
+                            _dp, _dp, _dp, _dp]
+    lib.om_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.om_cell_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    _lib = lib
+    return lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Mesh:
+    """Oracle mesh: connectivity, stencils and least-squares matrices built in plain C."""
+
+    def __init__(self, node_xy, tri, node_B=None, periodic_L=None):
+        lib = load()
+        self.node_xy = _f64(node_xy)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.node_B = _f64(node_B if node_B is not None else np.zeros(self.node_xy.shape[0]))
+        self.n_tri = int(self.tri.shape[0])
+        per = periodic_L is not None
+        Lx, Ly = (periodic_L if per else (0.0, 0.0))
+        self._h = lib.om_mesh_new(_d(self.node_xy), self.node_xy.shape[0],
+                                  self.tri.ctypes.data_as(_ip), self.n_tri, _d(self.node_B),
+                                  int(per), float(Lx), float(Ly))
+        if not self._h:
+            raise ValueError("oracle rejected the mesh")
+        self.n_edges = lib.om_mesh_n_edges(self._h)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            load().om_mesh_free(self._h)
+            self._h = None
+
+    @classmethod
+    def from_scenario(cls, sc):
+        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None)
+
+    def geometry(self):
+        a, x, y = (np.zeros(self.n_tri) for _ in range(3))
+        load().om_cell_geometry(self._h, _d(a), _d(x), _d(y))
+        return a, x, y
+
+    def stencil(self, c):
+        cells = np.zeros(10, dtype=np.int32)
+        maps = np.zeros((10, 6))
+        load().om_stencil(self._h, c, cells.ctypes.data_as(_ip), _d(maps))
+        return cells, maps
+
+    def lsq_matrix(self, c):
+        M = np.zeros((9, 17))
+        load().om_lsq_matrix(self._h, c, _d(M))
+        return M
+
+    def reconstruct(self, c, W, gW, linear=False):
+        W, gW = _f64(W), _f64(gW)
+        val = np.zeros((6, 6))
+        grad = np.zeros((6, 6, 2))
+        r0 = np.zeros(6)
+        load().om_reconstruct_cell(self._h, c, _d(W), _d(gW), int(linear), _d(val), _d(grad), _d(r0))
+        return val, grad, r0
+
+
+def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False) -> Params:
+    return Params(G, chi, cfl, eps, eps_num, int(linear))
+
+
+def params_of(sc, linear=False) -> Params:
+    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear)
+
+
+def dt(mesh: Mesh, p: Params, W) -> float:
+    return load().om_dt(mesh._h, ctypes.byref(p), _d(_f64(W)))
+
+
+def operator(mesh: Mesh, p: Params, dt_: float, W, gW):
+    T = mesh.n_tri
+    L, Lt = np.zeros((6, T)), np.zeros((6, T))
+    G, Gt = np.zeros((6, 2, T)), np.zeros((6, 2, T))
+    load().om_operator(mesh._h, ctypes.byref(p), float(dt_), _d(_f64(W)), _d(_f64(gW)),
+                       _d(L), _d(Lt), _d(G), _d(Gt))
+    return L, Lt, G, Gt
+
+
+def step(mesh: Mesh, p: Params, dt_: float, W, gW, nstages: int = 2):
+    T = mesh.n_tri
+    Wo, gWo = np.zeros((6, T)), np.zeros((6, 2, T))
+    load().om_step(mesh._h, ctypes.byref(p), float(dt_), int(nstages), _d(_f64(W)), _d(_f64(gW)),
+                   _d(Wo), _d(gWo))
+    return Wo, gWo
+
+
+def run(mesh: Mesh, p: Params, W, gW, t_end: float, max_steps: int = 10 ** 9):
+    """Advance to t_end (last step clipped) with the CFL time step; returns (W, gW, t, steps)."""
+    t, n = 0.0, 0
+    while t < t_end - 1e-14 * max(1.0, t_end) and n < max_steps:
+        d = min(dt(mesh, p, W), t_end - t)
+        W, gW = step(mesh, p, d, W, gW)
+        t += d
+        n += 1
+    return W, gW, t, n
+
+
+def mass(mesh: Mesh, W):
+    out = np.zeros(2)
+    load().om_mass(mesh._h, _d(_f64(W)), _d(out))
+    return out
+
+
+def moments(U, lam, half, K):
+    out = np.zeros(K)
+    load().om_moments(float(U), float(lam), int(half), int(K), _d(out))
+    return out
+
+
+def time_integrals(delta, tau):
+    out = np.zeros(5)
+    load().om_time_integrals(float(delta), float(tau), _d(out))
+    return out
+
+
+def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0):
+    sL, sR = _f64(sideL), _f64(sideR)
+    F0, Ft, Wb, Wbt = (np.zeros(3) for _ in range(4))
+    load().om_gks_point(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
+                        _d(F0), _d(Ft), _d(Wb), _d(Wbt))
+    return F0, Ft, Wb, Wbt
+
+
+def gks_point_integrated(sideL, sideR, G, delta, tau):
+    F = np.zeros(3)
+    load().om_gks_point_integrated(_d(_f64(sideL)), _d(_f64(sideR)), float(G), float(delta),
+                                   float(tau), _d(F))
+    return F

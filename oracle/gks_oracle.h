@@ -1,0 +1,87 @@
+/*
+ * Oracle for the compact gas-kinetic scheme (GKS) for the two-layer shallow water equations on
+ * triangular meshes (Zhao, Gan & Xu, "High-order compact gas-kinetic scheme for two-layer shallow
+ * water equations on unstructured mesh").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64 CPU implementation written
+ * from the paper's equations, used to check the HIP implementation.  Only the test-suite, the smoke
+ * check and the CPU-baseline leg of the benchmark may load it; the product never calls it.  It
+ * shares no source with the HIP library.
+ *
+ * State layout used by every function: W[6][T] cell averages and gW[6][2][T] cell-averaged
+ * gradients, components in the order of the conservative system (Sec. 2.1, Eq. SWE-macro):
+ *   0 h2, 1 h2*U2, 2 h2*V2, 3 h1, 4 h1*U1, 5 h1*V1      (layer 1 = lower, layer 2 = upper).
+ */
+#ifndef GKS_ORACLE_H
+#define GKS_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct om_mesh om_mesh;
+
+typedef struct {
+    double G;        /* gravitational acceleration */
+    double chi;      /* density ratio rho2 / rho1 */
+    double cfl;      /* CFL number of the time step rule (Sec. 4) */
+    double eps;      /* relaxation constant epsilon of the collision time (Sec. 4), 0.05 */
+    double eps_num;  /* pressure-jump constant of the collision time (Sec. 4), 5 */
+    int linear;      /* 1: linear P^3 reconstruction everywhere (all weights at their linear
+                        values), 0: the nonlinear compact reconstruction */
+} om_params;
+
+/* Mesh: node coordinates [nn][2], counter-clockwise triangles [nt][3], bottom at the nodes
+ * (piecewise linear), periodic != 0 pairs the boundary edges of [0,Lx]x[0,Ly] by translation,
+ * otherwise every boundary edge is a reflecting wall.  Returns NULL on a malformed mesh. */
+om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, const double *node_B,
+                     int periodic, double Lx, double Ly);
+void om_mesh_free(om_mesh *m);
+int om_mesh_n_edges(const om_mesh *m);
+
+/* Stencil of cell c: 10 (cell, map) images; cells[10], maps[10][6] = (R00 R01 R10 R11 t0 t1). */
+void om_stencil(const om_mesh *m, int c, int *cells, double *maps);
+/* Least-squares solution matrix of cell c, [9][17] row-major (Sec. 3.4, Eq. Recons-system). */
+void om_lsq_matrix(const om_mesh *m, int c, double *M);
+/* Reconstruction of all six variables in cell c (with eta1 = h1 + B in place of h1) at the cell's
+ * six Gauss points (local edge k, point g -> index 2k+g):
+ *   val[6 gp][6 comp], grad[6 gp][6 comp][2], r0[6 comp] = omega_0 / d_0.
+ * linear != 0 returns the linear P^3 reconstruction (all weights at their linear values). */
+void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear,
+                         double *val, double *grad, double *r0);
+
+/* One Gauss point, one layer, local frame (u along the normal).  side = {h, U, V, dh_n, dh_t,
+ * d(hU)_n, d(hU)_t, d(hV)_n, d(hV)_t, Phi_n, Phi_t}.  Outputs in the local frame. */
+void om_gks_point(const double *sideL, const double *sideR, double G, double dt, double eps,
+                  double eps_num, double *F0, double *Ft, double *Wb, double *Wbt);
+/* Same, returning the time-integrated flux F(delta) for one delta (for the closed-form pins). */
+void om_gks_point_integrated(const double *sideL, const double *sideR, double G, double delta,
+                             double tau, double *F);
+/* Normalised moments <u^k>, k = 0..K-1, of the Gaussian with mean U and variance 1/(2 lambda):
+ * half = 0 full space, +1 over u > 0, -1 over u < 0. */
+void om_moments(double U, double lam, int half, int K, double *out);
+/* Time integrals of the coefficients C1..C5 of the evolution solution over [0, delta]. */
+void om_time_integrals(double delta, double tau, double *g5);
+
+/* Time step from the CFL rule (Sec. 4) for the state W. */
+double om_dt(const om_mesh *m, const om_params *p, const double *W);
+
+/* Spatial operator of one stage: for the stage state (W, gW) and the step's dt, returns
+ * L[6][T], Lt[6][T] (right-hand side and its time derivative) and the Green-Gauss gradients of
+ * the interface values GW[6][2][T], GWt[6][2][T] (Sec. 3.1-3.3). */
+int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
+                double *L, double *Lt, double *GW, double *GWt);
+
+/* One S2O4 step (Sec. 3.3, Eq. SWE-fully-discrete and the two-stage interface update).
+ * nstages = 1 stops after the first stage and returns W^{n+1/2}. */
+int om_step(const om_mesh *m, const om_params *p, double dt, int nstages, const double *W,
+            const double *gW, double *Wout, double *gWout);
+
+/* Per-layer mass sum_j |Omega_j| h_j, mass[0] = upper (h2), mass[1] = lower (h1). */
+void om_mass(const om_mesh *m, const double *W, double *mass);
+void om_cell_geometry(const om_mesh *m, double *area, double *cx, double *cy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

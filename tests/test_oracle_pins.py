@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: adaptive quadrature, closed-form
+fluxes of the shallow water equations, exact polynomial integration, invariances of the equations,
+and the paper's own printed results (well-balance, conservation, accuracy table).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle as o
+import workloads as w
+from tests._exact import mono_avg, poly_avg, poly_eval, poly_grad
+
+G = 9.81
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------------------------------
+# Gaussian moments and time integrals (Sec. 2.2)
+
+@pytest.mark.parametrize("U,lam", [(0.0, 0.3), (0.7, 0.1), (-1.3, 0.05), (2.5, 1.7)])
+def test_moments_match_quadrature(U, lam):
+    rho = lambda u: math.sqrt(lam / math.pi) * math.exp(-lam * (u - U) ** 2)
+    for half, lo, hi in ((0, -np.inf, np.inf), (1, 0.0, np.inf), (-1, -np.inf, 0.0)):
+        got = o.moments(U, lam, half, 7)
+        for k in range(7):
+            ref, _ = integrate.quad(lambda u: u ** k * rho(u), lo, hi, epsabs=1e-14, epsrel=1e-13, limit=200)
+            assert abs(got[k] - ref) <= 1e-11 * max(1.0, abs(ref)), (half, k, got[k], ref)
+
+
+@pytest.mark.parametrize("delta,tau", [(1e-3, 5e-5), (2e-2, 1e-2), (0.1, 0.3)])
+def test_time_integrals_match_quadrature(delta, tau):
+    # coefficients of the evolution solution (Sec. 2.2) integrated numerically over [0, delta]
+    C = [lambda t: 1 - math.exp(-t / tau),
+         lambda t: -tau * (1 - math.exp(-t / tau)) + t * math.exp(-t / tau),
+         lambda t: -tau * (1 - math.exp(-t / tau)) + t,
+         lambda t: math.exp(-t / tau),
+         lambda t: -t * math.exp(-t / tau)]
+    got = o.time_integrals(delta, tau)
+    for i in range(5):
+        ref, _ = integrate.quad(C[i], 0.0, delta, epsabs=1e-18, epsrel=1e-13)
+        assert abs(got[i] - ref) <= 1e-11 * max(abs(ref), delta * delta * 1e-6), (i, got[i], ref)
+
+
+# ------------------------------------------------------------------------------------------
+# the gas-kinetic flux at one Gauss point
+
+def _side(h, U, V, dh=(0, 0), dm=(0, 0), dn=(0, 0), phi=(0, 0)):
+    # h, U, V, dh_n, dh_t, d(hU)_n, d(hU)_t, d(hV)_n, d(hV)_t, Phi_n, Phi_t
+    return np.array([h, U, V, dh[0], dh[1], dm[0], dm[1], dn[0], dn[1], phi[0], phi[1]], dtype=float)
+
+
+def _euler_flux(h, U, V):
+    return np.array([h * U, h * U * U + 0.5 * G * h * h, h * U * V])
+
+
+@pytest.mark.parametrize("h,U,V", [(1.0, 0.3, -0.2), (0.2, -1.5, 0.7), (2.0, 0.0, 0.0)])
+def test_flux_uniform_state_is_exact_flux(h, U, V):
+    s = _side(h, U, V)
+    for delta, tau in ((0.01, 5e-4), (0.01, 0.02), (0.003, 1e-7)):
+        F = o.gks_point_integrated(s, s, G, delta, tau)
+        np.testing.assert_allclose(F / delta, _euler_flux(h, U, V), rtol=1e-12, atol=1e-13)
+    F0, Ft, Wb, Wbt = o.gks_point(s, s, G, 0.01)
+    np.testing.assert_allclose(F0, _euler_flux(h, U, V), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(Ft, 0, atol=1e-9)
+    np.testing.assert_allclose(Wb, [h, h * U, h * V], rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(Wbt, 0, atol=1e-13)
+
+
+def test_flux_lake_at_rest_balances():
+    # still water over a sloping bottom: dh = -dB, acceleration -G dB (both sides identical)
+    dB = np.array([0.37, -0.21])
+    h = 0.6
+    s = _side(h, 0, 0, dh=-dB, phi=-G * dB)
+    F0, Ft, Wb, Wbt = o.gks_point(s, s, G, 0.004)
+    np.testing.assert_allclose(F0, [0, 0.5 * G * h * h, 0], atol=1e-14)
+    np.testing.assert_allclose(Ft, 0, atol=1e-10)
+    np.testing.assert_allclose(Wbt, 0, atol=1e-14)
+
+
+def _swe_time_derivative(h, U, V, dh, dm, dn, phi):
+    """dW/dt of the single-layer shallow water system with acceleration phi, from the flux
+    Jacobians (chain rule), in the local frame with derivatives along (n, t)."""
+    # dF^n/dW and dF^t/dW for W = (h, hU, hV)
+    An = np.array([[0, 1, 0], [G * h - U * U, 2 * U, 0], [-U * V, V, U]])
+    At = np.array([[0, 0, 1], [-U * V, V, U], [G * h - V * V, 0, 2 * V]])
+    dWn = np.array([dh[0], dm[0], dn[0]])
+    dWt = np.array([dh[1], dm[1], dn[1]])
+    S = np.array([0.0, h * phi[0], h * phi[1]])
+    return -An @ dWn - At @ dWt + S, An, At, dWn, dWt
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_flux_smooth_limit_matches_pde(seed):
+    rng = np.random.default_rng(seed)
+    h, U, V = rng.uniform(0.5, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1)
+    dh, dm, dn, phi = (rng.uniform(-0.5, 0.5, 2) for _ in range(4))
+    s = _side(h, U, V, dh, dm, dn, phi)
+    Wt, An, At, dWn, dWt = _swe_time_derivative(h, U, V, dh, dm, dn, phi)
+    F0, Ft, Wb, Wbt = o.gks_point(s, s, G, 1e-3)
+    np.testing.assert_allclose(Wbt, Wt, rtol=1e-12, atol=1e-12)
+    # vanishing collision time: F(delta) = delta F(W) + delta^2/2 dF/dt with dF/dt = A_n W_t
+    delta, tau = 1e-2, 1e-13
+    F = o.gks_point_integrated(s, s, G, delta, tau)
+    ref = delta * _euler_flux(h, U, V) + 0.5 * delta ** 2 * (An @ Wt)
+    np.testing.assert_allclose(F, ref, rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [3, 4, 5])
+def test_flux_mirror_symmetry(seed):
+    """Reflecting x_n -> -x_n swaps the sides: mass and tangential-momentum fluxes change sign,
+    the normal-momentum flux does not."""
+    rng = np.random.default_rng(seed)
+
+    def rnd():
+        return _side(rng.uniform(0.5, 1.5), rng.uniform(-1, 1), rng.uniform(-1, 1),
+                     rng.uniform(-0.5, 0.5, 2), rng.uniform(-0.5, 0.5, 2), rng.uniform(-0.5, 0.5, 2),
+                     rng.uniform(-2, 2, 2))
+
+    def mirror(s):
+        m = s.copy()
+        m[1] = -s[1]                 # U_n
+        m[3] = -s[3]                 # dh/dn
+        m[6] = -s[6]                 # d(hU_n)/dt
+        m[7] = -s[7]                 # d(hU_t)/dn
+        m[9] = -s[9]                 # Phi_n
+        return m
+
+    sL, sR = rnd(), rnd()
+    F0, Ft, Wb, Wbt = o.gks_point(sL, sR, G, 2e-3)
+    M0, Mt, Mb, Mbt = o.gks_point(mirror(sR), mirror(sL), G, 2e-3)
+    sgn = np.array([-1, 1, -1])
+    np.testing.assert_allclose(M0, sgn * F0, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(Mt, sgn * Ft, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(Mb, -sgn * Wb, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(Mbt, -sgn * Wbt, rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------------------------------------------------------
+# reconstruction (Sec. 3.4)
+
+MONO = [(1, 0), (0, 1), (2, 0), (1, 1), (0, 2), (3, 0), (2, 1), (1, 2), (0, 3)]
+FAC = [1, 1, 0.5, 1, 0.5, 1 / 6, 0.5, 0.5, 1 / 6]
+
+
+def _image_tri(mesh_xy, tri, cell, mp):
+    R = np.array([[mp[0], mp[1]], [mp[2], mp[3]]])
+    t = mp[4:6]
+    return (R @ mesh_xy[tri[cell]].T).T + t
+
+
+@pytest.mark.parametrize("kind", ["periodic", "wall"])
+def test_lsq_matrix_matches_svd_pseudoinverse(kind):
+    if kind == "periodic":
+        sc = w.smooth_periodic(6)
+    else:
+        sc = w.lake_at_rest(6, seed=11)
+    mesh = o.Mesh.from_scenario(sc)
+    area, cx, cy = mesh.geometry()
+    for c in range(0, sc.n_tri, 7):
+        cells, maps = mesh.stencil(c)
+        x0 = (cx[c], cy[c])
+        h = math.sqrt(2 * area[c])
+        t0 = _image_tri(sc.node_xy, sc.tri, cells[0], maps[0])
+        off = [FAC[k] * mono_avg(t0, x0, *MONO[k]) for k in range(9)]
+        A = np.zeros((17, 9))
+        for l in range(10):
+            tl = _image_tri(sc.node_xy, sc.tri, cells[l], maps[l])
+            for k, (p, q) in enumerate(MONO):
+                if l >= 1:
+                    A[l - 1, k] = FAC[k] * mono_avg(tl, x0, p, q) - off[k]
+                if l <= 3:
+                    A[9 + 2 * l, k] = h * FAC[k] * p * mono_avg(tl, x0, p - 1, q) if p else 0.0
+                    A[10 + 2 * l, k] = h * FAC[k] * q * mono_avg(tl, x0, p, q - 1) if q else 0.0
+        M_ref = np.linalg.pinv(A)
+        M = mesh.lsq_matrix(c)
+        scale = np.abs(M_ref).max(axis=1, keepdims=True)
+        assert np.all(np.abs(M - M_ref) <= 1e-9 * scale), (c, np.abs(M - M_ref).max())
+
+
+def test_stencil_topology():
+    sc = w.lake_at_rest(7, seed=3)
+    mesh = o.Mesh.from_scenario(sc)
+    for c in range(sc.n_tri):
+        cells, maps = mesh.stencil(c)
+        tris = [_image_tri(sc.node_xy, sc.tri, cells[l], maps[l]) for l in range(10)]
+
+        def shared(a, b):
+            return sum(np.min(np.linalg.norm(a[i] - b, axis=1)) < 1e-12 for i in range(3))
+
+        for k in range(3):
+            assert shared(tris[0], tris[1 + k]) == 2          # face neighbours share an edge
+            for q in range(2):
+                nb = tris[4 + 2 * k + q]
+                assert shared(tris[1 + k], nb) == 2           # second ring shares an edge with it
+                assert shared(tris[0], nb) < 3
+            # the face neighbour across local edge k contains vertices k and k+1 of the cell
+            for v in (k, (k + 1) % 3):
+                assert np.min(np.linalg.norm(tris[1 + k] - tris[0][v], axis=1)) < 1e-12
+
+
+def _poly_cell_data(sc, polys):
+    """Exact cell averages and cell-averaged gradients of six polynomials -> W[6,T], gW[6,2,T]."""
+    T = sc.n_tri
+    W = np.zeros((6, T))
+    gW = np.zeros((6, 2, T))
+    for c in range(T):
+        tv = sc.node_xy[sc.tri[c]]
+        for v, P in enumerate(polys):
+            W[v, c] = poly_avg(tv, P)
+            Px = {(p - 1, q): cf * p for (p, q), cf in P.items() if p > 0}
+            Py = {(p, q - 1): cf * q for (p, q), cf in P.items() if q > 0}
+            gW[v, 0, c] = poly_avg(tv, Px) if Px else 0.0
+            gW[v, 1, c] = poly_avg(tv, Py) if Py else 0.0
+    return W, gW
+
+
+def _gauss_points(tv):
+    s = [0.5 - math.sqrt(3) / 6, 0.5 + math.sqrt(3) / 6]
+    return [tv[k] + s[g] * (tv[(k + 1) % 3] - tv[k]) for k in range(3) for g in range(2)]
+
+
+@pytest.mark.parametrize("degree,linear", [(3, True), (1, False)])
+def test_reconstruction_reproduces_polynomials(degree, linear):
+    """Cubic data are reproduced exactly by the linear least-squares P^3 and linear data by the
+    nonlinear combination (every candidate is exact)."""
+    sc = w.lake_at_rest(8, seed=5, bump_amp=0.0)
+    rng = np.random.default_rng(7)
+    polys = []
+    for v in range(6):
+        P = {(p, q): rng.uniform(-1, 1) for p in range(degree + 1) for q in range(degree + 1 - p)}
+        P[(0, 0)] += 2.0
+        polys.append(P)
+    W, gW = _poly_cell_data(sc, polys)
+    mesh = o.Mesh.from_scenario(sc)
+    interior = [c for c in range(sc.n_tri) if np.all(sc.node_xy[sc.tri[c]] > 0.2) and np.all(sc.node_xy[sc.tri[c]] < 0.8)]
+    assert len(interior) > 10
+    for c in interior[::3]:
+        val, grad, r0 = mesh.reconstruct(c, W, gW, linear=linear)
+        for p, x in enumerate(_gauss_points(sc.node_xy[sc.tri[c]])):
+            for v in range(6):
+                ref = poly_eval(polys[v], *x)
+                gx, gy = poly_grad(polys[v], *x)
+                assert abs(val[p, v] - ref) < 1e-11, (c, p, v, val[p, v], ref)
+                assert abs(grad[p, v, 0] - gx) < 1e-9 and abs(grad[p, v, 1] - gy) < 1e-9
+
+
+def test_reconstruction_nonoscillatory_at_a_jump():
+    """At a step the nonlinear combination stays close to the data range where the linear P^3
+    overshoots (the purpose of the WENO-type reconstruction, Sec. 3.4)."""
+    sc = w.lake_at_rest(16, seed=9, bump_amp=0.0)
+    T = sc.n_tri
+    cen = sc.node_xy[sc.tri].mean(axis=1)
+    W = np.zeros((6, T))
+    W[0] = np.where(cen[:, 0] + 0.3 * cen[:, 1] < 0.62, 1.0, 0.5)
+    W[3] = 1.0
+    gW = np.zeros((6, 2, T))
+    mesh = o.Mesh.from_scenario(sc)
+    over_lin, over_nl = 0.0, 0.0
+    for c in range(T):
+        vl, _, _ = mesh.reconstruct(c, W, gW, linear=True)
+        vn, _, _ = mesh.reconstruct(c, W, gW, linear=False)
+        over_lin = max(over_lin, (vl[:, 0] - 1.0).max(), (0.5 - vl[:, 0]).max())
+        over_nl = max(over_nl, (vn[:, 0] - 1.0).max(), (0.5 - vn[:, 0]).max())
+    assert over_lin > 0.05
+    assert over_nl < 0.25 * over_lin, (over_nl, over_lin)
+
+
+# ------------------------------------------------------------------------------------------
+# whole scheme: well-balance, conservation, invariances, accuracy
+
+def _advance(sc, steps, mesh=None):
+    mesh = mesh or o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    W, gW = sc.W0.copy(), sc.gradW0.copy()
+    for _ in range(steps):
+        d = o.dt(mesh, p, W)
+        W, gW = o.step(mesh, p, d, W, gW)
+    return mesh, W, gW
+
+
+def test_lake_at_rest_is_preserved_to_roundoff():
+    """Sec. 3.2: h1 + B = const, h2 = const, U = 0 is kept (the paper reports < 1e-8; the scheme
+    with these readings keeps it to round-off)."""
+    sc = w.lake_at_rest(10, chi=0.98)
+    mesh, W, gW = _advance(sc, 60)
+    assert np.abs(W[[1, 2, 4, 5]]).max() < 1e-13
+    assert np.abs(W[0] - sc.W0[0]).max() < 1e-13
+    assert np.abs(W[3] - sc.W0[3]).max() < 1e-13
+    assert np.abs(gW - sc.gradW0).max() < 1e-11
+
+
+@pytest.mark.parametrize("make", [lambda: w.lake_at_rest(9, perturb=1e-2),
+                                  lambda: w.dam_break(8, left=(1.0, 0.5), right=(0.6, 0.9)),
+                                  lambda: w.smooth_periodic(8)])
+def test_layer_mass_is_conserved(make):
+    sc = make()
+    mesh = o.Mesh.from_scenario(sc)
+    m0 = o.mass(mesh, sc.W0)
+    _, W, _ = _advance(sc, 8, mesh)
+    m1 = o.mass(mesh, W)
+    assert np.all(np.abs(m1 - m0) <= 1e-14 * m0 * 8), (m1 - m0) / m0
+    assert np.isfinite(W).all() and (W[[0, 3]] > 0).all()
+
+
+def _rotate_scenario(sc, th):
+    R = np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    xy = sc.node_xy @ R.T
+    W = sc.W0.copy()
+    gW = sc.gradW0.copy()
+    for o_ in (0, 3):
+        W[o_ + 1:o_ + 3] = R @ sc.W0[o_ + 1:o_ + 3]
+        gW[o_] = R @ sc.gradW0[o_]
+        Gm = sc.gradW0[o_ + 1:o_ + 3]                           # [a, d, T] = d m_a / d x_d
+        gW[o_ + 1:o_ + 3] = np.einsum("ab,bdt,cd->act", R, Gm, R)
+    import dataclasses
+    return dataclasses.replace(sc, node_xy=xy, W0=W, gradW0=gW), R
+
+
+@pytest.mark.parametrize("theta,linear", [(0.7, True), (math.pi / 2, False)])
+def test_rotation_equivariance(theta, linear):
+    """The equations are rotation invariant.  The nonlinear weights act on each momentum component
+    separately, so with them only quarter turns (which permute / negate the components) are exact;
+    the linear reconstruction is checked at an arbitrary angle."""
+    sc = w.lake_at_rest(7, perturb=2e-2, seed=21)
+    sc.W0[4] = 0.05 * sc.W0[3]  # add a flow so that momentum rotation matters
+    sc.W0[2] = -0.03 * sc.W0[0]
+    rs, R = _rotate_scenario(sc, theta)
+    m1, m2 = o.Mesh.from_scenario(sc), o.Mesh.from_scenario(rs)
+    p = o.params_of(sc, linear=linear)
+    d = 0.8 * o.dt(m1, p, sc.W0)
+    W1, g1 = o.step(m1, p, d, sc.W0, sc.gradW0)
+    W2, g2 = o.step(m2, p, d, rs.W0, rs.gradW0)
+    W1r = W1.copy()
+    for o_ in (0, 3):
+        W1r[o_ + 1:o_ + 3] = R @ W1[o_ + 1:o_ + 3]
+    np.testing.assert_allclose(W2, W1r, rtol=0, atol=1e-12)
+    g1r = g1.copy()
+    for o_ in (0, 3):
+        g1r[o_] = R @ g1[o_]
+        g1r[o_ + 1:o_ + 3] = np.einsum("ab,bdt,cd->act", R, g1[o_ + 1:o_ + 3], R)
+    np.testing.assert_allclose(g2, g1r, rtol=0, atol=1e-10)
+
+
+def test_cell_numbering_invariance():
+    sc = w.dam_break(7, left=(1.0, 0.5), right=(0.7, 0.8))
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(sc.n_tri)
+    tri = sc.tri[perm]
+    shift = rng.integers(0, 3, sc.n_tri)
+    tri = np.stack([np.roll(tri[i], shift[i]) for i in range(sc.n_tri)])
+    m1 = o.Mesh.from_scenario(sc)
+    m2 = o.Mesh(sc.node_xy, tri, sc.node_B)
+    p = o.params_of(sc)
+    d = o.dt(m1, p, sc.W0)
+    W1, g1 = o.step(m1, p, d, sc.W0, sc.gradW0)
+    W2, g2 = o.step(m2, p, d, sc.W0[:, perm], sc.gradW0[:, :, perm])
+    np.testing.assert_allclose(W2, W1[:, perm], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(g2, g1[:, :, perm], rtol=0, atol=1e-11)
+
+
+def _e1_error(n):
+    sc = w.accuracy_e1(n)
+    mesh = o.Mesh.from_scenario(sc)
+    W, gW, t, _ = o.run(mesh, o.params_of(sc), sc.W0, sc.gradW0, sc.t_end)
+    ex = sc.exact(t)
+    a, _, _ = mesh.geometry()
+    return [(a * np.abs(W[v] - ex[v])).sum() / a.sum() for v in (3, 0)]
+
+
+def test_accuracy_table_magnitude_and_order():
+    """Sec. 4.1 accuracy test (table of L1 errors at t = 0.1): same magnitude as the printed
+    errors at h_re = 1/8 and 1/16 and close to second-order convergence, the order the paper
+    attributes to its second-order layer-coupling source."""
+    with open(os.path.join(GOLDEN, "accuracy_table.json")) as f:
+        gold = json.load(f)
+    errs = {"1/8": _e1_error(16), "1/16": _e1_error(32), "1/32": _e1_error(64)}
+    for v, key in ((0, "h1"), (1, "h2")):
+        for row, e in errs.items():
+            # the paper does not state its mesh or the L1 normalisation: agree within a factor 5
+            ref = gold["rows"][row][key]
+            assert ref / 5 < e[v] < 5 * ref, (key, row, e[v], ref)
+        # mean order over h_re = 1/8 .. 1/32
+        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.8

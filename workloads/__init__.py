@@ -1,0 +1,17 @@
+"""Seeded synthetic inputs shared by the HIP path, its tests, the bench and the oracle's tests.
+
+This package builds triangular meshes and initial cell data for the two-layer shallow water
+problems (meshes, bottom topography at nodes, cell averages and cell-averaged gradients of the
+initial state).  It holds none of the scheme's arithmetic: no reconstruction, flux, source or
+time-stepping code lives here, only geometry generation and quadrature of analytic initial data.
+"""
+from .meshes import periodic_square, jittered_square  # noqa: F401
+from .scenarios import (  # noqa: F401
+    Scenario,
+    smooth_periodic,
+    accuracy_e1,
+    lake_at_rest,
+    dam_break,
+    ensemble,
+    COMPONENTS,
+)

@@ -1,0 +1,235 @@
+"""Initial data for the two-layer shallow water test problems.
+
+The state is given as cell averages ``W0[6, T]`` and cell-averaged gradients ``gradW0[6, 2, T]``
+in the component order of the conservative system: (h2, h2 U2, h2 V2, h1, h1 U1, h1 V1), layer 1
+being the lower, denser layer.  Smooth data are averaged with a collapsed (Duffy) Gauss-Legendre
+rule over each triangle and the gradients come from the divergence theorem with Gauss-Legendre
+points on the edges.  Rest states over a bottom given at the nodes use that bottom's piecewise
+linear interpolant, so that h1 + B is exactly the prescribed level cell by cell.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+from .meshes import jittered_square, periodic_square
+
+COMPONENTS = ("h2", "h2U2", "h2V2", "h1", "h1U1", "h1V1")
+
+
+@dataclasses.dataclass
+class Scenario:
+    name: str
+    node_xy: np.ndarray          # [N, 2] f64
+    tri: np.ndarray              # [T, 3] i32, counter-clockwise
+    node_B: np.ndarray           # [N] f64 bottom at nodes (piecewise linear)
+    boundary: str                # "periodic" or "wall"
+    periodic_L: Optional[tuple]  # (Lx, Ly) for periodic meshes
+    G: float
+    chi: float
+    cfl: float
+    t_end: float
+    W0: np.ndarray               # [6, T]
+    gradW0: np.ndarray           # [6, 2, T]
+    exact: Optional[Callable] = None  # exact(t) -> W cell averages [6, T] when known
+
+    @property
+    def n_tri(self) -> int:
+        return int(self.tri.shape[0])
+
+
+# ---------------------------------------------------------------------------------------------
+# quadrature of analytic data (input preparation only)
+
+def _gl01(q: int):
+    x, w = np.polynomial.legendre.leggauss(q)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def _tri_rule(q: int):
+    """Collapsed Gauss-Legendre rule on the reference triangle {(s, t): s, t >= 0, s + t <= 1}.
+
+    Returns barycentric-free reference points (s, t) and weights summing to 1 (an average)."""
+    g, w = _gl01(q)
+    s = np.repeat(g, q)
+    r = np.tile(g, q)
+    t = r * (1.0 - s)
+    wt = np.repeat(w, q) * np.tile(w, q) * (1.0 - s)
+    return s, t, wt / wt.sum()
+
+
+def _geometry(xy, tri):
+    a, b, c = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    area = 0.5 * ((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+    return a, b, c, area
+
+
+def cell_average(xy, tri, fn, q: int = 8):
+    """Average of fn(x, y) (vectorised, returns [k, ...]) over each triangle -> [k, T]."""
+    a, b, c, _ = _geometry(xy, tri)
+    s, t, w = _tri_rule(q)
+    acc = None
+    for sk, tk, wk in zip(s, t, w):
+        x = a[:, 0] + sk * (b[:, 0] - a[:, 0]) + tk * (c[:, 0] - a[:, 0])
+        y = a[:, 1] + sk * (b[:, 1] - a[:, 1]) + tk * (c[:, 1] - a[:, 1])
+        v = np.asarray(fn(x, y)) * wk
+        acc = v if acc is None else acc + v
+    return acc
+
+
+def cell_gradient(xy, tri, fn, q: int = 8):
+    """Cell-averaged gradient (1/|T|) * boundary integral of fn * n over each triangle -> [k, 2, T]."""
+    a, b, c, area = _geometry(xy, tri)
+    g, w = _gl01(q)
+    acc = None
+    for p, r in ((a, b), (b, c), (c, a)):
+        ex, ey = r[:, 0] - p[:, 0], r[:, 1] - p[:, 1]
+        # outward normal times edge length for a counter-clockwise triangle
+        nlx, nly = ey, -ex
+        for gk, wk in zip(g, w):
+            x = p[:, 0] + gk * ex
+            y = p[:, 1] + gk * ey
+            v = np.asarray(fn(x, y)) * wk
+            term = np.stack([v * nlx, v * nly], axis=-2)
+            acc = term if acc is None else acc + term
+    return acc / area
+
+
+def _p1_bottom(xy, tri, node_B):
+    """Mean and gradient of the piecewise-linear bottom on each triangle."""
+    a, b, c, area = _geometry(xy, tri)
+    Ba, Bb, Bc = node_B[tri[:, 0]], node_B[tri[:, 1]], node_B[tri[:, 2]]
+    mean = (Ba + Bb + Bc) / 3.0
+    # gradient of the plane through the three vertices
+    gx = (Ba * (b[:, 1] - c[:, 1]) + Bb * (c[:, 1] - a[:, 1]) + Bc * (a[:, 1] - b[:, 1])) / (2 * area)
+    gy = (Ba * (c[:, 0] - b[:, 0]) + Bb * (a[:, 0] - c[:, 0]) + Bc * (b[:, 0] - a[:, 0])) / (2 * area)
+    return mean, gx, gy
+
+
+def _pack_smooth(xy, tri, prim):
+    """prim(x, y) -> (h2, U2, V2, h1, U1, V1) arrays; returns conservative averages and gradients."""
+
+    def cons(x, y):
+        h2, U2, V2, h1, U1, V1 = prim(x, y)
+        return np.stack([h2, h2 * U2, h2 * V2, h1, h1 * U1, h1 * V1])
+
+    return cell_average(xy, tri, cons), cell_gradient(xy, tri, cons)
+
+
+# ---------------------------------------------------------------------------------------------
+# the problems
+
+def smooth_periodic(n: int = 20, chi: float = 0.98, cfl: float = 0.3, t_end: float = 0.1,
+                    G: float = 9.81) -> Scenario:
+    """Periodic [0,2]^2, flat bottom, h1 = 1 + 0.2 sin(pi(x+y)), h2 = 1 - 0.1 sin(pi(x+y)),
+    U = V = 0.5 in both layers (the small single-instance FP64 problem)."""
+    xy, tri, L = periodic_square(n, 2.0)
+
+    def prim(x, y):
+        s = np.sin(np.pi * (x + y))
+        one = np.ones_like(x)
+        return (1.0 - 0.1 * s, 0.5 * one, 0.5 * one, 1.0 + 0.2 * s, 0.5 * one, 0.5 * one)
+
+    W0, gW0 = _pack_smooth(xy, tri, prim)
+    return Scenario(f"smooth_periodic_n{n}", xy, tri, np.zeros(xy.shape[0]), "periodic", L, G, chi,
+                    cfl, t_end, W0, gW0)
+
+
+def accuracy_e1(n: int, cfl: float = 0.5, t_end: float = 0.1, G: float = 9.81) -> Scenario:
+    """Translating two-layer Gaussian with chi = 1 on [0,2]^2 (mesh leg h = 2/n), exact solution
+    known: h1 = 0.9 + 0.02 exp(-50 |x - (1+t, 1+t)|^2), h2 = 1 - h1, U = V = 1."""
+    xy, tri, L = periodic_square(n, 2.0)
+
+    def prim_at(t):
+        def prim(x, y):
+            h1 = 0.9 + 0.02 * np.exp(-50.0 * ((x - 1.0 - t) ** 2 + (y - 1.0 - t) ** 2))
+            one = np.ones_like(x)
+            return (1.0 - h1, one, one, h1, one, one)
+        return prim
+
+    W0, gW0 = _pack_smooth(xy, tri, prim_at(0.0))
+
+    def exact(t):
+        return _pack_smooth(xy, tri, prim_at(t))[0]
+
+    return Scenario(f"accuracy_e1_n{n}", xy, tri, np.zeros(xy.shape[0]), "periodic", L, G, 1.0,
+                    cfl, t_end, W0, gW0, exact)
+
+
+def _bump(xy, amp=0.5, cx=0.5, cy=0.5, k=50.0):
+    return amp * np.exp(-k * ((xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2))
+
+
+def lake_at_rest(n: int, seed: int = 20230604, chi: float = 0.98, eta1: float = 0.8,
+                 h2: float = 0.2, perturb: float = 0.0, disk=(0.3, 0.3, 0.1), cfl: float = 0.3,
+                 t_end: float = 1e9, G: float = 9.81, bump_amp: float = 0.5) -> Scenario:
+    """Jittered Delaunay mesh of [0,1]^2 with walls, bottom B = bump_amp exp(-50 r^2) about the
+    centre, lower-layer level h1 + B = eta1, upper layer h2, at rest.  With ``perturb`` != 0 the
+    interface inside the disk |x - (cx, cy)| < r (cell centroids) is raised by ``perturb`` and the
+    upper layer thinned by the same amount (free surface unchanged)."""
+    xy, tri = jittered_square(n, seed)
+    node_B = _bump(xy, amp=bump_amp)
+    return _level_state(f"lake_at_rest_n{n}", xy, tri, node_B, chi, cfl, t_end, G,
+                        lambda cx, cy: (np.full_like(cx, eta1), np.full_like(cx, h2)),
+                        perturb, disk)
+
+
+def dam_break(n: int, seed: int = 20230605, chi: float = 0.95, x_dam: float = 0.5,
+              left=(1.0, 0.5), right=(0.5, 1.0), sin_amp: float = 0.1, bump_amp: float = 0.0,
+              cfl: float = 0.3, t_end: float = 1e9, G: float = 9.81) -> Scenario:
+    """Two-layer dam break on a jittered mesh of [0,1]^2 with walls: lower-layer level h1 + B and
+    upper thickness h2 jump from ``left`` to ``right`` across x = x_dam (by cell centroid), bottom
+    B = sin_amp sin(2 pi x) sin(2 pi y) + bump_amp exp(-50 |x - (0.75, 0.5)|^2), fluid at rest."""
+    xy, tri = jittered_square(n, seed)
+    node_B = sin_amp * np.sin(2 * np.pi * xy[:, 0]) * np.sin(2 * np.pi * xy[:, 1])
+    if bump_amp:
+        node_B = node_B + _bump(xy, amp=bump_amp, cx=0.75, cy=0.5)
+
+    def levels(cx, cy):
+        lft = cx < x_dam
+        return np.where(lft, left[0], right[0]), np.where(lft, left[1], right[1])
+
+    return _level_state(f"dam_break_n{n}", xy, tri, node_B, chi, cfl, t_end, G, levels, 0.0, None)
+
+
+def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, disk):
+    T = tri.shape[0]
+    Bm, Bx, By = _p1_bottom(xy, tri, node_B)
+    c = xy[tri].mean(axis=1)
+    eta1, h2 = levels(c[:, 0], c[:, 1])
+    eta1 = np.asarray(eta1, dtype=np.float64).copy()
+    h2 = np.asarray(h2, dtype=np.float64).copy()
+    if perturb:
+        cx, cy, r = disk
+        inside = (c[:, 0] - cx) ** 2 + (c[:, 1] - cy) ** 2 < r * r
+        eta1[inside] += perturb
+        h2[inside] -= perturb
+    W0 = np.zeros((6, T))
+    gW0 = np.zeros((6, 2, T))
+    W0[0] = h2
+    W0[3] = eta1 - Bm
+    gW0[3, 0] = -Bx
+    gW0[3, 1] = -By
+    if (W0[3] <= 0).any() or (W0[0] <= 0).any():
+        raise ValueError("non-positive layer thickness in initial data")
+    return Scenario(name, xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0)
+
+
+def ensemble(n_scen: int = 256, seed: int = 20230606, t_min: int = 5000, t_max: int = 200000,
+             cfl: float = 0.3, G: float = 9.81):
+    """Independent bump + rest + disk-perturbation scenarios with log-uniform sizes, log-uniform
+    perturbation amplitudes in [1e-4, 1e-2] and density ratios uniform in [0.90, 0.99]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for s in range(n_scen):
+        T = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
+        n = max(4, int(round(math.sqrt(T / 2.0))))
+        amp = math.exp(rng.uniform(math.log(1e-4), math.log(1e-2)))
+        chi = float(rng.uniform(0.90, 0.99))
+        sc = lake_at_rest(n, seed=seed + 1 + s, chi=chi, perturb=amp, cfl=cfl, G=G)
+        sc.name = f"ensemble_{s}_n{n}"
+        out.append(sc)
+    return out

@@ -1,0 +1,173 @@
+"""Thin ctypes binding of the HIP library's C ABI (include/gks.h).
+
+Argument marshalling only: every step of the scheme runs in the library's kernels.  The binding
+raises if the shared object is missing; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgks.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_vp = ctypes.c_void_p
+
+GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_EMESH, GKS_ENONFINITE, GKS_EUNSUPPORTED = range(7)
+GKS_BC_WALL, GKS_BC_PERIODIC = 0, 1
+GKS_FP64 = 0
+
+# every entry point declared in include/gks.h
+SYMBOLS = ("gks_mesh_create", "gks_mesh_destroy", "gks_mesh_info", "gks_state_init", "gks_state_destroy",
+           "gks_stage", "gks_step", "gks_state_read", "gks_state_mass", "gks_last_error")
+
+
+class GksError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gks error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("t_end", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("linear", ctypes.c_int32)]
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.gks_last_error.restype = ctypes.c_char_p
+    lib.gks_mesh_create.argtypes = [_dp, ctypes.c_int64, _i32p, ctypes.c_int64, _dp, ctypes.c_int32, _dp,
+                                    ctypes.POINTER(_vp)]
+    lib.gks_mesh_destroy.argtypes = [_vp]
+    lib.gks_mesh_destroy.restype = None
+    lib.gks_mesh_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64)]
+    lib.gks_state_init.argtypes = [_vp, ctypes.POINTER(Params), _dp, _dp, _vp, ctypes.POINTER(_vp)]
+    lib.gks_state_destroy.argtypes = [_vp]
+    lib.gks_state_destroy.restype = None
+    lib.gks_stage.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_step.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_state_read.argtypes = [_vp, _dp, _dp, _dp]
+    lib.gks_state_mass.argtypes = [_vp, _dp]
+    for name in SYMBOLS:
+        if name not in ("gks_mesh_destroy", "gks_state_destroy", "gks_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != GKS_OK:
+        raise GksError(code, load().gks_last_error().decode())
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def current_stream():
+    """Handle of torch's current HIP stream (device memory and streams come from PyTorch)."""
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible to torch")
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Mesh:
+    def __init__(self, node_xy, tri, node_B=None, periodic_L=None):
+        lib = load()
+        self.node_xy = _f64(node_xy)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nB = None if node_B is None else _f64(node_B)
+        per = None if periodic_L is None else _f64(periodic_L)
+        h = _vp()
+        _check(lib.gks_mesh_create(_d(self.node_xy), self.node_xy.shape[0], self.tri.ctypes.data_as(_i32p),
+                                   self.tri.shape[0], None if nB is None else _d(nB),
+                                   GKS_BC_PERIODIC if per is not None else GKS_BC_WALL,
+                                   None if per is None else _d(per), ctypes.byref(h)))
+        self._h = h
+        T, E, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.gks_mesh_info(h, ctypes.byref(T), ctypes.byref(E), ctypes.byref(NG)))
+        self.n_tri, self.n_edges, self.n_ghost = T.value, E.value, NG.value
+
+    @classmethod
+    def from_scenario(cls, sc):
+        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gks_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class State:
+    def __init__(self, mesh: Mesh, W0, gradW0, G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0,
+                 t_end=0.0, linear=False, stream=None):
+        lib = load()
+        self.mesh = mesh
+        T = mesh.n_tri
+        W0 = _f64(W0).reshape(6, T)
+        gW0 = _f64(gradW0).reshape(6, 2, T)
+        self.params = Params(G, chi, cfl, eps, eps_num, t_end, GKS_FP64, int(linear))
+        if stream is None:
+            stream = current_stream()
+        self.stream = stream
+        h = _vp()
+        _check(lib.gks_state_init(mesh._h, ctypes.byref(self.params), _d(W0), _d(gW0), stream, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_scenario(cls, mesh, sc, **kw):
+        return cls(mesh, sc.W0, sc.gradW0, G=sc.G, chi=sc.chi, cfl=sc.cfl, **kw)
+
+    def stage(self, k, dt=None):
+        d = None if dt is None else ctypes.byref(ctypes.c_double(dt))
+        _check(load().gks_stage(self._h, int(k), d))
+
+    def step(self, n=1, want_dt=False):
+        if want_dt:
+            d = ctypes.c_double()
+            _check(load().gks_step(self._h, int(n), ctypes.byref(d)))
+            return d.value
+        _check(load().gks_step(self._h, int(n), None))
+        return None
+
+    def read(self):
+        T = self.mesh.n_tri
+        W = np.zeros((6, T))
+        gW = np.zeros((6, 2, T))
+        t = ctypes.c_double()
+        _check(load().gks_state_read(self._h, _d(W), _d(gW), ctypes.byref(t)))
+        return W, gW, t.value
+
+    def mass(self):
+        m = np.zeros(2)
+        _check(load().gks_state_mass(self._h, _d(m)))
+        return m
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gks_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -106,6 +106,25 @@ gks_status gks_state_read(const gks_state *st, double *W, double *gradW, double 
  * a deterministic device reduction; synchronising. */
 gks_status gks_state_mass(const gks_state *st, double mass[2]);
 
+/* Kernel classes for gks_profile_read. */
+typedef enum {
+    GKS_KERNEL_GHOST = 0,   /* mirror ghost cells refreshed from their source cells */
+    GKS_KERNEL_RECON = 1,   /* compact reconstruction at the Gauss points (Sec. 3.4) */
+    GKS_KERNEL_HHAT = 2,    /* edge-centre heights of the force model (Sec. 2.3) */
+    GKS_KERNEL_PLANE = 3,   /* plane gradient of the force model (Sec. 2.3) */
+    GKS_KERNEL_FLUX = 4,    /* gas-kinetic evolution at the Gauss points (Sec. 2.2) */
+    GKS_KERNEL_UPDATE = 5,  /* gather, sources, S2O4 stage update (Sec. 3.1-3.3) */
+    GKS_KERNEL_DT = 6,      /* CFL time step (Sec. 4) */
+    GKS_KERNEL_COUNT = 7
+} gks_kernel;
+
+/* Kernel timing for measurement tools: enable != 0 starts recording a HIP event pair on the
+ * state's stream around every kernel launch (clearing earlier records), 0 stops.  Synchronising. */
+gks_status gks_profile(gks_state *st, int32_t enable);
+/* Total time in ms and number of launches recorded for one kernel class since gks_profile
+ * enabled recording.  Synchronising. */
+gks_status gks_profile_read(gks_state *st, int32_t kernel, double *total_ms, int64_t *launches);
+
 const char *gks_last_error(void);
 
 #ifdef __cplusplus

@@ -58,7 +58,47 @@ struct gks_state {
     int nparts = 0;
     int half = 0;  // 1 between stage 0 and stage 1: the latest state is W^{n+1/2} (Wb)
     std::vector<void *> owned;
+    // optional kernel timing: an event pair around every launch, per kernel class
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> prof;
 };
+
+namespace {
+
+hipEvent_t next_event(gks_state *s)
+{
+    if (s->ev_used == s->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        s->ev_pool.push_back(e);
+    }
+    return s->ev_pool[s->ev_used++];
+}
+
+// runs launch() on the state's stream, bracketed by events when profiling is on
+template <typename F>
+void timed(gks_state *s, int kernel, F &&launch)
+{
+    if (!s->prof_on) {
+        launch();
+        return;
+    }
+    hipEvent_t a = next_event(s), b = next_event(s);
+    if (a && b) (void)hipEventRecord(a, s->stream);
+    launch();
+    if (a && b) {
+        (void)hipEventRecord(b, s->stream);
+        s->prof.push_back({kernel, a, b});
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -183,8 +223,38 @@ gks_status gks_state_init(const gks_mesh *mesh, const gks_params *prm, const dou
 void gks_state_destroy(gks_state *s)
 {
     if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     for (void *p : s->owned) (void)hipFree(p);
     delete s;
+}
+
+gks_status gks_profile(gks_state *s, int32_t enable)
+{
+    if (!s) return fail(GKS_EINVAL, "null state");
+    HIP_OK(hipStreamSynchronize(s->stream));
+    s->prof.clear();
+    s->ev_used = 0;
+    s->prof_on = enable != 0;
+    return GKS_OK;
+}
+
+gks_status gks_profile_read(gks_state *s, int32_t kernel, double *total_ms, int64_t *launches)
+{
+    if (!s || kernel < 0 || kernel >= GKS_KERNEL_COUNT) return fail(GKS_EINVAL, "bad profile query");
+    HIP_OK(hipStreamSynchronize(s->stream));
+    double tot = 0;
+    int64_t n = 0;
+    for (const auto &r : s->prof)
+        if (r.kernel == kernel) {
+            float ms = 0;
+            HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+            tot += ms;
+            n++;
+        }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = n;
+    return GKS_OK;
 }
 
 static gks_status run_stage(gks_state *s, int stage)
@@ -193,15 +263,28 @@ static gks_status run_stage(gks_state *s, int stage)
     hipStream_t st = s->stream;
     double *Win = stage == 0 ? s->Wa : s->Wb, *gWin = stage == 0 ? s->gWa : s->gWb;
     double *Wout = stage == 0 ? s->Wb : s->Wa, *gWout = stage == 0 ? s->gWb : s->gWa;
-    if (m.NG > 0) hipLaunchKernelGGL(gks::k_ghost_fill, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Win, gWin);
-    hipLaunchKernelGGL(gks::k_recon, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Win, gWin,
-                       s->rec, s->r0);
-    hipLaunchKernelGGL(gks::k_hhat, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rec, s->hmid);
-    hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
-    hipLaunchKernelGGL(gks::k_flux, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p, s->scal, s->rec,
-                       s->r0, s->gP1, s->eo);
-    hipLaunchKernelGGL(gks::k_update, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage, s->scal, s->eo,
-                       Win, Wout, gWout, s->Wc, s->Gc);
+    if (m.NG > 0)
+        timed(s, GKS_KERNEL_GHOST, [&] {
+            hipLaunchKernelGGL(gks::k_ghost_fill, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Win, gWin);
+        });
+    timed(s, GKS_KERNEL_RECON, [&] {
+        hipLaunchKernelGGL(gks::k_recon, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Win,
+                           gWin, s->rec, s->r0);
+    });
+    timed(s, GKS_KERNEL_HHAT, [&] {
+        hipLaunchKernelGGL(gks::k_hhat, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rec, s->hmid);
+    });
+    timed(s, GKS_KERNEL_PLANE, [&] {
+        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
+    });
+    timed(s, GKS_KERNEL_FLUX, [&] {
+        hipLaunchKernelGGL(gks::k_flux, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p, s->scal, s->rec,
+                           s->r0, s->gP1, s->eo);
+    });
+    timed(s, GKS_KERNEL_UPDATE, [&] {
+        hipLaunchKernelGGL(gks::k_update, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage, s->scal,
+                           s->eo, Win, Wout, gWout, s->Wc, s->Gc);
+    });
     HIP_OK(hipGetLastError());
     s->half = stage == 0;
     return GKS_OK;
@@ -210,10 +293,12 @@ static gks_status run_stage(gks_state *s, int stage)
 static gks_status compute_dt(gks_state *s)
 {
     const gks::MeshDev &m = s->mesh->d;
-    hipLaunchKernelGGL(gks::k_dt_partial, dim3(s->nparts), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->Wa,
-                       s->part);
-    hipLaunchKernelGGL(gks::k_dt_final, dim3(1), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->part, s->nparts,
-                       s->scal);
+    timed(s, GKS_KERNEL_DT, [&] {
+        hipLaunchKernelGGL(gks::k_dt_partial, dim3(s->nparts), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->Wa,
+                           s->part);
+        hipLaunchKernelGGL(gks::k_dt_final, dim3(1), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->part,
+                           s->nparts, s->scal);
+    });
     HIP_OK(hipGetLastError());
     return GKS_OK;
 }

@@ -24,7 +24,9 @@ GKS_FP64 = 0
 
 # every entry point declared in include/gks.h
 SYMBOLS = ("gks_mesh_create", "gks_mesh_destroy", "gks_mesh_info", "gks_state_init", "gks_state_destroy",
-           "gks_stage", "gks_step", "gks_state_read", "gks_state_mass", "gks_last_error")
+           "gks_stage", "gks_step", "gks_state_read", "gks_state_mass", "gks_profile", "gks_profile_read",
+           "gks_last_error")
+KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt")
 
 
 class GksError(RuntimeError):
@@ -60,6 +62,8 @@ def load():
     lib.gks_step.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_read.argtypes = [_vp, _dp, _dp, _dp]
     lib.gks_state_mass.argtypes = [_vp, _dp]
+    lib.gks_profile.argtypes = [_vp, ctypes.c_int32]
+    lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64)]
     for name in SYMBOLS:
         if name not in ("gks_mesh_destroy", "gks_state_destroy", "gks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -163,6 +167,18 @@ class State:
         m = np.zeros(2)
         _check(load().gks_state_mass(self._h, _d(m)))
         return m
+
+    def profile(self, enable=True):
+        _check(load().gks_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} for every kernel class."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            _check(load().gks_profile_read(self._h, k, ctypes.byref(ms), ctypes.byref(n)))
+            out[name] = (ms.value, n.value)
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

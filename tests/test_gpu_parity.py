@@ -154,3 +154,22 @@ def test_rejects_bad_input(gks):
     st = gks.State.from_scenario(m, sc)
     with pytest.raises(gks.GksError):
         st.stage(0, -1.0)
+
+
+def test_full_size_step_parity(gks):
+    """The benchmarked workload at full size (520,200 triangles): one S2O4 step with the device's
+    CFL step, every cell compared with the oracle's step."""
+    sc = w.lake_at_rest(510, seed=20230604, perturb=1e-3, disk=(0.3, 0.3, 0.1))
+    print(f"[parity] full size T={sc.n_tri}", flush=True)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc)
+    dt = st.step(1, want_dt=True)
+    W, gW, _ = st.read()
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    dref = o.dt(om, p, sc.W0)
+    assert abs(dt - dref) <= 4e-16 * dref
+    Wr, gWr = o.step(om, p, dref, sc.W0, sc.gradW0)
+    e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
+    print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
+    assert e.max() < TOL_FP64 and g.max() < TOL_FP64, (e, g)

@@ -10,6 +10,10 @@
 #include "gks_kernels.h"
 #include "mesh_setup.h"
 
+#ifndef GKS_RECON_STAGE_M
+#define GKS_RECON_STAGE_M false
+#endif
+
 namespace {
 
 thread_local std::string g_err;
@@ -268,8 +272,8 @@ static gks_status run_stage(gks_state *s, int stage)
             hipLaunchKernelGGL(gks::k_ghost_fill, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Win, gWin);
         });
     timed(s, GKS_KERNEL_RECON, [&] {
-        hipLaunchKernelGGL(gks::k_recon, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Win,
-                           gWin, s->rec, s->r0);
+        hipLaunchKernelGGL(gks::k_recon<GKS_RECON_STAGE_M>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st,
+                           m, s->p, Win, gWin, s->rec, s->r0);
     });
     timed(s, GKS_KERNEL_HHAT, [&] {
         hipLaunchKernelGGL(gks::k_hhat, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rec, s->hmid);

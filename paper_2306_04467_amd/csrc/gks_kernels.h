@@ -32,6 +32,18 @@ struct Phys {
     int linear;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Cells and edges
+// are numbered with spatial locality, so give each XCD one contiguous range of blocks: neighbour
+// gathers then hit the same L2 instead of being fetched from HBM by several XCDs.
+constexpr int N_XCD = 8;
+
+__device__ inline int64_t xcd_block()
+{
+    const int64_t b = blockIdx.x, nb = gridDim.x;
+    const int64_t q = nb / N_XCD, r = nb % N_XCD, x = b % N_XCD, j = b / N_XCD;
+    return x * q + (x < r ? x : r) + j;
+}
+
 // --------------------------------------------------------------------------------------------
 // ghost mirror cells: state of the source cell seen through an orthogonal map R
 
@@ -67,13 +79,25 @@ __global__ void k_ghost_fill(MeshDev m, double *__restrict__ W, double *__restri
 
 constexpr int RECON_CELLS = 32;
 
+// STAGE_M: the block first copies its 32 cells' least-squares operators into LDS (coalesced), so
+// the six variable-threads of a cell read them from LDS instead of six times through the caches.
+template <bool STAGE_M>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ W,
                                                const double *__restrict__ gW, double *__restrict__ rec,
                                                double *__restrict__ r0)
 {
     const int lane = threadIdx.x & 31, v = threadIdx.x >> 5;
-    const int64_t c = (int64_t)blockIdx.x * RECON_CELLS + lane;
+    const int64_t c = xcd_block() * RECON_CELLS + lane;
     const int64_t T = m.T, TG = m.T + m.NG;
+    __shared__ double Ms[STAGE_M ? 153 * RECON_CELLS : 1];
+    if (STAGE_M) {
+        const int64_t c0 = xcd_block() * RECON_CELLS;
+        for (int i = threadIdx.x; i < 153 * RECON_CELLS; i += blockDim.x) {
+            const int k = i / RECON_CELLS, cl = i % RECON_CELLS;
+            Ms[i] = (c0 + cl < T) ? m.M[(int64_t)k * T + c0 + cl] : 0.0;
+        }
+        __syncthreads();
+    }
     if (c >= T) return;
     const double Q0 = W[v * TG + c];
     const double hs = m.hs[c];
@@ -97,7 +121,10 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     for (int k = 0; k < 9; k++) {
         double s = 0;
 #pragma unroll
-        for (int r = 0; r < 17; r++) s = fma(m.M[(k * 17 + r) * T + c], rhs[r], s);
+        for (int r = 0; r < 17; r++) {
+            const double mk = STAGE_M ? Ms[(k * 17 + r) * RECON_CELLS + lane] : m.M[(k * 17 + r) * T + c];
+            s = fma(mk, rhs[r], s);
+        }
         a[k] = s;
     }
     // scaled vertices (centroid at the origin) and the cell means of the basis
@@ -234,7 +261,7 @@ __device__ inline double rec_at(const double *rec, int64_t T, int slot, int comp
 
 __global__ void k_hhat(MeshDev m, Phys p, const double *__restrict__ rec, double *__restrict__ hmid)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
     const int64_t T = m.T, E = m.E;
     const int32_t L = m.eL[e], R = m.eR[e], sl = m.eslot[e];
@@ -275,7 +302,7 @@ __global__ void k_hhat(MeshDev m, Phys p, const double *__restrict__ rec, double
 // gradient of the plane through the three edge-centre heights (Green-Gauss, exact for planes)
 __global__ void k_plane(MeshDev m, const double *__restrict__ hmid, double *__restrict__ gP1)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T, E = m.E;
     double s[4] = {0, 0, 0, 0};
@@ -461,7 +488,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const double *_
                                               const double *__restrict__ rec, const double *__restrict__ r0,
                                               const double *__restrict__ gP1, double *__restrict__ eo)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t idx = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t e = idx >> 2;
     const int g = idx & 1, lay = (idx >> 1) & 1;  // lay 0: lower layer (h1), 1: upper (h2)
     if (e >= m.E) return;
@@ -564,7 +591,7 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, int stage, co
                                                 double *__restrict__ Wout, double *__restrict__ gWout,
                                                 double *__restrict__ Wc, double *__restrict__ Gc)
 {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T, E = m.E, TG = m.T + m.NG;
     const double dt = dtp[0], G = p.G;

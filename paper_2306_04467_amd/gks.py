@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgks.so")
+# GKS_LIBRARY may name another build of the same ABI (used to compare kernel variants)
+LIB_PATH = os.environ.get("GKS_LIBRARY", os.path.join(_HERE, "libgks.so"))
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -16,7 +16,8 @@
  *  - All pointers to user arrays are HOST pointers; the library copies them (the caller keeps
  *    ownership).  Handles are owned by the library until the matching *_destroy call.
  *  - Cell arrays are structure-of-arrays: W[6][n_tri] and gradW[6][2][n_tri] (component-major,
- *    then x / y, then cell), components in the order above, cells in the order of `tri`.
+ *    then x / y, then cell), components in the order above, cells in the order of `tri` (for a
+ *    batch: scenario 0's cells, then scenario 1's, ...).
  *  - Work is enqueued on the HIP stream given to gks_state_init (NULL = the null stream) and is
  *    asynchronous, except the calls documented as synchronising.
  *  - Errors are returned as gks_status codes, never as exceptions; gks_last_error() gives a
@@ -51,7 +52,11 @@ typedef enum {
 } gks_bc;
 
 typedef enum {
-    GKS_FP64 = 0          /* every stage in double precision */
+    GKS_FP64 = 0,         /* every stage in double precision */
+    GKS_FP32_MIXED = 1    /* bulk arithmetic and storage in single precision; cell and Gauss-point
+                             thicknesses, the hydrostatic flux term, the interface thickness and
+                             every edge sum of the update (the lake-at-rest balance of Sec. 3.2)
+                             stay in double, and so do the mass sums */
 } gks_precision;
 
 typedef struct {
@@ -60,7 +65,7 @@ typedef struct {
     double cfl;      /* CFL number of dt = CFL * dX / U_max (Sec. 4) */
     double eps;      /* collision-time constant epsilon (Sec. 4: 0.05) */
     double eps_num;  /* pressure-jump constant of the collision time (Sec. 4: 5) */
-    double t_end;    /* the last step is clipped so that t never exceeds t_end */
+    double t_end;    /* the last step is clipped so that t never exceeds t_end (<= 0: no limit) */
     int32_t precision;  /* gks_precision */
     int32_t linear;     /* 1: linear P^3 reconstruction everywhere, 0: nonlinear (Sec. 3.4) */
 } gks_params;
@@ -76,35 +81,67 @@ typedef struct {
 gks_status gks_mesh_create(const double *node_xy, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
                            const double *node_B, int32_t bc, const double *periodic_L,
                            gks_mesh **out);
+/* Concatenate n independent single meshes into one batch mesh of n scenarios (an ensemble
+ * advanced together, each scenario with its own time step).  The inputs stay valid and owned by
+ * the caller. */
+gks_status gks_mesh_batch(const gks_mesh *const *meshes, int32_t n, gks_mesh **out);
 void gks_mesh_destroy(gks_mesh *mesh);
-/* sizes: n_tri, n_edges, n_ghost (mirror cells kept for wall stencils) */
-gks_status gks_mesh_info(const gks_mesh *mesh, int64_t *n_tri, int64_t *n_edges, int64_t *n_ghost);
+/* sizes: triangles, edges, ghost mirror cells (kept for wall stencils), scenarios; any may be NULL */
+gks_status gks_mesh_info(const gks_mesh *mesh, int64_t *n_tri, int64_t *n_edges, int64_t *n_ghost,
+                         int32_t *n_scenarios);
+/* cell range [first_cell, first_cell + n_cells) of scenario s in the batch's cell order */
+gks_status gks_mesh_scenario(const gks_mesh *mesh, int32_t s, int64_t *first_cell, int64_t *n_cells);
 
-/* Create a state on `mesh` (which must outlive it) from host arrays W0 [6][n_tri] and
- * gradW0 [6][2][n_tri] (cell averages and cell-averaged gradients at t = 0).  `stream` is a
- * hipStream_t (NULL = null stream).  Returns GKS_ENONFINITE if a thickness is <= 0 or a value is
- * not finite. */
+/* Create a state on `mesh` (which must outlive it).  params: one entry per scenario of the mesh
+ * (1 for a single mesh); G, cfl, eps, eps_num, precision and linear must agree across scenarios,
+ * chi and t_end may differ.  W0 [6][n_tri], gradW0 [6][2][n_tri]: cell averages and cell-averaged
+ * gradients at t = 0.  `stream` is a hipStream_t (NULL = null stream).  Returns GKS_ENONFINITE if
+ * a thickness is <= 0 or a value is not finite. */
 gks_status gks_state_init(const gks_mesh *mesh, const gks_params *params, const double *W0,
                           const double *gradW0, void *stream, gks_state **out);
 void gks_state_destroy(gks_state *st);
 
 /* One S2O4 stage (Sec. 3.3, Eq. SWE-fully-discrete).  stage = 0 turns W^n into W^{n+1/2} and
  * stores what stage 1 needs; stage = 1 turns W^{n+1/2} into W^{n+1}.  Stages must alternate
- * 0, 1, 0, ... (GKS_EINVAL otherwise).  dt: host pointer to the step size for stage 0, or NULL to
- * use the CFL step computed on the device; must be NULL for stage 1 (the step size is reused). */
+ * 0, 1, 0, ... (GKS_EINVAL otherwise).  dt: host pointer to the step size for stage 0 (single
+ * scenario only), or NULL to use the CFL step computed on the device; must be NULL for stage 1
+ * (the step size is reused). */
 gks_status gks_stage(gks_state *st, int32_t stage, const double *dt);
-/* n_steps full steps with the CFL time step computed on the device (no host synchronisation).
- * If dt_last is not NULL the call synchronises and returns the last step size.  GKS_EINVAL if
- * called between stage 0 and stage 1. */
+/* n_steps full steps, every scenario with its own CFL time step computed on the device (no host
+ * synchronisation).  If dt_last is not NULL the call synchronises and returns the last step size
+ * of scenario 0.  GKS_EINVAL if called between stage 0 and stage 1. */
 gks_status gks_step(gks_state *st, int32_t n_steps, double *dt_last);
+/* The same n_steps steps replayed from a HIP graph that holds one captured step (time step and
+ * both stages of every scenario); the graph is captured on the first call on a private stream
+ * and ordered after / before the work of the state's stream. */
+gks_status gks_batch_step(gks_state *st, int32_t n_steps);
 
 /* Copy the latest state to the host (synchronising): W^{n+1/2} between stage 0 and stage 1,
- * otherwise W^n.  W [6][n_tri], gradW [6][2][n_tri] (either may be NULL), t = its time (may be
- * NULL). */
+ * otherwise W^n.  W [6][n_tri], gradW [6][2][n_tri] (either may be NULL), t = time of scenario 0
+ * (may be NULL). */
 gks_status gks_state_read(const gks_state *st, double *W, double *gradW, double *t);
-/* Per-layer mass sum |Omega_j| h_j in FP64, mass[0] = upper layer (h2), mass[1] = lower (h1);
- * a deterministic device reduction; synchronising. */
-gks_status gks_state_mass(const gks_state *st, double mass[2]);
+/* Time of the latest state and last step size of scenario s (synchronising). */
+gks_status gks_state_time(const gks_state *st, int32_t s, double *t, double *dt);
+/* Per-layer mass sum |Omega_j| h_j in FP64 of scenario s (s = -1: all cells), mass[0] = upper
+ * layer (h2), mass[1] = lower (h1); a deterministic device reduction; synchronising. */
+gks_status gks_state_mass(const gks_state *st, int32_t s, double mass[2]);
+
+/* Intermediate arrays of the last stage, for tests and inspection tools. */
+typedef enum {
+    GKS_BUF_RECH = 0,  /* double [6 slots][2][n_tri]: h2 and h1 + B at the cells' Gauss points
+                          (slot = 2 * local edge + point, in the cell's counter-clockwise order) */
+    GKS_BUF_RECM = 1,  /* real [6 slots][16][n_tri]: the four momenta, then the x/y gradients of
+                          the six variables (h2, h2U2, h2V2, h1 + B, h1U1, h1V1) at the Gauss points */
+    GKS_BUF_R0 = 2,    /* real [2][n_tri]: omega_0 / d_0 of h1 + B and of h2 */
+    GKS_BUF_EOH = 3,   /* double [4][n_edges]: 1/2 G hb^2 (upper, lower), hb (upper, lower), Gauss
+                          points averaged, hb the interface thickness of the evolution solution */
+    GKS_BUF_EOM = 4,   /* real [22][n_edges]: flux F0 without 1/2 G hb^2 n (6), its time derivative
+                          (6), interface momenta (4), interface time derivatives (6), global frame */
+    GKS_BUF_COUNT = 5
+} gks_buffer;
+/* Copy one intermediate array to host memory `dst` of `bytes` bytes (synchronising); "real" is
+ * double for GKS_FP64 states and float for GKS_FP32_MIXED.  GKS_EINVAL if bytes is too small. */
+gks_status gks_state_buffer(const gks_state *st, int32_t which, void *dst, int64_t bytes);
 
 /* Kernel classes for gks_profile_read. */
 typedef enum {
@@ -119,7 +156,8 @@ typedef enum {
 } gks_kernel;
 
 /* Kernel timing for measurement tools: enable != 0 starts recording a HIP event pair on the
- * state's stream around every kernel launch (clearing earlier records), 0 stops.  Synchronising. */
+ * state's stream around every kernel launch of gks_stage / gks_step (clearing earlier records),
+ * 0 stops.  Synchronising. */
 gks_status gks_profile(gks_state *st, int32_t enable);
 /* Total time in ms and number of launches recorded for one kernel class since gks_profile
  * enabled recording.  Synchronising. */

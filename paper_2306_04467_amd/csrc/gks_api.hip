@@ -1,6 +1,8 @@
-// C ABI of the GKS library: mesh / state lifetime, stage orchestration, host <-> device copies.
+// C ABI of the GKS library: mesh / state lifetime, stage orchestration, batched stepping with HIP
+// graphs, host <-> device copies.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -9,10 +11,6 @@
 #include "../../include/gks.h"
 #include "gks_kernels.h"
 #include "mesh_setup.h"
-
-#ifndef GKS_RECON_STAGE_M
-#define GKS_RECON_STAGE_M false
-#endif
 
 namespace {
 
@@ -24,20 +22,31 @@ gks_status fail(gks_status s, const std::string &msg)
     return s;
 }
 
-#define HIP_OK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
+#define HIP_OK(expr)                                                                                      \
+    do {                                                                                                  \
+        hipError_t e_ = (expr);                                                                           \
         if (e_ != hipSuccess) return fail(GKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
 template <typename T>
-hipError_t upload(const std::vector<T> &h, T **d, std::vector<void *> &owned)
+hipError_t upload(const std::vector<T> &h, const T **d, std::vector<void *> &owned)
 {
     size_t n = std::max<size_t>(h.size(), 1);
-    hipError_t e = hipMalloc((void **)d, n * sizeof(T));
+    T *p = nullptr;
+    hipError_t e = hipMalloc((void **)&p, n * sizeof(T));
     if (e != hipSuccess) return e;
-    owned.push_back(*d);
-    if (!h.empty()) e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    owned.push_back(p);
+    *d = p;
+    if (!h.empty()) e = hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t upload_f32(const std::vector<double> &h, const void **d, std::vector<void *> &owned)
+{
+    std::vector<float> f(h.begin(), h.end());
+    const float *p = nullptr;
+    hipError_t e = upload(f, &p, owned);
+    *d = p;
     return e;
 }
 
@@ -46,22 +55,34 @@ inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 }  // namespace
 
 struct gks_mesh {
-    gks::MeshDev d{};
+    gks::HostMesh host;             // kept for concatenation into batches and for state conversion
+    gks::MeshDev d64{}, d32{};      // device tables; bulk tables as double / as float
+    bool has32 = false;
     std::vector<void *> owned;
-    std::vector<double> Bbar, gB, area;  // host copies for state conversion
     int device = 0;
 };
 
 struct gks_state {
     const gks_mesh *mesh = nullptr;
+    int prec = GKS_FP64;
+    gks::MeshDev md{};
     gks::Phys p{};
     hipStream_t stream = nullptr;
-    double *Wa = nullptr, *gWa = nullptr, *Wb = nullptr, *gWb = nullptr;
-    double *Wc = nullptr, *Gc = nullptr, *rec = nullptr, *r0 = nullptr, *hmid = nullptr, *gP1 = nullptr;
-    double *eo = nullptr, *scal = nullptr, *part = nullptr;
+    double *Wh[2] = {nullptr, nullptr};
+    void *Wm[2] = {nullptr, nullptr}, *gW[2] = {nullptr, nullptr};
+    double *Wc = nullptr, *rech = nullptr, *hmid = nullptr, *gP1 = nullptr, *eoh = nullptr;
+    void *Gc = nullptr, *recm = nullptr, *r0 = nullptr, *eom = nullptr;
+    double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
+    uint8_t *smooth = nullptr;
     int nparts = 0;
-    int half = 0;  // 1 between stage 0 and stage 1: the latest state is W^{n+1/2} (Wb)
+    int half = 0;  // 1 between stage 0 and stage 1: the latest state is W^{n+1/2}
     std::vector<void *> owned;
+    // graph of one full step, replayed by gks_batch_step
+    hipStream_t gstream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    bool capturing = false;
     // optional kernel timing: an event pair around every launch, per kernel class
     bool prof_on = false;
     std::vector<hipEvent_t> ev_pool;
@@ -85,21 +106,173 @@ hipEvent_t next_event(gks_state *s)
     return s->ev_pool[s->ev_used++];
 }
 
-// runs launch() on the state's stream, bracketed by events when profiling is on
+// runs launch() on stream st, bracketed by events when profiling is on (never inside a capture)
 template <typename F>
-void timed(gks_state *s, int kernel, F &&launch)
+void timed(gks_state *s, hipStream_t st, int kernel, F &&launch)
 {
-    if (!s->prof_on) {
+    if (!s->prof_on || s->capturing) {
         launch();
         return;
     }
     hipEvent_t a = next_event(s), b = next_event(s);
-    if (a && b) (void)hipEventRecord(a, s->stream);
+    if (a && b) (void)hipEventRecord(a, st);
     launch();
     if (a && b) {
-        (void)hipEventRecord(b, s->stream);
+        (void)hipEventRecord(b, st);
         s->prof.push_back({kernel, a, b});
     }
+}
+
+template <typename R>
+void launch_stage(gks_state *s, int stage, hipStream_t st)
+{
+    const gks::MeshDev &m = s->md;
+    const int in = stage == 0 ? 0 : 1, out = 1 - in;
+    double *Whin = s->Wh[in];
+    R *Wmin = (R *)s->Wm[in], *gWin = (R *)s->gW[in];
+    double *Whout = s->Wh[out];
+    R *Wmout = (R *)s->Wm[out], *gWout = (R *)s->gW[out];
+    if (m.NG > 0)
+        timed(s, st, GKS_KERNEL_GHOST, [&] {
+            hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Whin, Wmin, gWin);
+        });
+    timed(s, st, GKS_KERNEL_RECON, [&] {
+        hipLaunchKernelGGL(gks::k_recon<R>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Whin,
+                           Wmin, gWin, s->smooth, s->rech, (R *)s->recm, (R *)s->r0);
+    });
+    timed(s, st, GKS_KERNEL_HHAT, [&] {
+        hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rech,
+                           (const R *)s->recm, s->hmid);
+    });
+    timed(s, st, GKS_KERNEL_PLANE, [&] {
+        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
+    });
+    timed(s, st, GKS_KERNEL_FLUX, [&] {
+        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p, s->rech,
+                           (const R *)s->recm, (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+    });
+    timed(s, st, GKS_KERNEL_UPDATE, [&] {
+        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage, s->eoh,
+                           (const R *)s->eom, Whin, Wmin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+    });
+}
+
+template <typename R>
+void launch_dt(gks_state *s, hipStream_t st)
+{
+    const gks::MeshDev &m = s->md;
+    timed(s, st, GKS_KERNEL_DT, [&] {
+        if (m.S == 1) {
+            hipLaunchKernelGGL(gks::k_dt_partial<R>, dim3(s->nparts), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->Wh[0],
+                               (const R *)s->Wm[0], s->part);
+            hipLaunchKernelGGL(gks::k_dt_final, dim3(1), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->part, s->nparts);
+        } else {
+            hipLaunchKernelGGL(gks::k_dt_batch<R>, dim3(m.S), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->Wh[0],
+                               (const R *)s->Wm[0]);
+        }
+    });
+}
+
+void stage_any(gks_state *s, int stage, hipStream_t st)
+{
+    if (s->prec == GKS_FP64)
+        launch_stage<double>(s, stage, st);
+    else
+        launch_stage<float>(s, stage, st);
+}
+
+void dt_any(gks_state *s, hipStream_t st)
+{
+    if (s->prec == GKS_FP64)
+        launch_dt<double>(s, st);
+    else
+        launch_dt<float>(s, st);
+}
+
+gks_status upload_mesh(gks_mesh *m)
+{
+    const gks::HostMesh &h = m->host;
+    gks::MeshDev &d = m->d64;
+    d.T = h.nt;
+    d.E = h.ne;
+    d.NG = h.ng;
+    d.S = h.S;
+    std::vector<void *> &o = m->owned;
+    hipError_t e = hipSuccess;
+    auto up = [&](auto &vec, auto **field) {
+        if (e == hipSuccess) e = upload(vec, field, o);
+    };
+    up(h.area, &d.area);
+    up(h.Bbar, &d.Bbar);
+    up(h.gB, &d.gB);
+    up(h.fl, &d.fl);
+    up(h.gg, &d.gg);
+    up(h.eBgp, &d.eBgp);
+    up(h.gR, &d.gR);
+    up(h.sdxmin, &d.sdxmin);
+    up(h.cedge, &d.cedge);
+    up(h.sten, &d.sten);
+    up(h.eL, &d.eL);
+    up(h.eR, &d.eR);
+    up(h.eslot, &d.eslot);
+    up(h.gsrc, &d.gsrc);
+    up(h.scell, &d.scell);
+    const double *M = nullptr, *hs = nullptr, *vtx = nullptr, *nbc = nullptr, *en = nullptr, *egB = nullptr;
+    up(h.M, &M);
+    up(h.hs, &hs);
+    up(h.vtx, &vtx);
+    up(h.nbc, &nbc);
+    up(h.en, &en);
+    up(h.egB, &egB);
+    d.M = M;
+    d.hs = hs;
+    d.vtx = vtx;
+    d.nbc = nbc;
+    d.en = en;
+    d.egB = egB;
+    if (h.S > 1) {
+        up(h.cscen, &d.cscen);
+        up(h.escen, &d.escen);
+    } else {
+        d.cscen = d.escen = nullptr;
+    }
+    if (e != hipSuccess) return fail(GKS_ENOMEM, std::string("mesh upload: ") + hipGetErrorString(e));
+    m->d32 = d;
+    return GKS_OK;
+}
+
+gks_status ensure_f32(gks_mesh *m)
+{
+    if (m->has32) return GKS_OK;
+    const gks::HostMesh &h = m->host;
+    gks::MeshDev &d = m->d32;
+    hipError_t e = hipSuccess;
+    std::vector<void *> &o = m->owned;
+    if (e == hipSuccess) e = upload_f32(h.M, &d.M, o);
+    if (e == hipSuccess) e = upload_f32(h.hs, &d.hs, o);
+    if (e == hipSuccess) e = upload_f32(h.vtx, &d.vtx, o);
+    if (e == hipSuccess) e = upload_f32(h.nbc, &d.nbc, o);
+    if (e == hipSuccess) e = upload_f32(h.en, &d.en, o);
+    if (e == hipSuccess) e = upload_f32(h.egB, &d.egB, o);
+    if (e != hipSuccess) return fail(GKS_ENOMEM, std::string("mesh upload: ") + hipGetErrorString(e));
+    m->has32 = true;
+    return GKS_OK;
+}
+
+template <typename R>
+void to_real(const std::vector<double> &src, std::vector<unsigned char> &dst)
+{
+    dst.resize(src.size() * sizeof(R));
+    R *p = reinterpret_cast<R *>(dst.data());
+    for (size_t i = 0; i < src.size(); i++) p[i] = (R)src[i];
+}
+
+template <typename R>
+void from_real(const std::vector<unsigned char> &src, std::vector<double> &dst)
+{
+    const R *p = reinterpret_cast<const R *>(src.data());
+    dst.resize(src.size() / sizeof(R));
+    for (size_t i = 0; i < dst.size(); i++) dst[i] = (double)p[i];
 }
 
 }  // namespace
@@ -115,34 +288,49 @@ gks_status gks_mesh_create(const double *node_xy, int64_t n_nodes, const int32_t
     if (bc != GKS_BC_WALL && bc != GKS_BC_PERIODIC) return fail(GKS_EINVAL, "unknown boundary kind");
     if (n_tri > (int64_t)1 << 29) return fail(GKS_EINVAL, "mesh too large for 32-bit cell indices");
     *out = nullptr;
-    gks::HostMesh hm;
-    std::string err;
-    if (gks::build_host_mesh(node_xy, n_nodes, tri, n_tri, node_B, bc, periodic_L, hm, err) != 0)
-        return fail(GKS_EMESH, err);
     gks_mesh *m = new gks_mesh();
-    HIP_OK(hipGetDevice(&m->device));
-    gks::MeshDev &d = m->d;
-    d.T = hm.nt;
-    d.E = hm.ne;
-    d.NG = hm.ng;
-    d.dxmin = hm.dxmin;
-    std::vector<void *> &o = m->owned;
-    hipError_t e = hipSuccess;
-#define UP(field, vec)                                                \
-    if (e == hipSuccess) {                                            \
-        e = upload(hm.vec, const_cast<std::remove_const_t<std::remove_pointer_t<decltype(d.field)>> **>(&d.field), o); \
+    std::string err;
+    if (gks::build_host_mesh(node_xy, n_nodes, tri, n_tri, node_B, bc, periodic_L, m->host, err) != 0) {
+        delete m;
+        return fail(GKS_EMESH, err);
     }
-    UP(area, area) UP(hs, hs) UP(vtx, vtx) UP(nbc, nbc) UP(fl, fl) UP(gg, gg) UP(Bbar, Bbar) UP(gB, gB)
-    UP(M, M) UP(cedge, cedge) UP(sten, sten) UP(eL, eL) UP(eR, eR) UP(eslot, eslot) UP(en, en)
-    UP(eBgp, eBgp) UP(egB, egB) UP(gsrc, gsrc) UP(gR, gR)
-#undef UP
-    if (e != hipSuccess) {
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return fail(GKS_EDEVICE, "no HIP device");
+    }
+    gks_status r = upload_mesh(m);
+    if (r != GKS_OK) {
         gks_mesh_destroy(m);
-        return fail(GKS_ENOMEM, std::string("mesh upload: ") + hipGetErrorString(e));
+        return r;
     }
-    m->Bbar = hm.Bbar;
-    m->gB = hm.gB;
-    m->area = hm.area;
+    *out = m;
+    return GKS_OK;
+}
+
+gks_status gks_mesh_batch(const gks_mesh *const *meshes, int32_t n, gks_mesh **out)
+{
+    if (!meshes || n <= 0 || !out) return fail(GKS_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    std::vector<const gks::HostMesh *> parts;
+    int64_t T = 0;
+    for (int32_t i = 0; i < n; i++) {
+        if (!meshes[i]) return fail(GKS_EINVAL, "null mesh in batch");
+        if (meshes[i]->host.S != 1) return fail(GKS_EINVAL, "batches cannot be nested");
+        parts.push_back(&meshes[i]->host);
+        T += meshes[i]->host.nt + meshes[i]->host.ng;
+    }
+    if (T > (int64_t)1 << 30) return fail(GKS_EINVAL, "batch too large for 32-bit cell indices");
+    gks_mesh *m = new gks_mesh();
+    m->host = gks::concat_host_meshes(parts);
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return fail(GKS_EDEVICE, "no HIP device");
+    }
+    gks_status r = upload_mesh(m);
+    if (r != GKS_OK) {
+        gks_mesh_destroy(m);
+        return r;
+    }
     *out = m;
     return GKS_OK;
 }
@@ -154,72 +342,121 @@ void gks_mesh_destroy(gks_mesh *m)
     delete m;
 }
 
-gks_status gks_mesh_info(const gks_mesh *m, int64_t *n_tri, int64_t *n_edges, int64_t *n_ghost)
+gks_status gks_mesh_info(const gks_mesh *m, int64_t *n_tri, int64_t *n_edges, int64_t *n_ghost, int32_t *n_scen)
 {
     if (!m) return fail(GKS_EINVAL, "null mesh");
-    if (n_tri) *n_tri = m->d.T;
-    if (n_edges) *n_edges = m->d.E;
-    if (n_ghost) *n_ghost = m->d.NG;
+    if (n_tri) *n_tri = m->host.nt;
+    if (n_edges) *n_edges = m->host.ne;
+    if (n_ghost) *n_ghost = m->host.ng;
+    if (n_scen) *n_scen = m->host.S;
     return GKS_OK;
 }
 
-gks_status gks_state_init(const gks_mesh *mesh, const gks_params *prm, const double *W0, const double *gradW0,
+gks_status gks_mesh_scenario(const gks_mesh *m, int32_t s, int64_t *first_cell, int64_t *n_cells)
+{
+    if (!m || s < 0 || s >= m->host.S) return fail(GKS_EINVAL, "bad scenario index");
+    if (first_cell) *first_cell = m->host.scell[s];
+    if (n_cells) *n_cells = m->host.scell[s + 1] - m->host.scell[s];
+    return GKS_OK;
+}
+
+gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const double *W0, const double *gradW0,
                           void *stream, gks_state **out)
 {
-    if (!mesh || !prm || !W0 || !gradW0 || !out) return fail(GKS_EINVAL, "null argument");
-    if (prm->precision != GKS_FP64) return fail(GKS_EUNSUPPORTED, "only GKS_FP64 in this build");
-    if (!(prm->G > 0) || !(prm->cfl > 0) || !(prm->chi > 0) || !(prm->eps > 0) || !(prm->eps_num >= 0))
-        return fail(GKS_EINVAL, "bad physical parameters");
+    if (!mesh_c || !prm || !W0 || !gradW0 || !out) return fail(GKS_EINVAL, "null argument");
+    gks_mesh *mesh = const_cast<gks_mesh *>(mesh_c);
+    const gks::HostMesh &h = mesh->host;
+    const int32_t S = h.S;
+    for (int32_t s = 0; s < S; s++) {
+        const gks_params &q = prm[s];
+        if (q.precision != GKS_FP64 && q.precision != GKS_FP32_MIXED)
+            return fail(GKS_EUNSUPPORTED, "unknown precision");
+        if (!(q.G > 0) || !(q.cfl > 0) || !(q.chi > 0) || !(q.eps > 0) || !(q.eps_num >= 0))
+            return fail(GKS_EINVAL, "bad physical parameters");
+        if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
+            q.precision != prm[0].precision || q.linear != prm[0].linear)
+            return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision and linear");
+    }
     *out = nullptr;
-    const int64_t T = mesh->d.T, TG = T + mesh->d.NG, E = mesh->d.E;
+    const int prec = prm[0].precision;
+    if (prec == GKS_FP32_MIXED) {
+        gks_status r = ensure_f32(mesh);
+        if (r != GKS_OK) return r;
+    }
+    const int64_t T = h.nt, TG = T + h.ng, E = h.ne;
     // host conversion: the device state carries eta1 = h1 + B and grad(eta1)
-    std::vector<double> w(6 * TG, 0.0), g(12 * TG, 0.0);
+    std::vector<double> wh(2 * TG, 0.0), wm(4 * TG, 0.0), g(12 * TG, 0.0);
     for (int v = 0; v < 6; v++)
         for (int64_t c = 0; c < T; c++) {
             double x = W0[v * T + c];
             if (!std::isfinite(x) || ((v == 0 || v == 3) && !(x > 0)))
                 return fail(GKS_ENONFINITE, "bad initial value at component " + std::to_string(v) + ", cell " +
                                                 std::to_string(c));
-            w[v * TG + c] = v == 3 ? x + mesh->Bbar[c] : x;
+            if (v == 0) wh[c] = x;
+            else if (v == 3) wh[TG + c] = x + h.Bbar[c];
+            else wm[(v < 3 ? v - 1 : v - 2) * TG + c] = x;
             for (int d = 0; d < 2; d++) {
                 double y = gradW0[(2 * v + d) * T + c];
                 if (!std::isfinite(y)) return fail(GKS_ENONFINITE, "non-finite initial gradient");
-                g[(2 * v + d) * TG + c] = v == 3 ? y + mesh->gB[d * T + c] : y;
+                g[(2 * v + d) * TG + c] = v == 3 ? y + h.gB[d * T + c] : y;
             }
         }
     gks_state *s = new gks_state();
     s->mesh = mesh;
-    s->p.G = prm->G;
-    s->p.chi = prm->chi;
-    s->p.eps = prm->eps;
-    s->p.eps_num = prm->eps_num;
-    s->p.cfl = prm->cfl;
-    s->p.t_end = prm->t_end > 0 ? prm->t_end : 1e300;
-    s->p.linear = prm->linear;
+    s->prec = prec;
+    s->md = prec == GKS_FP64 ? mesh->d64 : mesh->d32;
     s->stream = (hipStream_t)stream;
     s->nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (T + gks::DT_BLOCK - 1) / gks::DT_BLOCK));
+    const size_t rs = prec == GKS_FP64 ? sizeof(double) : sizeof(float);
+    const size_t uT = (size_t)T, uTG = (size_t)TG, uE = (size_t)E, uS = (size_t)S;
     struct Buf {
-        double **p;
-        size_t n;
-    } bufs[] = {{&s->Wa, 6 * (size_t)TG}, {&s->gWa, 12 * (size_t)TG}, {&s->Wb, 6 * (size_t)TG},
-                {&s->gWb, 12 * (size_t)TG}, {&s->Wc, 6 * (size_t)T}, {&s->Gc, 12 * (size_t)T},
-                {&s->rec, 108 * (size_t)T}, {&s->r0, 2 * (size_t)T}, {&s->hmid, 2 * (size_t)E},
-                {&s->gP1, 4 * (size_t)T}, {&s->eo, 24 * (size_t)E}, {&s->scal, 2},
-                {&s->part, 2 * (size_t)std::max(s->nparts, 1024)}};
+        void **p;
+        size_t bytes;
+    } bufs[] = {{(void **)&s->Wh[0], 2 * uTG * 8}, {(void **)&s->Wh[1], 2 * uTG * 8}, {&s->Wm[0], 4 * uTG * rs},
+                {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
+                {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {(void **)&s->rech, 12 * uT * 8},
+                {&s->recm, 96 * uT * rs}, {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
+                {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
+                {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max(s->nparts, 1024) * 8},
+                {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
     for (auto &b : bufs) {
-        hipError_t e = hipMalloc((void **)b.p, b.n * sizeof(double));
+        hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
         if (e != hipSuccess) {
             gks_state_destroy(s);
             return fail(GKS_ENOMEM, std::string("state allocation: ") + hipGetErrorString(e));
         }
         s->owned.push_back(*b.p);
     }
-    double scal0[2] = {0.0, 0.0};
-    HIP_OK(hipMemcpy(s->Wa, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->gWa, g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->scal, scal0, sizeof(scal0), hipMemcpyHostToDevice));
-    HIP_OK(hipMemset(s->Wb, 0, 6 * (size_t)TG * sizeof(double)));
-    HIP_OK(hipMemset(s->gWb, 0, 12 * (size_t)TG * sizeof(double)));
+    std::vector<double> chi(S), tend(S), scal(2 * S, 0.0);
+    for (int32_t i = 0; i < S; i++) {
+        chi[i] = prm[i].chi;
+        tend[i] = prm[i].t_end > 0 ? prm[i].t_end : 1e300;
+    }
+    s->p.G = prm[0].G;
+    s->p.eps = prm[0].eps;
+    s->p.eps_num = prm[0].eps_num;
+    s->p.cfl = prm[0].cfl;
+    s->p.linear = prm[0].linear;
+    s->p.chi = s->chi;
+    s->p.t_end = s->tend;
+    s->p.scal = s->scal;
+    std::vector<unsigned char> bm, bg;
+    if (prec == GKS_FP64) {
+        to_real<double>(wm, bm);
+        to_real<double>(g, bg);
+    } else {
+        to_real<float>(wm, bm);
+        to_real<float>(g, bg);
+    }
+    HIP_OK(hipMemcpy(s->Wh[0], wh.data(), wh.size() * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->Wm[0], bm.data(), bm.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->gW[0], bg.data(), bg.size(), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->chi, chi.data(), S * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->tend, tend.data(), S * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(s->scal, scal.data(), 2 * S * 8, hipMemcpyHostToDevice));
+    HIP_OK(hipMemset(s->Wh[1], 0, 2 * TG * 8));
+    HIP_OK(hipMemset(s->Wm[1], 0, 4 * TG * rs));
+    HIP_OK(hipMemset(s->gW[1], 0, 12 * TG * rs));
     *out = s;
     return GKS_OK;
 }
@@ -228,6 +465,12 @@ void gks_state_destroy(gks_state *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
+    if (s->gstream) (void)hipStreamSynchronize(s->gstream);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (hipEvent_t e : s->gev)
+        if (e) (void)hipEventDestroy(e);
+    if (s->gstream) (void)hipStreamDestroy(s->gstream);
     for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     for (void *p : s->owned) (void)hipFree(p);
     delete s;
@@ -261,52 +504,6 @@ gks_status gks_profile_read(gks_state *s, int32_t kernel, double *total_ms, int6
     return GKS_OK;
 }
 
-static gks_status run_stage(gks_state *s, int stage)
-{
-    const gks::MeshDev &m = s->mesh->d;
-    hipStream_t st = s->stream;
-    double *Win = stage == 0 ? s->Wa : s->Wb, *gWin = stage == 0 ? s->gWa : s->gWb;
-    double *Wout = stage == 0 ? s->Wb : s->Wa, *gWout = stage == 0 ? s->gWb : s->gWa;
-    if (m.NG > 0)
-        timed(s, GKS_KERNEL_GHOST, [&] {
-            hipLaunchKernelGGL(gks::k_ghost_fill, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Win, gWin);
-        });
-    timed(s, GKS_KERNEL_RECON, [&] {
-        hipLaunchKernelGGL(gks::k_recon<GKS_RECON_STAGE_M>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st,
-                           m, s->p, Win, gWin, s->rec, s->r0);
-    });
-    timed(s, GKS_KERNEL_HHAT, [&] {
-        hipLaunchKernelGGL(gks::k_hhat, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rec, s->hmid);
-    });
-    timed(s, GKS_KERNEL_PLANE, [&] {
-        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
-    });
-    timed(s, GKS_KERNEL_FLUX, [&] {
-        hipLaunchKernelGGL(gks::k_flux, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p, s->scal, s->rec,
-                           s->r0, s->gP1, s->eo);
-    });
-    timed(s, GKS_KERNEL_UPDATE, [&] {
-        hipLaunchKernelGGL(gks::k_update, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage, s->scal,
-                           s->eo, Win, Wout, gWout, s->Wc, s->Gc);
-    });
-    HIP_OK(hipGetLastError());
-    s->half = stage == 0;
-    return GKS_OK;
-}
-
-static gks_status compute_dt(gks_state *s)
-{
-    const gks::MeshDev &m = s->mesh->d;
-    timed(s, GKS_KERNEL_DT, [&] {
-        hipLaunchKernelGGL(gks::k_dt_partial, dim3(s->nparts), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->Wa,
-                           s->part);
-        hipLaunchKernelGGL(gks::k_dt_final, dim3(1), dim3(gks::DT_BLOCK), 0, s->stream, m, s->p, s->part,
-                           s->nparts, s->scal);
-    });
-    HIP_OK(hipGetLastError());
-    return GKS_OK;
-}
-
 gks_status gks_stage(gks_state *s, int32_t stage, const double *dt)
 {
     if (!s || (stage != 0 && stage != 1)) return fail(GKS_EINVAL, "bad stage arguments");
@@ -314,17 +511,19 @@ gks_status gks_stage(gks_state *s, int32_t stage, const double *dt)
     if (stage == 0 && s->half) return fail(GKS_EINVAL, "stage 0 must follow stage 1");
     if (stage == 0) {
         if (dt) {
+            if (s->md.S != 1) return fail(GKS_EINVAL, "an explicit dt needs a single-scenario state");
             if (!(*dt > 0) || !std::isfinite(*dt)) return fail(GKS_EINVAL, "dt must be positive");
-            hipLaunchKernelGGL(gks::k_set_dt, dim3(1), dim3(1), 0, s->stream, s->scal, *dt);
-            HIP_OK(hipGetLastError());
+            hipLaunchKernelGGL(gks::k_set_dt, dim3(1), dim3(1), 0, s->stream, s->p, *dt);
         } else {
-            gks_status r = compute_dt(s);
-            if (r != GKS_OK) return r;
+            dt_any(s, s->stream);
         }
     } else if (dt) {
         return fail(GKS_EINVAL, "stage 1 reuses the step size of stage 0");
     }
-    return run_stage(s, stage);
+    stage_any(s, stage, s->stream);
+    HIP_OK(hipGetLastError());
+    s->half = stage == 0;
+    return GKS_OK;
 }
 
 gks_status gks_step(gks_state *s, int32_t n_steps, double *dt_last)
@@ -332,10 +531,10 @@ gks_status gks_step(gks_state *s, int32_t n_steps, double *dt_last)
     if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
     if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
     for (int i = 0; i < n_steps; i++) {
-        gks_status r = compute_dt(s);
-        if (r == GKS_OK) r = run_stage(s, 0);
-        if (r == GKS_OK) r = run_stage(s, 1);
-        if (r != GKS_OK) return r;
+        dt_any(s, s->stream);
+        stage_any(s, 0, s->stream);
+        stage_any(s, 1, s->stream);
+        HIP_OK(hipGetLastError());
     }
     if (dt_last) {
         double sc[2];
@@ -346,42 +545,90 @@ gks_status gks_step(gks_state *s, int32_t n_steps, double *dt_last)
     return GKS_OK;
 }
 
-gks_status gks_state_read(const gks_state *s, double *W, double *gradW, double *t)
+gks_status gks_batch_step(gks_state *s, int32_t n_steps)
 {
-    if (!s) return fail(GKS_EINVAL, "null state");
-    const gks_mesh *mesh = s->mesh;
-    const int64_t T = mesh->d.T, TG = T + mesh->d.NG;
-    const double *Wsrc = s->half ? s->Wb : s->Wa, *gWsrc = s->half ? s->gWb : s->gWa;
-    HIP_OK(hipStreamSynchronize(s->stream));
-    if (W) {
-        std::vector<double> w(6 * TG);
-        HIP_OK(hipMemcpy(w.data(), Wsrc, w.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (int v = 0; v < 6; v++)
-            for (int64_t c = 0; c < T; c++) W[v * T + c] = v == 3 ? w[v * TG + c] - mesh->Bbar[c] : w[v * TG + c];
+    if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
+    if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
+    if (!s->gexec) {
+        // capture one full step (every scenario's dt, both stages) on a private stream
+        HIP_OK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
+        HIP_OK(hipEventCreateWithFlags(&s->gev[1], hipEventDisableTiming));
+        s->capturing = true;
+        HIP_OK(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
+        dt_any(s, s->gstream);
+        stage_any(s, 0, s->gstream);
+        stage_any(s, 1, s->gstream);
+        hipError_t e = hipStreamEndCapture(s->gstream, &s->graph);
+        s->capturing = false;
+        HIP_OK(e);
+        HIP_OK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
     }
-    if (gradW) {
-        std::vector<double> g(12 * TG);
-        HIP_OK(hipMemcpy(g.data(), gWsrc, g.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (int v = 0; v < 6; v++)
-            for (int d = 0; d < 2; d++)
-                for (int64_t c = 0; c < T; c++)
-                    gradW[(2 * v + d) * T + c] =
-                        v == 3 ? g[(2 * v + d) * TG + c] - mesh->gB[d * T + c] : g[(2 * v + d) * TG + c];
-    }
-    if (t) {
-        double sc[2];
-        HIP_OK(hipMemcpy(sc, s->scal, sizeof(sc), hipMemcpyDeviceToHost));
-        *t = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
-    }
+    // order the graph replays after the work already queued on the state's stream, and later
+    // work on that stream after them
+    HIP_OK(hipEventRecord(s->gev[0], s->stream));
+    HIP_OK(hipStreamWaitEvent(s->gstream, s->gev[0], 0));
+    for (int i = 0; i < n_steps; i++) HIP_OK(hipGraphLaunch(s->gexec, s->gstream));
+    HIP_OK(hipEventRecord(s->gev[1], s->gstream));
+    HIP_OK(hipStreamWaitEvent(s->stream, s->gev[1], 0));
     return GKS_OK;
 }
 
-gks_status gks_state_mass(const gks_state *s, double mass[2])
+gks_status gks_state_read(const gks_state *s, double *W, double *gradW, double *t)
 {
-    if (!s || !mass) return fail(GKS_EINVAL, "null argument");
-    const gks::MeshDev &m = s->mesh->d;
+    if (!s) return fail(GKS_EINVAL, "null state");
+    const gks::HostMesh &h = s->mesh->host;
+    const int64_t T = h.nt, TG = T + h.ng;
+    const int b = s->half ? 1 : 0;
+    const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
+    HIP_OK(hipStreamSynchronize(s->stream));
+    if (W) {
+        std::vector<double> wh(2 * TG), wm;
+        std::vector<unsigned char> raw(4 * TG * rs);
+        HIP_OK(hipMemcpy(wh.data(), s->Wh[b], wh.size() * 8, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(raw.data(), s->Wm[b], raw.size(), hipMemcpyDeviceToHost));
+        if (s->prec == GKS_FP64) from_real<double>(raw, wm); else from_real<float>(raw, wm);
+        for (int64_t c = 0; c < T; c++) {
+            W[c] = wh[c];
+            W[3 * T + c] = wh[TG + c] - h.Bbar[c];
+            W[T + c] = wm[c];
+            W[2 * T + c] = wm[TG + c];
+            W[4 * T + c] = wm[2 * TG + c];
+            W[5 * T + c] = wm[3 * TG + c];
+        }
+    }
+    if (gradW) {
+        std::vector<double> g;
+        std::vector<unsigned char> raw(12 * TG * rs);
+        HIP_OK(hipMemcpy(raw.data(), s->gW[b], raw.size(), hipMemcpyDeviceToHost));
+        if (s->prec == GKS_FP64) from_real<double>(raw, g); else from_real<float>(raw, g);
+        for (int v = 0; v < 6; v++)
+            for (int d = 0; d < 2; d++)
+                for (int64_t c = 0; c < T; c++)
+                    gradW[(2 * v + d) * T + c] = v == 3 ? g[(2 * v + d) * TG + c] - h.gB[d * T + c] : g[(2 * v + d) * TG + c];
+    }
+    if (t) return gks_state_time(s, 0, t, nullptr);
+    return GKS_OK;
+}
+
+gks_status gks_state_time(const gks_state *s, int32_t scen, double *t, double *dt)
+{
+    if (!s || scen < 0 || scen >= s->md.S) return fail(GKS_EINVAL, "bad scenario index");
+    double sc[2];
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(sc, s->scal + 2 * scen, sizeof(sc), hipMemcpyDeviceToHost));
+    if (t) *t = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
+    if (dt) *dt = sc[0];
+    return GKS_OK;
+}
+
+gks_status gks_state_mass(const gks_state *s, int32_t scen, double mass[2])
+{
+    if (!s || !mass || scen < -1 || scen >= s->md.S) return fail(GKS_EINVAL, "bad mass query");
+    const gks::HostMesh &h = s->mesh->host;
+    const int64_t c0 = scen < 0 ? 0 : h.scell[scen], c1 = scen < 0 ? h.nt : h.scell[scen + 1];
     const int nb = 256;
-    hipLaunchKernelGGL(gks::k_mass_partial, dim3(nb), dim3(256), 0, s->stream, m, s->half ? s->Wb : s->Wa,
+    hipLaunchKernelGGL(gks::k_mass_partial, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[s->half ? 1 : 0], c0, c1,
                        s->part);
     HIP_OK(hipGetLastError());
     std::vector<double> part(2 * nb);
@@ -396,3 +643,23 @@ gks_status gks_state_mass(const gks_state *s, double mass[2])
 }
 
 }  // extern "C"
+
+extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *dst, int64_t bytes)
+{
+    if (!s || !dst || which < 0 || which >= GKS_BUF_COUNT) return fail(GKS_EINVAL, "bad buffer query");
+    const int64_t T = s->md.T, E = s->md.E;
+    const int64_t rs = s->prec == GKS_FP64 ? 8 : 4;
+    const void *src = nullptr;
+    int64_t need = 0;
+    switch (which) {
+    case GKS_BUF_RECH: src = s->rech; need = 12 * T * 8; break;
+    case GKS_BUF_RECM: src = s->recm; need = 96 * T * rs; break;
+    case GKS_BUF_R0: src = s->r0; need = 2 * T * rs; break;
+    case GKS_BUF_EOH: src = s->eoh; need = 4 * E * 8; break;
+    default: src = s->eom; need = 22 * E * rs; break;
+    }
+    if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(dst, src, (size_t)need, hipMemcpyDeviceToHost));
+    return GKS_OK;
+}

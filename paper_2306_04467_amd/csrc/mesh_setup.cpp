@@ -442,7 +442,101 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
     m.gR.assign(4 * std::max<int64_t>(m.ng, 1), 0);
     for (int64_t g = 0; g < m.ng; g++)
         for (int i = 0; i < 4; i++) m.gR[i * m.ng + g] = gR[4 * g + i];
+    m.S = 1;
+    m.scell = {0, nt};
+    m.sdxmin = {m.dxmin};
     return 0;
+}
+
+}  // namespace gks
+
+namespace gks {
+
+HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts)
+{
+    HostMesh o;
+    o.S = (int32_t)parts.size();
+    for (const HostMesh *p : parts) {
+        o.nt += p->nt;
+        o.ne += p->ne;
+        o.ng += p->ng;
+    }
+    const int64_t T = o.nt, E = o.ne, NG = o.ng;
+    auto cells = [&](std::vector<double> &dst, int width, std::vector<double> HostMesh::*src) {
+        dst.assign((size_t)width * T, 0);
+        int64_t off = 0;
+        for (const HostMesh *p : parts) {
+            for (int w = 0; w < width; w++)
+                for (int64_t c = 0; c < p->nt; c++) dst[w * T + off + c] = (p->*src)[w * p->nt + c];
+            off += p->nt;
+        }
+    };
+    auto edges = [&](std::vector<double> &dst, int width, std::vector<double> HostMesh::*src) {
+        dst.assign((size_t)width * E, 0);
+        int64_t off = 0;
+        for (const HostMesh *p : parts) {
+            for (int w = 0; w < width; w++)
+                for (int64_t e = 0; e < p->ne; e++) dst[w * E + off + e] = (p->*src)[w * p->ne + e];
+            off += p->ne;
+        }
+    };
+    cells(o.area, 1, &HostMesh::area);
+    cells(o.hs, 1, &HostMesh::hs);
+    cells(o.vtx, 6, &HostMesh::vtx);
+    cells(o.nbc, 6, &HostMesh::nbc);
+    cells(o.fl, 3, &HostMesh::fl);
+    cells(o.gg, 6, &HostMesh::gg);
+    cells(o.Bbar, 1, &HostMesh::Bbar);
+    cells(o.gB, 2, &HostMesh::gB);
+    cells(o.M, 153, &HostMesh::M);
+    edges(o.en, 2, &HostMesh::en);
+    edges(o.eBgp, 2, &HostMesh::eBgp);
+    edges(o.egB, 2, &HostMesh::egB);
+    o.cedge.assign(3 * T, 0);
+    o.sten.assign(9 * T, 0);
+    o.eL.assign(E, 0);
+    o.eR.assign(E, 0);
+    o.eslot.assign(E, 0);
+    o.gsrc.assign(NG, 0);
+    o.gR.assign(4 * std::max<int64_t>(NG, 1), 0);
+    o.cscen.assign(T, 0);
+    o.escen.assign(E, 0);
+    o.scell.assign(o.S + 1, 0);
+    o.sdxmin.assign(o.S, 0);
+    int64_t coff = 0, eoff = 0, goff = 0;
+    for (int32_t s = 0; s < o.S; s++) {
+        const HostMesh *p = parts[s];
+        o.scell[s] = coff;
+        o.sdxmin[s] = p->dxmin;
+        // a cell index of the part: real cells shift by coff, ghost cells move behind all real cells
+        auto cell_index = [&](int32_t i) -> int32_t {
+            return i < p->nt ? (int32_t)(coff + i) : (int32_t)(T + goff + (i - p->nt));
+        };
+        for (int64_t c = 0; c < p->nt; c++) {
+            o.cscen[coff + c] = s;
+            for (int k = 0; k < 3; k++) {
+                int32_t code = p->cedge[k * p->nt + c];
+                o.cedge[k * T + coff + c] = code >= 0 ? (int32_t)(code + eoff) : ~(int32_t)(~code + eoff);
+            }
+            for (int k = 0; k < 9; k++) o.sten[k * T + coff + c] = cell_index(p->sten[k * p->nt + c]);
+        }
+        for (int64_t e = 0; e < p->ne; e++) {
+            o.escen[eoff + e] = s;
+            o.eL[eoff + e] = (int32_t)(p->eL[e] + coff);
+            o.eR[eoff + e] = p->eR[e] >= 0 ? (int32_t)(p->eR[e] + coff) : -1;
+            o.eslot[eoff + e] = p->eslot[e];
+        }
+        for (int64_t g = 0; g < p->ng; g++) {
+            o.gsrc[goff + g] = (int32_t)(p->gsrc[g] + coff);
+            for (int i = 0; i < 4; i++) o.gR[i * NG + goff + g] = p->gR[i * p->ng + g];
+        }
+        coff += p->nt;
+        eoff += p->ne;
+        goff += p->ng;
+    }
+    o.scell[o.S] = T;
+    o.dxmin = *std::min_element(o.sdxmin.begin(), o.sdxmin.end());
+    return o;
 }
 
 }  // namespace gks

@@ -33,10 +33,20 @@ struct HostMesh {
     // ghosts
     std::vector<int32_t> gsrc;       // [NG] source cell
     std::vector<double> gR;          // [4][NG] orthogonal map applied to the source state
+    // scenarios (independent meshes concatenated into one); a single mesh has S = 1 and
+    // empty cscen / escen
+    int32_t S = 1;
+    std::vector<int32_t> cscen, escen;  // [T], [E] scenario of each cell / edge
+    std::vector<int64_t> scell;         // [S + 1] first cell of each scenario
+    std::vector<double> sdxmin;         // [S]
 };
 
 // Returns 0 on success, otherwise fills err.  bc: 0 walls, 1 periodic on [0,L0]x[0,L1].
 int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt, const double *B,
                     int bc, const double *L, HostMesh &m, std::string &err);
+
+// Concatenate independent meshes into one with S scenarios (cells, edges and ghosts renumbered
+// with offsets; ghost cells of all scenarios follow all real cells).
+HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts);
 
 }  // namespace gks

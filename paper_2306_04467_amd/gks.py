@@ -17,16 +17,21 @@ _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
 
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_EMESH, GKS_ENONFINITE, GKS_EUNSUPPORTED = range(7)
 GKS_BC_WALL, GKS_BC_PERIODIC = 0, 1
-GKS_FP64 = 0
+GKS_FP64, GKS_FP32_MIXED = 0, 1
+PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 
 # every entry point declared in include/gks.h
-SYMBOLS = ("gks_mesh_create", "gks_mesh_destroy", "gks_mesh_info", "gks_state_init", "gks_state_destroy",
-           "gks_stage", "gks_step", "gks_state_read", "gks_state_mass", "gks_profile", "gks_profile_read",
+SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_info", "gks_mesh_scenario",
+           "gks_state_init", "gks_state_destroy", "gks_stage", "gks_step", "gks_batch_step", "gks_state_read",
+           "gks_state_time", "gks_state_mass", "gks_state_buffer", "gks_profile", "gks_profile_read",
            "gks_last_error")
+BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 4, True),
+           "eom": (4, 22, False)}
 KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt")
 
 
@@ -52,19 +57,23 @@ def load():
     lib.gks_last_error.restype = ctypes.c_char_p
     lib.gks_mesh_create.argtypes = [_dp, ctypes.c_int64, _i32p, ctypes.c_int64, _dp, ctypes.c_int32, _dp,
                                     ctypes.POINTER(_vp)]
+    lib.gks_mesh_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(_vp)]
     lib.gks_mesh_destroy.argtypes = [_vp]
     lib.gks_mesh_destroy.restype = None
-    lib.gks_mesh_info.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
-                                  ctypes.POINTER(ctypes.c_int64)]
+    lib.gks_mesh_info.argtypes = [_vp, _i64p, _i64p, _i64p, _i32p]
+    lib.gks_mesh_scenario.argtypes = [_vp, ctypes.c_int32, _i64p, _i64p]
     lib.gks_state_init.argtypes = [_vp, ctypes.POINTER(Params), _dp, _dp, _vp, ctypes.POINTER(_vp)]
     lib.gks_state_destroy.argtypes = [_vp]
     lib.gks_state_destroy.restype = None
     lib.gks_stage.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_step.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_batch_step.argtypes = [_vp, ctypes.c_int32]
     lib.gks_state_read.argtypes = [_vp, _dp, _dp, _dp]
-    lib.gks_state_mass.argtypes = [_vp, _dp]
+    lib.gks_state_time.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
+    lib.gks_state_mass.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_state_buffer.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64]
     lib.gks_profile.argtypes = [_vp, ctypes.c_int32]
-    lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, _i64p]
     for name in SYMBOLS:
         if name not in ("gks_mesh_destroy", "gks_state_destroy", "gks_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -95,25 +104,40 @@ def current_stream():
 
 
 class Mesh:
-    def __init__(self, node_xy, tri, node_B=None, periodic_L=None):
+    def __init__(self, node_xy=None, tri=None, node_B=None, periodic_L=None, _handle=None):
         lib = load()
-        self.node_xy = _f64(node_xy)
-        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
-        nB = None if node_B is None else _f64(node_B)
-        per = None if periodic_L is None else _f64(periodic_L)
-        h = _vp()
-        _check(lib.gks_mesh_create(_d(self.node_xy), self.node_xy.shape[0], self.tri.ctypes.data_as(_i32p),
-                                   self.tri.shape[0], None if nB is None else _d(nB),
-                                   GKS_BC_PERIODIC if per is not None else GKS_BC_WALL,
-                                   None if per is None else _d(per), ctypes.byref(h)))
-        self._h = h
-        T, E, NG = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _check(lib.gks_mesh_info(h, ctypes.byref(T), ctypes.byref(E), ctypes.byref(NG)))
-        self.n_tri, self.n_edges, self.n_ghost = T.value, E.value, NG.value
+        if _handle is None:
+            self.node_xy = _f64(node_xy)
+            self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+            nB = None if node_B is None else _f64(node_B)
+            per = None if periodic_L is None else _f64(periodic_L)
+            h = _vp()
+            _check(lib.gks_mesh_create(_d(self.node_xy), self.node_xy.shape[0], self.tri.ctypes.data_as(_i32p),
+                                       self.tri.shape[0], None if nB is None else _d(nB),
+                                       GKS_BC_PERIODIC if per is not None else GKS_BC_WALL,
+                                       None if per is None else _d(per), ctypes.byref(h)))
+            _handle = h
+        self._h = _handle
+        T, E, NG, S = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.gks_mesh_info(self._h, ctypes.byref(T), ctypes.byref(E), ctypes.byref(NG), ctypes.byref(S)))
+        self.n_tri, self.n_edges, self.n_ghost, self.n_scenarios = T.value, E.value, NG.value, S.value
 
     @classmethod
     def from_scenario(cls, sc):
         return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None)
+
+    @classmethod
+    def batch(cls, meshes):
+        """Concatenate single meshes into one batch mesh (the inputs stay usable)."""
+        arr = (_vp * len(meshes))(*[m._h for m in meshes])
+        h = _vp()
+        _check(load().gks_mesh_batch(arr, len(meshes), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def scenario_range(self, s):
+        a, n = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().gks_mesh_scenario(self._h, int(s), ctypes.byref(a), ctypes.byref(n)))
+        return a.value, n.value
 
     def close(self):
         if getattr(self, "_h", None):
@@ -124,25 +148,44 @@ class Mesh:
         self.close()
 
 
+def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False):
+    return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear))
+
+
 class State:
-    def __init__(self, mesh: Mesh, W0, gradW0, G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0,
-                 t_end=0.0, linear=False, stream=None):
+    """State on a (single or batch) mesh.  params: one Params, or a list with one per scenario."""
+
+    def __init__(self, mesh: Mesh, W0, gradW0, params=None, stream=None, **kw):
         lib = load()
         self.mesh = mesh
         T = mesh.n_tri
         W0 = _f64(W0).reshape(6, T)
         gW0 = _f64(gradW0).reshape(6, 2, T)
-        self.params = Params(G, chi, cfl, eps, eps_num, t_end, GKS_FP64, int(linear))
+        if params is None:
+            params = make_params(**kw)
+        plist = list(params) if isinstance(params, (list, tuple)) else [params]
+        if len(plist) != mesh.n_scenarios:
+            raise ValueError("one Params per scenario is needed")
+        self._params = (Params * len(plist))(*plist)
         if stream is None:
             stream = current_stream()
         self.stream = stream
         h = _vp()
-        _check(lib.gks_state_init(mesh._h, ctypes.byref(self.params), _d(W0), _d(gW0), stream, ctypes.byref(h)))
+        _check(lib.gks_state_init(mesh._h, self._params, _d(W0), _d(gW0), stream, ctypes.byref(h)))
         self._h = h
 
     @classmethod
-    def from_scenario(cls, mesh, sc, **kw):
-        return cls(mesh, sc.W0, sc.gradW0, G=sc.G, chi=sc.chi, cfl=sc.cfl, **kw)
+    def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, **kw):
+        p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear)
+        return cls(mesh, sc.W0, sc.gradW0, params=p, **kw)
+
+    @classmethod
+    def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, **kw):
+        ps = [make_params(G=s.G, chi=s.chi, cfl=s.cfl, t_end=s.t_end if s.t_end < 1e8 else 0.0,
+                          precision=precision, linear=linear) for s in scs]
+        W0 = np.concatenate([s.W0 for s in scs], axis=1)
+        gW0 = np.concatenate([s.gradW0 for s in scs], axis=2)
+        return cls(batch_mesh, W0, gW0, params=ps, **kw)
 
     def stage(self, k, dt=None):
         d = None if dt is None else ctypes.byref(ctypes.c_double(dt))
@@ -156,6 +199,9 @@ class State:
         _check(load().gks_step(self._h, int(n), None))
         return None
 
+    def batch_step(self, n=1):
+        _check(load().gks_batch_step(self._h, int(n)))
+
     def read(self):
         T = self.mesh.n_tri
         W = np.zeros((6, T))
@@ -164,10 +210,24 @@ class State:
         _check(load().gks_state_read(self._h, _d(W), _d(gW), ctypes.byref(t)))
         return W, gW, t.value
 
-    def mass(self):
+    def time(self, s=0):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        _check(load().gks_state_time(self._h, int(s), ctypes.byref(t), ctypes.byref(dt)))
+        return t.value, dt.value
+
+    def mass(self, s=-1):
         m = np.zeros(2)
-        _check(load().gks_state_mass(self._h, _d(m)))
+        _check(load().gks_state_mass(self._h, int(s), _d(m)))
         return m
+
+    def buffer(self, name):
+        """Intermediate array of the last stage (see gks_buffer in include/gks.h)."""
+        which, rows, fp64 = BUFFERS[name]
+        n = self.mesh.n_edges if name in ("eoh", "eom") else self.mesh.n_tri
+        dt = np.float64 if (fp64 or self._params[0].precision == GKS_FP64) else np.float32
+        out = np.zeros((rows, n), dtype=dt)
+        _check(load().gks_state_buffer(self._h, which, out.ctypes.data_as(_vp), out.nbytes))
+        return out
 
     def profile(self, enable=True):
         _check(load().gks_profile(self._h, int(bool(enable))))

@@ -3,14 +3,16 @@
 
 One step = the whole hot path once: device CFL time step, then the two S2O4 stages, each running
 ghost refresh, reconstruction, force-model heights and planes, gas-kinetic flux at every Gauss
-point and the gather/source/update kernel.  Inputs are resident on the GPU before timing starts.
+point and the gather/source/update kernel.  Inputs are resident on the GPU before timing starts;
+the timed region is bracketed by device synchronisation and measured with HIP events.
 
-Default workload: FP64 plain path on the 520,200-triangle jittered Delaunay mesh of [0,1]^2 with a
-Gaussian bottom bump, lake at rest plus a 1e-3 interface perturbation in a disk, reflecting walls.
-
-Prints ONE JSON line (see the design doc for the fields).  Kernel durations for the roofline come from
-HIP events recorded by the library around each launch on its stream; the CPU baseline times the
-FP64 oracle on the host for one full step of the same workload.
+Headline (``value``): FP64 plain path on the 520,200-triangle jittered Delaunay mesh of [0,1]^2
+with a Gaussian bottom bump, lake at rest plus a 1e-3 interface perturbation in a disk, walls.
+Also reported on the same JSON line: the mixed FP32/FP64 path on the same workload, the batched
+ensemble of 256 independent scenarios (sizes log-uniform in 5k-200k triangles, FP32, steps replayed
+from a HIP graph), each with its relative L1 error against the FP64 oracle; the roofline of the
+dominant kernel (algorithmic bytes / duration measured with HIP events recorded by the library
+around each launch on its stream); and the oracle's single-threaded throughput on the host.
 """
 from __future__ import annotations
 
@@ -27,21 +29,35 @@ METRIC = "triangle-stage updates/s, FP64 plain vs FP32+learned-indicator, at rel
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes_fp64(T, E, NG):
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(T, E, NG, prec):
     """Bytes each kernel must move per launch if every input is read once and every output
-    written once (neighbour re-reads served by caches).  FP64 words, int32 indices."""
+    written once (neighbour re-reads are cache traffic).  r = bytes of the bulk precision; the
+    thicknesses, hydrostatic terms and geometry of the update are FP64; indices are int32."""
+    r = 8 if prec == "fp64" else 4
+    d = 8
     return {
-        "recon": T * (8 * (6 + 12 + 153 + 6 + 1 + 6) + 4 * 9 + 8 * (108 + 2)),
-        "flux": T * 8 * (108 + 2 + 4) + E * (4 * 3 + 8 * 6 + 8 * 24),
-        "hhat": T * 8 * 36 + E * (4 * 3 + 8 * 4 + 8 * 2),
-        "plane": T * (4 * 3 + 8 * 6 + 8 * 4) + E * 8 * 2,
-        "update": T * (4 * 3 + 8 * 12) + E * 8 * 24 + T * 8 * 36,  # stage average of 6+36 / 36+18 words
-        "ghost": NG * (8 * 36 + 8 * 4 + 4),
-        "dt": T * 8 * 4,
+        # own state (2 thicknesses FP64, 4 momenta, 12 gradients), M (153), geometry, stencil;
+        # writes Gauss-point records (12 FP64 thicknesses, 96 values/gradients) and 2 weights
+        "recon": T * (2 * d + 4 * r + 12 * r + 153 * r + 13 * r + 4 * 9 + 12 * d + 96 * r + 2 * r),
+        # every record once, weights and plane gradients once per cell; edge tables; outputs
+        "flux": T * (12 * d + 96 * r + 2 * r + 4 * d) + E * (4 * 3 + 2 * r + 2 * d + 2 * r + 4 * d + 22 * r),
+        "hhat": T * (12 * d + 24 * r) + E * (4 * 3 + 2 * r + 2 * d + 2 * d),
+        "plane": T * (4 * 3 + 6 * d + 4 * d) + E * 2 * d,
+        # geometry, edge outputs once, state / carry (average of the two stages)
+        "update": T * (4 * 3 + 12 * d) + E * (4 * d + 22 * r) + T * ((2 * d + 4 * r) * 2 + 12 * r + 6 * d + 12 * r
+                                                                     + (6 * d + 12 * r)) // 2,
+        "ghost": NG * (2 * 2 * d + 2 * 16 * r + 4 * d + 4),
+        "dt": T * (2 * d + 4 * r + d),
     }
 
 
 def rel_l1(W, Wr, area, G):
+    """max over the six variables of the area-weighted relative L1 error; momenta are measured
+    against sum |Omega| h sqrt(G h)."""
     import numpy as np
 
     out = []
@@ -51,7 +67,112 @@ def rel_l1(W, Wr, area, G):
         den = (area * h * np.sqrt(G * h)).sum()
         for v in (o + 1, o + 2):
             out.append((area * np.abs(W[v] - Wr[v])).sum() / den)
-    return max(out)
+    return float(max(out))
+
+
+def sc_area(sc):
+    a, b, c = (sc.node_xy[sc.tri[:, k]] for k in range(3))
+    return 0.5 * ((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
+
+
+def timed_steps(st, steps, warmup, graph=False):
+    import torch
+
+    run = st.batch_step if graph else st.step
+    run(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def kernel_roofline(st, mesh, steps, prec):
+    st.profile(True)
+    st.step(steps)
+    prof = st.profile_read()
+    st.profile(False)
+    alg = algorithmic_bytes(mesh.n_tri, mesh.n_edges, mesh.n_ghost, prec)
+    kernels = {}
+    for k, (tot, n) in prof.items():
+        if n:
+            avg = tot / n
+            kernels[k] = {"avg_ms": round(avg, 5), "launches": n, "alg_GBs": round(alg[k] / (avg / 1e3) / 1e9, 1)}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    avg = kernels[dom]["avg_ms"]
+    achieved = alg[dom] / (avg / 1e3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_launch": int(alg[dom])}
+    return kernels, roof
+
+
+def run_single(sc, prec, steps, warmup, profile):
+    from paper_2306_04467_amd import Mesh, State
+
+    mesh = Mesh.from_scenario(sc)
+    st = State.from_scenario(mesh, sc, precision=prec)
+    ms = timed_steps(st, steps, warmup)
+    value = mesh.n_tri * 2 * steps / (ms / 1e3)
+    log(f"{prec}: {steps} steps {ms:.2f} ms, {value / 1e9:.3f} G tri-stage/s")
+    kernels, roof = kernel_roofline(st, mesh, steps, prec) if profile else ({}, None)
+    if profile:
+        log(f"{prec} kernels: {json.dumps(kernels)}")
+    return mesh, value, ms / steps, kernels, roof
+
+
+def one_step_error(mesh, sc, prec, Wr, dt):
+    from paper_2306_04467_amd import State
+
+    st = State.from_scenario(mesh, sc, precision=prec)
+    st.stage(0, dt)
+    st.stage(1)
+    W, _, _ = st.read()
+    return rel_l1(W, Wr, sc_area(sc), sc.G)
+
+
+def run_ensemble(n_scen, steps, warmup, with_error):
+    import numpy as np
+
+    import workloads
+    from paper_2306_04467_amd import Mesh, State
+
+    t0 = time.time()
+    scs = workloads.ensemble(n_scen)
+    T = sum(s.n_tri for s in scs)
+    log(f"ensemble: {n_scen} scenarios, {T} triangles built ({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    meshes = [Mesh.from_scenario(s) for s in scs]
+    bm = Mesh.batch(meshes)
+    for m in meshes:
+        m.close()
+    log(f"ensemble mesh setup {time.time() - t0:.1f}s")
+    st = State.from_scenarios(bm, scs, precision="fp32")
+    ms = timed_steps(st, steps, warmup, graph=True)
+    value = T * 2 * steps / (ms / 1e3)
+    log(f"ensemble fp32 graph: {steps} steps {ms:.2f} ms, {value / 1e9:.3f} G tri-stage/s")
+    out = {"value": round(value, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5),
+           "steps": steps, "n_scenarios": n_scen, "n_tri": T, "precision": "fp32-mixed",
+           "launch": "one HIP graph replay per step (all scenarios, both stages)"}
+    if with_error:
+        # error of the first three scenarios after one step, against the oracle
+        import oracle
+
+        st2 = State.from_scenarios(bm, scs, precision="fp32")
+        st2.step(1)
+        W, _, _ = st2.read()
+        errs = []
+        for i in range(3):
+            sc = scs[i]
+            om = oracle.Mesh.from_scenario(sc)
+            p = oracle.params_of(sc)
+            Wr, _ = oracle.step(om, p, oracle.dt(om, p, sc.W0), sc.W0, sc.gradW0)
+            c0, n = bm.scenario_range(i)
+            errs.append(rel_l1(W[:, c0:c0 + n], Wr, sc_area(sc), sc.G))
+        out["rel_l1_vs_oracle_1step_first3"] = float(np.max(errs))
+    return out
 
 
 def main():
@@ -59,9 +180,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--n", type=int, default=510, help="lattice size: 2 n^2 triangles")
+    ap.add_argument("--n", type=int, default=510, help="lattice size of the headline mesh: 2 n^2 triangles")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
+                    help="run only this precision on the headline workload")
+    ap.add_argument("--ensemble", type=int, default=256, help="scenarios in the ensemble leg (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed pass")
+    ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -80,101 +204,61 @@ def main():
               "the multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import workloads
-    from paper_2306_04467_amd import Mesh, State
 
     torch.cuda.set_device(0)
     t0 = time.time()
     sc = workloads.lake_at_rest(args.n, seed=20230604, perturb=1e-3, disk=(0.3, 0.3, 0.1))
-    print(f"[bench] workload built: {sc.n_tri} triangles ({time.time() - t0:.1f}s)", file=sys.stderr, flush=True)
-    t0 = time.time()
-    mesh = Mesh.from_scenario(sc)
-    print(f"[bench] mesh setup: {mesh.n_edges} edges, {mesh.n_ghost} ghosts ({time.time() - t0:.1f}s)",
-          file=sys.stderr, flush=True)
-    st = State.from_scenario(mesh, sc)
-    stream = torch.cuda.current_stream()
+    log(f"workload built: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
+    precs = [args.precision] if args.precision else ["fp64", "fp32"]
+    res = {}
+    for prec in precs:
+        res[prec] = run_single(sc, prec, args.steps, args.warmup, not args.no_profile)
+    head = precs[0]
+    mesh, value, ms_step, kernels, roof = res[head]
 
-    st.step(args.warmup)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_wall = time.time()
-    ev0.record(stream)
-    st.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.time() - t_wall
-    ms = ev0.elapsed_time(ev1)
-    ms_per_step = ms / args.steps
-    T, E, NG = mesh.n_tri, mesh.n_edges, mesh.n_ghost
-    value = T * 2 * args.steps / (ms / 1e3)
-    print(f"[bench] {args.steps} steps: {ms:.2f} ms (wall {t_wall * 1e3:.1f} ms), {value / 1e9:.3f} G tri-stage/s",
-          file=sys.stderr, flush=True)
-
-    # per-kernel durations from HIP events on the library's stream, same steps again
-    roofline, kernels = None, {}
-    if not args.no_profile:
-        st.profile(True)
-        st.step(args.steps)
-        prof = st.profile_read()
-        st.profile(False)
-        alg = algorithmic_bytes_fp64(T, E, NG)
-        for k, (tot, n) in prof.items():
-            if n:
-                avg = tot / n
-                kernels[k] = {"avg_ms": round(avg, 5), "launches": n,
-                              "alg_GBs": round(alg[k] / (avg / 1e3) / 1e9, 1)}
-        dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-        avg = kernels[dom]["avg_ms"]
-        achieved = alg[dom] / (avg / 1e3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                    "alg_bytes_per_launch": alg[dom]}
-        print(f"[bench] kernels: {json.dumps(kernels)}", file=sys.stderr, flush=True)
-
-    cpu = None
-    err = None
+    cpu, errs = None, {}
     if not args.no_cpu_baseline:
         import oracle
 
-        W1 = State.from_scenario(mesh, sc)
         om = oracle.Mesh.from_scenario(sc)
         p = oracle.params_of(sc)
         dt = oracle.dt(om, p, sc.W0)
         tc = time.time()
         Wr, _ = oracle.step(om, p, dt, sc.W0, sc.gradW0)
         tc = time.time() - tc
-        W1.stage(0, dt)
-        W1.stage(1)
-        Wg, _, _ = W1.read()
-        area = sc_area(sc)
-        err = rel_l1(Wg, Wr, area, sc.G)
-        cpu = {"value": round(T * 2 / tc, 1), "unit": "triangle-stage/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full S2O4 step (2 stages) of the same {T}-triangle workload, single-threaded "
-                         f"FP64 C oracle, {tc:.1f} s"}
-        print(f"[bench] oracle step {tc:.1f}s, rel-L1 GPU vs oracle {err:.3e}", file=sys.stderr, flush=True)
+        for prec in precs:
+            errs[prec] = one_step_error(res[prec][0], sc, prec, Wr, dt)
+        cpu = {"value": round(sc.n_tri * 2 / tc, 1), "unit": "triangle-stage/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full S2O4 step (2 stages) of the same {sc.n_tri}-triangle workload, "
+                         f"single-threaded FP64 C oracle, {tc:.1f} s"}
+        log(f"oracle step {tc:.1f}s; rel-L1 vs oracle after one step: {errs}")
+
+    extra = {}
+    if "fp32" in res and head != "fp32":
+        _, v32, ms32, k32, r32 = res["fp32"]
+        extra["fp32_mixed"] = {"value": round(v32, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms32, 5),
+                               "speedup_vs_fp64": round(v32 / value, 3), "rel_l1_vs_oracle_1step": errs.get("fp32"),
+                               "roofline": r32, "kernels": k32}
+    if args.ensemble > 0:
+        extra["ensemble"] = run_ensemble(args.ensemble, 50, 5, not args.no_cpu_baseline)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "triangle-stage/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"fp64 plain: jittered-node Delaunay [0,1]^2, {T} triangles, Gaussian bottom "
-                               f"bump 0.5exp(-50r^2), lake at rest eta1=0.8 h2=0.2 + 1e-3 interface "
+        "config": {"workload": f"{head} plain: jittered-node Delaunay [0,1]^2, {sc.n_tri} triangles, Gaussian "
+                               f"bottom bump 0.5exp(-50r^2), lake at rest eta1=0.8 h2=0.2 + 1e-3 interface "
                                f"perturbation in a disk, walls, chi=0.98, CFL 0.3",
-                   "n_tri": T, "n_edges": E, "precision": "fp64", "rel_l1_vs_oracle_1step": err},
-        "roofline": roofline, "cpu_baseline": cpu, "kernels": kernels,
+                   "n_tri": sc.n_tri, "n_edges": mesh.n_edges, "precision": head,
+                   "rel_l1_vs_oracle_1step": errs.get(head)},
+        "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, **extra,
     }
     print(json.dumps(line), flush=True)
-
-
-def sc_area(sc):
-    import numpy as np
-
-    a, b, c = (sc.node_xy[sc.tri[:, k]] for k in range(3))
-    return 0.5 * ((b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0]))
 
 
 if __name__ == "__main__":

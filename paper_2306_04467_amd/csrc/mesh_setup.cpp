@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <thread>
 #include <tuple>
 #include <unordered_map>
 
@@ -377,7 +378,14 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
     m.sten.assign(9 * nt, 0);
     m.nbc.assign(6 * nt, 0);
     m.M.assign(153 * nt, 0);
-    for (int64_t c = 0; c < nt; c++) {
+    // stencil images and least-squares operators: independent per cell, computed by a pool of host
+    // threads; the images' linear parts are kept to number the ghost cells serially afterwards
+    struct SlotImage {
+        int64_t cell;
+        double a, b, c, d;
+    };
+    std::vector<SlotImage> slots(9 * (size_t)nt);
+    auto cell_work = [&](int64_t c) {
         int64_t img_cell[10];
         Aff img_T[10];
         img_cell[0] = c;
@@ -399,7 +407,10 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
                 img_T[4 + 2 * k + (q - 1)] = aff_then(faceT[k], T2);
             }
         }
-        for (int s = 0; s < 9; s++) m.sten[s * nt + c] = index_of(img_cell[1 + s], img_T[1 + s]);
+        for (int s = 0; s < 9; s++) {
+            const Aff &T = img_T[1 + s];
+            slots[9 * (size_t)c + s] = {img_cell[1 + s], T.a, T.b, T.c, T.d};
+        }
         // least-squares rows in scaled coordinates about the centroid
         const double hs = m.hs[c];
         double v0[3][2];
@@ -436,7 +447,22 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
         double Mc[153];
         lsq_operator(A, Mc);
         for (int i = 0; i < 153; i++) m.M[(int64_t)i * nt + c] = Mc[i];
+    };
+    {
+        const int64_t nthr = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(),
+                                                                       (nt + 4095) / 4096}));
+        std::vector<std::thread> pool;
+        for (int64_t t = 0; t < nthr; t++)
+            pool.emplace_back([&, t] {
+                for (int64_t c = t * nt / nthr; c < (t + 1) * nt / nthr; c++) cell_work(c);
+            });
+        for (auto &th : pool) th.join();
     }
+    for (int64_t c = 0; c < nt; c++)
+        for (int s = 0; s < 9; s++) {
+            const SlotImage &im = slots[9 * (size_t)c + s];
+            m.sten[s * nt + c] = index_of(im.cell, Aff{im.a, im.b, im.c, im.d, 0, 0});
+        }
     m.ng = (int64_t)gsrc.size();
     m.gsrc = gsrc;
     m.gR.assign(4 * std::max<int64_t>(m.ng, 1), 0);

@@ -218,18 +218,32 @@ def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, dis
     return Scenario(name, xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0)
 
 
+def _ensemble_member(args):
+    s, n, seed, chi, amp, cfl, G = args
+    sc = lake_at_rest(n, seed=seed, chi=chi, perturb=amp, cfl=cfl, G=G)
+    sc.name = f"ensemble_{s}_n{n}"
+    return sc
+
+
 def ensemble(n_scen: int = 256, seed: int = 20230606, t_min: int = 5000, t_max: int = 200000,
-             cfl: float = 0.3, G: float = 9.81):
+             cfl: float = 0.3, G: float = 9.81, workers: Optional[int] = None):
     """Independent bump + rest + disk-perturbation scenarios with log-uniform sizes, log-uniform
-    perturbation amplitudes in [1e-4, 1e-2] and density ratios uniform in [0.90, 0.99]."""
+    perturbation amplitudes in [1e-4, 1e-2] and density ratios uniform in [0.90, 0.99].  The
+    parameters are drawn in order from one seeded generator; the meshes are built by a pool of
+    processes (at most 16)."""
+    import os
+    from concurrent.futures import ProcessPoolExecutor
+
     rng = np.random.default_rng(seed)
-    out = []
+    jobs = []
     for s in range(n_scen):
         T = math.exp(rng.uniform(math.log(t_min), math.log(t_max)))
         n = max(4, int(round(math.sqrt(T / 2.0))))
         amp = math.exp(rng.uniform(math.log(1e-4), math.log(1e-2)))
         chi = float(rng.uniform(0.90, 0.99))
-        sc = lake_at_rest(n, seed=seed + 1 + s, chi=chi, perturb=amp, cfl=cfl, G=G)
-        sc.name = f"ensemble_{s}_n{n}"
-        out.append(sc)
-    return out
+        jobs.append((s, n, seed + 1 + s, chi, amp, cfl, G))
+    workers = workers if workers is not None else min(16, os.cpu_count() or 1)
+    if workers <= 1 or n_scen < 4:
+        return [_ensemble_member(j) for j in jobs]
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_ensemble_member, jobs, chunksize=4))

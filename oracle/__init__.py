@@ -62,8 +62,38 @@ def load():
                             _dp, _dp, _dp, _dp]
     lib.om_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.om_cell_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    lib.om_features.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    lib.om_mlp_forward.argtypes = [_dp, _dp, ctypes.c_int, _dp]
+    lib.om_mlp_grad.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+    lib.om_mlp_grad.restype = ctypes.c_double
     _lib = lib
     return lib
+
+
+MLP_IN, MLP_H = 40, 64
+MLP_PARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
+
+
+def features(mesh, W, gW):
+    """Indicator features [T, 40] of every cell (see om_features)."""
+    X = np.zeros((mesh.n_tri, MLP_IN))
+    load().om_features(mesh._h, _d(_f64(W)), _d(_f64(gW)), _d(X))
+    return X
+
+
+def mlp_forward(P, X):
+    X = _f64(X)
+    z = np.zeros(X.shape[0])
+    load().om_mlp_forward(_d(_f64(P)), _d(X), X.shape[0], _d(z))
+    return z
+
+
+def mlp_grad(P, X, y):
+    """(mean logistic loss, gradient [6849]) of the MLP on the batch (X, y)."""
+    X = _f64(X)
+    g = np.zeros(MLP_PARAMS)
+    loss = load().om_mlp_grad(_d(_f64(P)), _d(X), _d(_f64(y)), X.shape[0], _d(g))
+    return loss, g
 
 
 def _d(a):

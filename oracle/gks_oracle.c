@@ -1255,3 +1255,103 @@ void om_mass(const om_mesh *m, const double *W, double *mass)
         mass[1] += m->area[c] * W[3 * T + c];
     }
 }
+
+/* ----------------------------------------------------------------------------------------- */
+/* learned smoothness indicator: features and the multilayer perceptron                       */
+
+#define MLP_IN 40
+#define MLP_H 64
+
+void om_features(const om_mesh *m, const double *W, const double *gW, double *X)
+{
+    for (int c = 0; c < m->nt; c++) {
+        double q[NS][NV], gq[NS][NV][2];
+        for (int l = 0; l < NS; l++) {
+            int n = m->st_cell[NS * c + l];
+            image_state(m, n, m->st_map[NS * c + l].R, W, gW, q[l], &gq[l][0][0]);
+        }
+        double h = sqrt(2.0 * m->area[c]);
+        double *x = X + (size_t)c * MLP_IN;
+        const int fields[2] = {3, 0}; /* eta1, h2 */
+        for (int f = 0; f < 2; f++) {
+            int v = fields[f];
+            double Q0 = q[0][v], s = 0;
+            for (int l = 1; l < NS; l++) s = fmax(s, fabs(q[l][v] - Q0));
+            s += 1e-12 * fabs(Q0);
+            for (int l = 1; l < NS; l++) x[17 * f + l - 1] = (q[l][v] - Q0) / s;
+            for (int l = 0; l < 4; l++)
+                for (int d = 0; d < 2; d++) x[17 * f + 9 + 2 * l + d] = h * gq[l][v][d] / s;
+        }
+        for (int l = 1; l <= 3; l++) x[34 + l - 1] = m->area[m->st_cell[NS * c + l]] / m->area[c];
+        for (int k = 0; k < 3; k++) x[37 + k] = m->e_len[m->c_edge[3 * c + k]] / h;
+    }
+}
+
+/* hidden activations of one sample (ReLU layers) */
+static void mlp_hidden(const double *P, const double *x, double *a1, double *h1, double *a2, double *h2)
+{
+    const double *W1 = P, *b1 = W1 + MLP_IN * MLP_H, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    for (int j = 0; j < MLP_H; j++) {
+        double s = b1[j];
+        for (int i = 0; i < MLP_IN; i++) s += x[i] * W1[i * MLP_H + j];
+        a1[j] = s;
+        h1[j] = s > 0 ? s : 0;
+    }
+    for (int j = 0; j < MLP_H; j++) {
+        double s = b2[j];
+        for (int i = 0; i < MLP_H; i++) s += h1[i] * W2[i * MLP_H + j];
+        a2[j] = s;
+        h2[j] = s > 0 ? s : 0;
+    }
+}
+
+void om_mlp_forward(const double *P, const double *X, int B, double *z)
+{
+    const double *w3 = P + MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H, *b3 = w3 + MLP_H;
+    for (int s = 0; s < B; s++) {
+        double a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+        mlp_hidden(P, X + (size_t)s * MLP_IN, a1, h1, a2, h2);
+        double zz = b3[0];
+        for (int j = 0; j < MLP_H; j++) zz += h2[j] * w3[j];
+        z[s] = zz;
+    }
+}
+
+/* gradient of the mean logistic loss by backpropagation (chain rule, one sample at a time) */
+double om_mlp_grad(const double *P, const double *X, const double *y, int B, double *grad)
+{
+    const int n1 = MLP_IN * MLP_H, n2 = MLP_H * MLP_H;
+    const double *W2 = P + n1 + MLP_H, *w3 = W2 + n2 + MLP_H, *b3 = w3 + MLP_H;
+    double *gW1 = grad, *gb1 = gW1 + n1, *gW2 = gb1 + MLP_H, *gb2 = gW2 + n2, *gw3 = gb2 + MLP_H, *gb3 = gw3 + MLP_H;
+    for (int i = 0; i < n1 + MLP_H + n2 + MLP_H + MLP_H + 1; i++) grad[i] = 0;
+    double loss = 0;
+    for (int s = 0; s < B; s++) {
+        const double *x = X + (size_t)s * MLP_IN;
+        double a1[MLP_H], h1[MLP_H], a2[MLP_H], h2[MLP_H];
+        mlp_hidden(P, x, a1, h1, a2, h2);
+        double z = b3[0];
+        for (int j = 0; j < MLP_H; j++) z += h2[j] * w3[j];
+        /* softplus(z) - y z, written to avoid overflow */
+        loss += (z > 0 ? z + log1p(exp(-z)) : log1p(exp(z))) - y[s] * z;
+        double dz = (1.0 / (1.0 + exp(-z)) - y[s]) / B;
+        double d2[MLP_H], d1[MLP_H];
+        gb3[0] += dz;
+        for (int j = 0; j < MLP_H; j++) {
+            gw3[j] += dz * h2[j];
+            d2[j] = a2[j] > 0 ? dz * w3[j] : 0;
+            gb2[j] += d2[j];
+        }
+        for (int i = 0; i < MLP_H; i++) {
+            double acc = 0;
+            for (int j = 0; j < MLP_H; j++) {
+                gW2[i * MLP_H + j] += h1[i] * d2[j];
+                acc += W2[i * MLP_H + j] * d2[j];
+            }
+            d1[i] = a1[i] > 0 ? acc : 0;
+            gb1[i] += d1[i];
+        }
+        for (int i = 0; i < MLP_IN; i++)
+            for (int j = 0; j < MLP_H; j++) gW1[i * MLP_H + j] += x[i] * d1[j];
+    }
+    return loss / B;
+}

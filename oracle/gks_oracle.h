@@ -81,6 +81,18 @@ int om_step(const om_mesh *m, const om_params *p, double dt, int nstages, const 
 void om_mass(const om_mesh *m, const double *W, double *mass);
 void om_cell_geometry(const om_mesh *m, double *area, double *cx, double *cy);
 
+/* Learned smoothness indicator (reference for the GPU kernels).
+ * Features X[T][40] of each cell: for the interface level eta1 = h1 + B, then h2: the 9 stencil
+ * differences (Q_l - Q_0)/s and the 8 scaled gradients h grad Q_l / s of the cell and its face
+ * neighbours, s = max_l |Q_l - Q_0| + 1e-12 |Q_0|; then the face neighbours' area ratios and the
+ * cell's edge lengths over h = sqrt(2 |Omega|).
+ * MLP 40 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters P[6849] = W1[40][64], b1[64],
+ * W2[64][64], b2[64], w3[64], b3.  Loss: mean over the batch of softplus(z) - y z (logistic loss
+ * on the logit z). */
+void om_features(const om_mesh *m, const double *W, const double *gW, double *X);
+void om_mlp_forward(const double *P, const double *X, int B, double *z);
+double om_mlp_grad(const double *P, const double *X, const double *y, int B, double *grad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -152,7 +152,8 @@ typedef enum {
     GKS_KERNEL_FLUX = 4,    /* gas-kinetic evolution at the Gauss points (Sec. 2.2) */
     GKS_KERNEL_UPDATE = 5,  /* gather, sources, S2O4 stage update (Sec. 3.1-3.3) */
     GKS_KERNEL_DT = 6,      /* CFL time step (Sec. 4) */
-    GKS_KERNEL_COUNT = 7
+    GKS_KERNEL_INDICATOR = 7, /* learned smoothness indicator (skip mask of the reconstruction) */
+    GKS_KERNEL_COUNT = 8
 } gks_kernel;
 
 /* Kernel timing for measurement tools: enable != 0 starts recording a HIP event pair on the
@@ -162,6 +163,79 @@ gks_status gks_profile(gks_state *st, int32_t enable);
 /* Total time in ms and number of launches recorded for one kernel class since gks_profile
  * enabled recording.  Synchronising. */
 gks_status gks_profile_read(gks_state *st, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------------------------
+ * Learned smoothness indicator.  The nonlinear weights of the compact reconstruction (Sec. 3.4)
+ * return the linear P^3 reconstruction where the data are smooth, and the force model of Sec. 2.3
+ * needs no modelling there.  A small network predicts per cell, from its compact stencil, that
+ * the nonlinear weights would change nothing; such cells take the linear reconstruction directly.
+ *
+ * Network: 44 features -> 64 -> 64 -> 1 logit, ReLU hidden layers.  Parameters P[7105] (float):
+ * W1[44][64], b1[64], W2[64][64], b2[64], w3[64], b3 (row-major, input index first).
+ * Features of cell c, for the interface level eta1 = h1 + B and then for h2 (17 each, X[0..33]):
+ * the 9 stencil differences (Q_l - Q_c) / s, then hs * grad Q / s of the cell and of its 3 face
+ * neighbours (x, y), with s = max_l |Q_l - Q_c| + 1e-12 |Q_c| and hs = sqrt(2 |Omega_c|); the size
+ * of the variation log10(s / h) / 4 with h the layer's thickness (X[34] lower, X[35] upper); the
+ * size of the layer's momentum variation log10((sm + 1e-12 a) / a) / 4, sm the largest stencil
+ * difference of its two momentum components, a = h sqrt(G h) (X[36] lower, X[37] upper); the 3
+ * face neighbours' areas over |Omega_c| (X[38..40]) and the 3 edge lengths over hs (X[41..43]).
+ * Inference uses bf16 operands with float accumulation (v_mfma_f32_32x32x8_bf16); a cell is
+ * skipped when its logit exceeds the threshold.
+ * ------------------------------------------------------------------------------------------ */
+
+/* Number of parameters and of inputs of the indicator network. */
+#define GKS_MLP_PARAMS 7105
+#define GKS_MLP_FEATURES 44
+
+/* Switch the indicator on for every later stage of `st` (params: host [7105], copied) with the
+ * given logit threshold, or off (params = NULL).  A HIP graph captured by gks_batch_step before
+ * the call is discarded and captured again. */
+gks_status gks_indicator_set(gks_state *st, const float *params, float threshold);
+/* Evaluate the indicator on the latest state (synchronising): logits [n_tri] and mask [n_tri]
+ * (1 = skip the nonlinear weights) to host memory, either may be NULL; n_skip (may be NULL) the
+ * number of skipped cells.  GKS_EINVAL if the indicator is off. */
+gks_status gks_indicator_eval(gks_state *st, float *logits, uint8_t *mask, int64_t *n_skip);
+/* Features [n_tri][44] of the latest state to host memory (synchronising). */
+gks_status gks_state_features(gks_state *st, float *X);
+/* Labels of the latest state to host memory y [n_tri] (synchronising): 1 where the nonlinear and
+ * the linear reconstruction agree at all six Gauss points to tol times the variable's scale
+ * (the layer thickness for h2 and h1 + B, h sqrt(G h) for the layer's momenta), else 0.  Runs the
+ * reconstruction twice; overwrites the intermediate arrays of gks_state_buffer. */
+gks_status gks_state_labels(gks_state *st, double tol, uint8_t *y);
+
+/* Trainer: a device-resident sample set (features and 0/1 labels) and the network's parameters
+ * with Adam moments, trained on the GPU in float (mean logistic loss softplus(z) - y z). */
+typedef struct gks_trainer gks_trainer;
+/* capacity: maximum number of samples; max_batch: largest minibatch; params0: host [7105]
+ * initial parameters; stream: hipStream_t (NULL = null stream). */
+gks_status gks_trainer_create(int64_t capacity, int32_t max_batch, const float *params0, void *stream,
+                              gks_trainer **out);
+void gks_trainer_destroy(gks_trainer *tr);
+/* Append n samples from host memory: X [n][44], y [n] (0 or 1).  GKS_EINVAL beyond capacity. */
+gks_status gks_trainer_add(gks_trainer *tr, const float *X, const uint8_t *y, int64_t n);
+/* Append the features and labels (tolerance tol, as gks_state_labels) of every cell of the
+ * latest state of `st`, computed on the device without a host copy; st must live on the
+ * trainer's device.  n_added may be NULL. */
+gks_status gks_trainer_add_state(gks_trainer *tr, gks_state *st, double tol, int64_t *n_added);
+/* Number of samples and of label-1 samples (either may be NULL). */
+gks_status gks_trainer_info(const gks_trainer *tr, int64_t *n_samples, int64_t *n_positive);
+/* Mean loss and its gradient [7105] at the current parameters over the samples idx [B] (host),
+ * 1 <= B <= max_batch (synchronising).  Sums over the batch run in sample order. */
+gks_status gks_trainer_grad(gks_trainer *tr, const int32_t *idx, int32_t B, float *loss, float *grad);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) over `epochs` passes of minibatches
+ * of `batch` samples, the order of each pass a Fisher-Yates shuffle drawn from splitmix64 seeded
+ * with `seed`.  epoch_loss [epochs] (may be NULL): mean minibatch loss of each pass
+ * (synchronising). */
+gks_status gks_trainer_fit(gks_trainer *tr, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                           float *epoch_loss);
+/* Current parameters to host memory [7105] (synchronising). */
+gks_status gks_trainer_params(const gks_trainer *tr, float *params);
+/* Logits of every sample with the inference arithmetic (bf16 operands) to host memory [n]
+ * (synchronising). */
+gks_status gks_trainer_logits(gks_trainer *tr, float *logits);
+/* Threshold for gks_indicator_set: the smallest logit threshold at which at most
+ * max_false_skip * n samples of label 0 would be skipped, with the inference arithmetic. */
+gks_status gks_trainer_threshold(gks_trainer *tr, double max_false_skip, float *threshold);
 
 const char *gks_last_error(void);
 

@@ -62,22 +62,23 @@ def load():
                             _dp, _dp, _dp, _dp]
     lib.om_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
     lib.om_cell_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
-    lib.om_features.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    lib.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp, _dp]
     lib.om_mlp_forward.argtypes = [_dp, _dp, ctypes.c_int, _dp]
     lib.om_mlp_grad.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
+    lib.om_mlp_forward_bf16.argtypes = [_dp, _dp, ctypes.c_int, _dp]
     lib.om_mlp_grad.restype = ctypes.c_double
     _lib = lib
     return lib
 
 
-MLP_IN, MLP_H = 40, 64
+MLP_IN, MLP_H = 44, 64
 MLP_PARAMS = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1
 
 
-def features(mesh, W, gW):
-    """Indicator features [T, 40] of every cell (see om_features)."""
+def features(mesh, W, gW, G=9.81):
+    """Indicator features [T, 44] of every cell (see om_features)."""
     X = np.zeros((mesh.n_tri, MLP_IN))
-    load().om_features(mesh._h, _d(_f64(W)), _d(_f64(gW)), _d(X))
+    load().om_features(mesh._h, float(G), _d(_f64(W)), _d(_f64(gW)), _d(X))
     return X
 
 
@@ -85,6 +86,14 @@ def mlp_forward(P, X):
     X = _f64(X)
     z = np.zeros(X.shape[0])
     load().om_mlp_forward(_d(_f64(P)), _d(X), X.shape[0], _d(z))
+    return z
+
+
+def mlp_forward_bf16(P, X):
+    """Logits with the bf16 operand rounding of the matrix-core inference (see om_mlp_forward_bf16)."""
+    X = _f64(X)
+    z = np.zeros(X.shape[0])
+    load().om_mlp_forward_bf16(_d(_f64(P)), _d(X), X.shape[0], _d(z))
     return z
 
 

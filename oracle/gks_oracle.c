@@ -1259,10 +1259,10 @@ void om_mass(const om_mesh *m, const double *W, double *mass)
 /* ----------------------------------------------------------------------------------------- */
 /* learned smoothness indicator: features and the multilayer perceptron                       */
 
-#define MLP_IN 40
+#define MLP_IN 44
 #define MLP_H 64
 
-void om_features(const om_mesh *m, const double *W, const double *gW, double *X)
+void om_features(const om_mesh *m, double G, const double *W, const double *gW, double *X)
 {
     for (int c = 0; c < m->nt; c++) {
         double q[NS][NV], gq[NS][NV][2];
@@ -1273,6 +1273,7 @@ void om_features(const om_mesh *m, const double *W, const double *gW, double *X)
         double h = sqrt(2.0 * m->area[c]);
         double *x = X + (size_t)c * MLP_IN;
         const int fields[2] = {3, 0}; /* eta1, h2 */
+        const double thick[2] = {W[3 * m->nt + c], W[c]}; /* h1, h2 of the cell */
         for (int f = 0; f < 2; f++) {
             int v = fields[f];
             double Q0 = q[0][v], s = 0;
@@ -1281,9 +1282,16 @@ void om_features(const om_mesh *m, const double *W, const double *gW, double *X)
             for (int l = 1; l < NS; l++) x[17 * f + l - 1] = (q[l][v] - Q0) / s;
             for (int l = 0; l < 4; l++)
                 for (int d = 0; d < 2; d++) x[17 * f + 9 + 2 * l + d] = h * gq[l][v][d] / s;
+            /* size of the variation against the layer thickness */
+            x[34 + f] = log10(s / thick[f]) / 4.0;
+            /* momentum variation of the same layer against h sqrt(G h) */
+            double cm = thick[f] * sqrt(G * thick[f]), sm = 0;
+            for (int l = 1; l < NS; l++)
+                for (int k = 1; k <= 2; k++) sm = fmax(sm, fabs(q[l][v + k] - q[0][v + k]));
+            x[36 + f] = log10((sm + 1e-12 * cm) / cm) / 4.0;
         }
-        for (int l = 1; l <= 3; l++) x[34 + l - 1] = m->area[m->st_cell[NS * c + l]] / m->area[c];
-        for (int k = 0; k < 3; k++) x[37 + k] = m->e_len[m->c_edge[3 * c + k]] / h;
+        for (int l = 1; l <= 3; l++) x[38 + l - 1] = m->area[m->st_cell[NS * c + l]] / m->area[c];
+        for (int k = 0; k < 3; k++) x[41 + k] = m->e_len[m->c_edge[3 * c + k]] / h;
     }
 }
 
@@ -1313,6 +1321,39 @@ void om_mlp_forward(const double *P, const double *X, int B, double *z)
         mlp_hidden(P, X + (size_t)s * MLP_IN, a1, h1, a2, h2);
         double zz = b3[0];
         for (int j = 0; j < MLP_H; j++) zz += h2[j] * w3[j];
+        z[s] = zz;
+    }
+}
+
+/* v rounded to single precision, then to 8 significant bits (bfloat16), ties to even */
+static double round_bf16(double v)
+{
+    float f = (float)v;
+    if (f == 0.0f || !isfinite(f)) return (double)f;
+    int e;
+    double m = frexp((double)f, &e); /* f = m 2^e, 0.5 <= |m| < 1 */
+    return ldexp(nearbyint(ldexp(m, 8)), e - 8);
+}
+
+void om_mlp_forward_bf16(const double *P, const double *X, int B, double *z)
+{
+    const double *W1 = P, *b1 = W1 + MLP_IN * MLP_H, *W2 = b1 + MLP_H, *b2 = W2 + MLP_H * MLP_H;
+    const double *w3 = b2 + MLP_H, *b3 = w3 + MLP_H;
+    for (int s = 0; s < B; s++) {
+        const double *x = X + (size_t)s * MLP_IN;
+        double h1[MLP_H], zz = b3[0];
+        for (int j = 0; j < MLP_H; j++) {
+            double a = 0;
+            for (int i = 0; i < MLP_IN; i++) a += round_bf16(x[i]) * round_bf16(W1[i * MLP_H + j]);
+            a = (double)(float)a + b1[j];
+            h1[j] = round_bf16(a > 0 ? a : 0);
+        }
+        for (int j = 0; j < MLP_H; j++) {
+            double a = 0;
+            for (int i = 0; i < MLP_H; i++) a += h1[i] * round_bf16(W2[i * MLP_H + j]);
+            a += b2[j];
+            zz += (a > 0 ? a : 0) * w3[j];
+        }
         z[s] = zz;
     }
 }

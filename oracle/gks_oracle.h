@@ -82,16 +82,24 @@ void om_mass(const om_mesh *m, const double *W, double *mass);
 void om_cell_geometry(const om_mesh *m, double *area, double *cx, double *cy);
 
 /* Learned smoothness indicator (reference for the GPU kernels).
- * Features X[T][40] of each cell: for the interface level eta1 = h1 + B, then h2: the 9 stencil
+ * Features X[T][44] of each cell: for the interface level eta1 = h1 + B, then h2: the 9 stencil
  * differences (Q_l - Q_0)/s and the 8 scaled gradients h grad Q_l / s of the cell and its face
- * neighbours, s = max_l |Q_l - Q_0| + 1e-12 |Q_0|; then the face neighbours' area ratios and the
- * cell's edge lengths over h = sqrt(2 |Omega|).
- * MLP 40 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters P[6849] = W1[40][64], b1[64],
+ * neighbours, s = max_l |Q_l - Q_0| + 1e-12 |Q_0| (17 each, X[0..33]); then log10(s / h)/4 with h
+ * the layer's thickness in the cell (eta1: h1, then h2; X[34], X[35]); then for the lower and the
+ * upper layer log10((sm + 1e-12 c) / c)/4 with sm the largest stencil difference of the layer's two
+ * momentum components and c = h sqrt(G h) (X[36], X[37]); then the face neighbours' area ratios
+ * (X[38..40]) and the cell's edge lengths over h = sqrt(2 |Omega|) (X[41..43]).
+ * MLP 44 -> 64 -> 64 -> 1 with ReLU hidden layers; parameters P[7105] = W1[44][64], b1[64],
  * W2[64][64], b2[64], w3[64], b3.  Loss: mean over the batch of softplus(z) - y z (logistic loss
  * on the logit z). */
-void om_features(const om_mesh *m, const double *W, const double *gW, double *X);
+void om_features(const om_mesh *m, double G, const double *W, const double *gW, double *X);
 void om_mlp_forward(const double *P, const double *X, int B, double *z);
 double om_mlp_grad(const double *P, const double *X, const double *y, int B, double *grad);
+/* The forward pass with the operand rounding of a bfloat16 matrix-core evaluation: the inputs,
+ * W1, the first hidden layer's activations and W2 rounded to single precision and then to 8
+ * significant bits (ties to even) before their products; sums, biases and the output layer in
+ * double.  Used where a decision (logit > threshold) must be taken in the kernel's precision. */
+void om_mlp_forward_bf16(const double *P, const double *X, int B, double *z);
 
 #ifdef __cplusplus
 }

@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
 
 #include "../../include/gks.h"
+#include "gks_indicator.h"
 #include "gks_kernels.h"
 #include "mesh_setup.h"
 
@@ -73,8 +75,17 @@ struct gks_state {
     double *Wc = nullptr, *rech = nullptr, *hmid = nullptr, *gP1 = nullptr, *eoh = nullptr;
     void *Gc = nullptr, *recm = nullptr, *r0 = nullptr, *eom = nullptr;
     double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
-    uint8_t *smooth = nullptr;
+    uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
     int nparts = 0;
+    // learned indicator: parameters, bf16 copies of the weight matrices, threshold
+    bool ind_on = false;
+    float ind_thr = 0;
+    float *ind_P = nullptr, *ind_logit = nullptr;
+    short *ind_W1b = nullptr, *ind_W2b = nullptr;
+    // second reconstruction (linear) for labels
+    double *lab_rech = nullptr;
+    void *lab_recm = nullptr, *lab_r0 = nullptr;
+    uint8_t *lab_y = nullptr;
     int half = 0;  // 1 between stage 0 and stage 1: the latest state is W^{n+1/2}
     std::vector<void *> owned;
     // graph of one full step, replayed by gks_batch_step
@@ -136,9 +147,15 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         timed(s, st, GKS_KERNEL_GHOST, [&] {
             hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Whin, Wmin, gWin);
         });
+    if (s->ind_on)
+        timed(s, st, GKS_KERNEL_INDICATOR, [&] {
+            hipLaunchKernelGGL(gks::k_indicator<R>, dim3(blocks(m.T, 32 * gks::IND_WAVES)), dim3(64 * gks::IND_WAVES),
+                               0, st, m, s->p.G, Whin, Wmin, gWin, s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr,
+                               s->smooth, (float *)nullptr);
+        });
     timed(s, st, GKS_KERNEL_RECON, [&] {
         hipLaunchKernelGGL(gks::k_recon<R>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Whin,
-                           Wmin, gWin, s->smooth, s->rech, (R *)s->recm, (R *)s->r0);
+                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, s->rech, (R *)s->recm, (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
         hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rech,
@@ -230,6 +247,11 @@ gks_status upload_mesh(gks_mesh *m)
     d.nbc = nbc;
     d.en = en;
     d.egB = egB;
+    {
+        const void *ig = nullptr;
+        if (e == hipSuccess) e = upload_f32(h.igeo, &ig, o);
+        d.igeo = static_cast<const float *>(ig);
+    }
     if (h.S > 1) {
         up(h.cscen, &d.cscen);
         up(h.escen, &d.escen);
@@ -663,3 +685,442 @@ extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *
     HIP_OK(hipMemcpy(dst, src, (size_t)need, hipMemcpyDeviceToHost));
     return GKS_OK;
 }
+
+// ---------------------------------------------------------------------------------------------
+// learned smoothness indicator and its trainer
+
+namespace {
+
+gks_status state_alloc(gks_state *s, void **p, size_t bytes)
+{
+    if (*p) return GKS_OK;
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 8));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(GKS_ENOMEM, std::string("indicator allocation: ") + hipGetErrorString(e));
+    }
+    s->owned.push_back(*p);
+    return GKS_OK;
+}
+
+// refresh the ghost cells of the latest state (they are otherwise refreshed at the start of a stage)
+template <typename R>
+void ghost_latest(gks_state *s, int b)
+{
+    const gks::MeshDev &m = s->md;
+    if (m.NG > 0)
+        hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, 256)), dim3(256), 0, s->stream, m, s->Wh[b],
+                           (R *)s->Wm[b], (R *)s->gW[b]);
+}
+
+template <typename R>
+void launch_features(gks_state *s, float *X)
+{
+    const int b = s->half ? 1 : 0;
+    ghost_latest<R>(s, b);
+    hipLaunchKernelGGL(gks::k_features<R>, dim3(blocks(s->md.T, 256)), dim3(256), 0, s->stream, s->md, s->p.G,
+                       s->Wh[b], (const R *)s->Wm[b], (const R *)s->gW[b], X);
+}
+
+template <typename R>
+void launch_labels(gks_state *s, double tol)
+{
+    const gks::MeshDev &m = s->md;
+    const int b = s->half ? 1 : 0;
+    ghost_latest<R>(s, b);
+    gks::Phys pn = s->p, pl = s->p;
+    pn.linear = 0;
+    pl.linear = 1;
+    const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
+    hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, s->rech, (R *)s->recm, (R *)s->r0);
+    hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, s->lab_rech, (R *)s->lab_recm, (R *)s->lab_r0);
+    hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
+                       s->rech, (const R *)s->recm, s->lab_rech, (const R *)s->lab_recm, s->lab_y);
+}
+
+gks_status labels_any(gks_state *s, double tol)
+{
+    if (!(tol >= 0) || !std::isfinite(tol)) return fail(GKS_EINVAL, "label tolerance must be finite and >= 0");
+    const size_t T = (size_t)s->md.T, rs = s->prec == GKS_FP64 ? 8 : 4;
+    gks_status r = state_alloc(s, (void **)&s->lab_rech, 12 * T * 8);
+    if (r == GKS_OK) r = state_alloc(s, &s->lab_recm, 96 * T * rs);
+    if (r == GKS_OK) r = state_alloc(s, &s->lab_r0, 2 * T * rs);
+    if (r == GKS_OK) r = state_alloc(s, (void **)&s->lab_y, T);
+    if (r != GKS_OK) return r;
+    if (s->prec == GKS_FP64)
+        launch_labels<double>(s, tol);
+    else
+        launch_labels<float>(s, tol);
+    HIP_OK(hipGetLastError());
+    return GKS_OK;
+}
+
+void drop_graph(gks_state *s)
+{
+    if (s->gstream) (void)hipStreamSynchronize(s->gstream);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+}
+
+// splitmix64 (Steele, Lea & Flood, "Fast splittable pseudorandom number generators", 2014)
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+}  // namespace
+
+struct gks_trainer {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int64_t cap = 0, n = 0, npos = 0;
+    int32_t maxB = 0;
+    int64_t adam_t = 0;
+    float *X = nullptr, *Y = nullptr, *logit = nullptr;
+    int32_t *perm = nullptr;
+    float *P = nullptr, *g = nullptr, *mo = nullptr, *ve = nullptr;
+    float *H1 = nullptr, *H2 = nullptr, *D1 = nullptr, *D2 = nullptr, *DZ = nullptr, *L = nullptr, *loss = nullptr;
+    short *W1b = nullptr, *W2b = nullptr;
+    std::vector<void *> owned;
+};
+
+namespace {
+
+// forward, back-propagation and weight gradients of the minibatch tr->perm[off .. off + B)
+void train_grad(gks_trainer *tr, int64_t off, int B, float *loss_out)
+{
+    const int32_t *idx = tr->perm + off;
+    hipLaunchKernelGGL(gks::k_mlp_forward_delta, dim3(blocks(B, gks::TRAIN_BLOCK)), dim3(gks::TRAIN_BLOCK), 0,
+                       tr->stream, tr->P, tr->X, tr->Y, idx, B, tr->H1, tr->H2, tr->D1, tr->D2, tr->DZ, tr->L);
+    hipLaunchKernelGGL(gks::k_mlp_weight_grad, dim3(blocks(gks::MLP_NP, 64)), dim3(64), 0, tr->stream, tr->X, idx, B,
+                       tr->H1, tr->H2, tr->D1, tr->D2, tr->DZ, tr->g);
+    hipLaunchKernelGGL(gks::k_mean, dim3(1), dim3(256), 0, tr->stream, tr->L, B, loss_out);
+}
+
+gks_status trainer_logits(gks_trainer *tr)
+{
+    hipLaunchKernelGGL(gks::k_weights_bf16, dim3(blocks(gks::MLP_H * gks::MLP_H, 256)), dim3(256), 0, tr->stream, tr->P,
+                       tr->W1b, tr->W2b);
+    if (tr->n > 0)
+        hipLaunchKernelGGL(gks::k_mlp_infer, dim3(blocks(tr->n, 32 * gks::IND_WAVES)), dim3(64 * gks::IND_WAVES), 0,
+                           tr->stream, tr->X, tr->n, tr->W1b, tr->W2b, tr->P, tr->logit);
+    HIP_OK(hipGetLastError());
+    return GKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gks_status gks_indicator_set(gks_state *s, const float *params, float threshold)
+{
+    if (!s) return fail(GKS_EINVAL, "null state");
+    if (!params) {
+        if (s->ind_on) drop_graph(s);
+        s->ind_on = false;
+        return GKS_OK;
+    }
+    if (!std::isfinite(threshold)) return fail(GKS_EINVAL, "threshold must be finite");
+    for (int i = 0; i < gks::MLP_NP; i++)
+        if (!std::isfinite(params[i])) return fail(GKS_ENONFINITE, "non-finite indicator parameter");
+    const size_t T = (size_t)s->md.T;
+    gks_status r = state_alloc(s, (void **)&s->ind_P, gks::MLP_NP * sizeof(float));
+    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W1b, gks::MLP_K * gks::MLP_H * sizeof(short));
+    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W2b, gks::MLP_H * gks::MLP_H * sizeof(short));
+    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_logit, T * sizeof(float));
+    if (r == GKS_OK) r = state_alloc(s, (void **)&s->smooth, T);
+    if (r != GKS_OK) return r;
+    // the captured graph (if any) holds the launches without the indicator
+    drop_graph(s);
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(s->ind_P, params, gks::MLP_NP * sizeof(float), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(gks::k_weights_bf16, dim3(blocks(gks::MLP_H * gks::MLP_H, 256)), dim3(256), 0, s->stream,
+                       s->ind_P, s->ind_W1b, s->ind_W2b);
+    HIP_OK(hipGetLastError());
+    s->ind_thr = threshold;
+    s->ind_on = true;
+    return GKS_OK;
+}
+
+gks_status gks_indicator_eval(gks_state *s, float *logits, uint8_t *mask, int64_t *n_skip)
+{
+    if (!s) return fail(GKS_EINVAL, "null state");
+    if (!s->ind_on) return fail(GKS_EINVAL, "the indicator is off");
+    const gks::MeshDev &m = s->md;
+    const int b = s->half ? 1 : 0;
+    if (s->prec == GKS_FP64) {
+        ghost_latest<double>(s, b);
+        hipLaunchKernelGGL(gks::k_indicator<double>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
+                           dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const double *)s->Wm[b],
+                           (const double *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
+                           s->ind_logit);
+    } else {
+        ghost_latest<float>(s, b);
+        hipLaunchKernelGGL(gks::k_indicator<float>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
+                           dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const float *)s->Wm[b],
+                           (const float *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
+                           s->ind_logit);
+    }
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s->stream));
+    const size_t T = (size_t)m.T;
+    if (logits) HIP_OK(hipMemcpy(logits, s->ind_logit, T * sizeof(float), hipMemcpyDeviceToHost));
+    if (mask || n_skip) {
+        std::vector<uint8_t> mk(T);
+        HIP_OK(hipMemcpy(mk.data(), s->smooth, T, hipMemcpyDeviceToHost));
+        if (mask) std::memcpy(mask, mk.data(), T);
+        if (n_skip) {
+            int64_t k = 0;
+            for (uint8_t v : mk) k += v;
+            *n_skip = k;
+        }
+    }
+    return GKS_OK;
+}
+
+gks_status gks_state_features(gks_state *s, float *X)
+{
+    if (!s || !X) return fail(GKS_EINVAL, "null argument");
+    const size_t T = (size_t)s->md.T;
+    float *d = nullptr;
+    HIP_OK(hipMalloc((void **)&d, T * gks::MLP_IN * sizeof(float)));
+    if (s->prec == GKS_FP64)
+        launch_features<double>(s, d);
+    else
+        launch_features<float>(s, d);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(X, d, T * gks::MLP_IN * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(GKS_EDEVICE, std::string("features: ") + hipGetErrorString(e));
+    return GKS_OK;
+}
+
+gks_status gks_state_labels(gks_state *s, double tol, uint8_t *y)
+{
+    if (!s || !y) return fail(GKS_EINVAL, "null argument");
+    gks_status r = labels_any(s, tol);
+    if (r != GKS_OK) return r;
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(y, s->lab_y, (size_t)s->md.T, hipMemcpyDeviceToHost));
+    return GKS_OK;
+}
+
+gks_status gks_trainer_create(int64_t capacity, int32_t max_batch, const float *params0, void *stream,
+                              gks_trainer **out)
+{
+    if (!out || !params0 || capacity <= 0 || max_batch <= 0 || capacity > ((int64_t)1 << 31) - 1)
+        return fail(GKS_EINVAL, "bad trainer arguments");
+    *out = nullptr;
+    for (int i = 0; i < gks::MLP_NP; i++)
+        if (!std::isfinite(params0[i])) return fail(GKS_ENONFINITE, "non-finite initial parameter");
+    gks_trainer *t = new gks_trainer();
+    t->stream = (hipStream_t)stream;
+    t->cap = capacity;
+    t->maxB = max_batch;
+    if (hipGetDevice(&t->device) != hipSuccess) {
+        delete t;
+        return fail(GKS_EDEVICE, "no HIP device");
+    }
+    const size_t C = (size_t)capacity, B = (size_t)max_batch, NP = gks::MLP_NP;
+    struct Buf {
+        void **p;
+        size_t bytes;
+    } bufs[] = {{(void **)&t->X, C * gks::MLP_IN * 4}, {(void **)&t->Y, C * 4}, {(void **)&t->logit, C * 4},
+                {(void **)&t->perm, C * 4}, {(void **)&t->P, NP * 4}, {(void **)&t->g, NP * 4},
+                {(void **)&t->mo, NP * 4}, {(void **)&t->ve, NP * 4}, {(void **)&t->H1, B * gks::MLP_H * 4},
+                {(void **)&t->H2, B * 64 * 4}, {(void **)&t->D1, B * 64 * 4}, {(void **)&t->D2, B * 64 * 4},
+                {(void **)&t->DZ, B * 4}, {(void **)&t->L, B * 4}, {(void **)&t->loss, (C / 1 + 1) * 4},
+                {(void **)&t->W1b, (size_t)gks::MLP_K * gks::MLP_H * 2},
+                {(void **)&t->W2b, (size_t)gks::MLP_H * gks::MLP_H * 2}};
+    for (auto &b : bufs) {
+        hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
+        if (e != hipSuccess) {
+            gks_trainer_destroy(t);
+            return fail(GKS_ENOMEM, std::string("trainer allocation: ") + hipGetErrorString(e));
+        }
+        t->owned.push_back(*b.p);
+    }
+    std::vector<float> zero(NP, 0.f);
+    hipError_t e = hipMemcpy(t->P, params0, NP * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t->mo, zero.data(), NP * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t->ve, zero.data(), NP * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        gks_trainer_destroy(t);
+        return fail(GKS_EDEVICE, std::string("trainer upload: ") + hipGetErrorString(e));
+    }
+    *out = t;
+    return GKS_OK;
+}
+
+void gks_trainer_destroy(gks_trainer *t)
+{
+    if (!t) return;
+    (void)hipStreamSynchronize(t->stream);
+    for (void *p : t->owned) (void)hipFree(p);
+    delete t;
+}
+
+gks_status gks_trainer_add(gks_trainer *t, const float *X, const uint8_t *y, int64_t n)
+{
+    if (!t || n < 0 || (n > 0 && (!X || !y))) return fail(GKS_EINVAL, "bad sample arguments");
+    if (t->n + n > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
+    std::vector<float> yf((size_t)n);
+    int64_t pos = 0;
+    for (int64_t i = 0; i < n; i++) {
+        if (y[i] > 1) return fail(GKS_EINVAL, "labels must be 0 or 1");
+        yf[i] = (float)y[i];
+        pos += y[i];
+    }
+    for (int64_t i = 0; i < n * gks::MLP_IN; i++)
+        if (!std::isfinite(X[i])) return fail(GKS_ENONFINITE, "non-finite feature");
+    HIP_OK(hipStreamSynchronize(t->stream));
+    HIP_OK(hipMemcpy(t->X + t->n * gks::MLP_IN, X, (size_t)n * gks::MLP_IN * 4, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(t->Y + t->n, yf.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    t->n += n;
+    t->npos += pos;
+    return GKS_OK;
+}
+
+gks_status gks_trainer_add_state(gks_trainer *t, gks_state *s, double tol, int64_t *n_added)
+{
+    if (!t || !s) return fail(GKS_EINVAL, "null argument");
+    if (s->mesh->device != t->device) return fail(GKS_EINVAL, "state and trainer live on different devices");
+    const int64_t T = s->md.T;
+    if (t->n + T > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
+    HIP_OK(hipStreamSynchronize(t->stream));
+    if (s->prec == GKS_FP64)
+        launch_features<double>(s, t->X + t->n * gks::MLP_IN);
+    else
+        launch_features<float>(s, t->X + t->n * gks::MLP_IN);
+    gks_status r = labels_any(s, tol);
+    if (r != GKS_OK) return r;
+    hipLaunchKernelGGL(gks::k_u8_to_f32, dim3(blocks(T, 256)), dim3(256), 0, s->stream, s->lab_y, T, t->Y + t->n);
+    HIP_OK(hipGetLastError());
+    std::vector<uint8_t> y((size_t)T);
+    HIP_OK(hipStreamSynchronize(s->stream));
+    HIP_OK(hipMemcpy(y.data(), s->lab_y, (size_t)T, hipMemcpyDeviceToHost));
+    int64_t pos = 0;
+    for (uint8_t v : y) pos += v;
+    t->n += T;
+    t->npos += pos;
+    if (n_added) *n_added = T;
+    return GKS_OK;
+}
+
+gks_status gks_trainer_info(const gks_trainer *t, int64_t *n_samples, int64_t *n_positive)
+{
+    if (!t) return fail(GKS_EINVAL, "null trainer");
+    if (n_samples) *n_samples = t->n;
+    if (n_positive) *n_positive = t->npos;
+    return GKS_OK;
+}
+
+gks_status gks_trainer_grad(gks_trainer *t, const int32_t *idx, int32_t B, float *loss, float *grad)
+{
+    if (!t || !idx || B < 1 || B > t->maxB) return fail(GKS_EINVAL, "bad gradient arguments");
+    for (int32_t i = 0; i < B; i++)
+        if (idx[i] < 0 || idx[i] >= t->n) return fail(GKS_EINVAL, "sample index out of range");
+    HIP_OK(hipStreamSynchronize(t->stream));
+    HIP_OK(hipMemcpy(t->perm, idx, (size_t)B * 4, hipMemcpyHostToDevice));
+    train_grad(t, 0, B, t->loss);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(t->stream));
+    if (loss) HIP_OK(hipMemcpy(loss, t->loss, 4, hipMemcpyDeviceToHost));
+    if (grad) HIP_OK(hipMemcpy(grad, t->g, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
+    return GKS_OK;
+}
+
+gks_status gks_trainer_fit(gks_trainer *t, int32_t epochs, int32_t batch, float lr, uint64_t seed,
+                           float *epoch_loss)
+{
+    if (!t || epochs < 0 || batch < 1 || batch > t->maxB || !(lr > 0) || !std::isfinite(lr))
+        return fail(GKS_EINVAL, "bad training arguments");
+    if (t->n == 0) return fail(GKS_EINVAL, "no samples");
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const int64_t n = t->n, nb = (n + batch - 1) / batch;
+    std::vector<int32_t> perm((size_t)n);
+    std::vector<float> bl((size_t)nb);
+    uint64_t state = seed;
+    for (int32_t ep = 0; ep < epochs; ep++) {
+        for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
+        for (int64_t i = n - 1; i > 0; i--) {
+            const int64_t j = (int64_t)(splitmix64(state) % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(t->perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        for (int64_t k = 0; k < nb; k++) {
+            const int64_t off = k * batch;
+            const int B = (int)std::min<int64_t>(batch, n - off);
+            train_grad(t, off, B, t->loss + k);
+            t->adam_t++;
+            const float c1 = 1.f - std::pow(b1, (float)t->adam_t), c2 = 1.f - std::pow(b2, (float)t->adam_t);
+            hipLaunchKernelGGL(gks::k_adam, dim3(blocks(gks::MLP_NP, 256)), dim3(256), 0, t->stream, t->P, t->g, t->mo,
+                               t->ve, lr, b1, b2, eps, c1, c2);
+        }
+        HIP_OK(hipGetLastError());
+        if (epoch_loss) {
+            HIP_OK(hipStreamSynchronize(t->stream));
+            HIP_OK(hipMemcpy(bl.data(), t->loss, (size_t)nb * 4, hipMemcpyDeviceToHost));
+            double acc = 0;
+            for (float v : bl) acc += v;
+            epoch_loss[ep] = (float)(acc / (double)nb);
+        }
+    }
+    HIP_OK(hipStreamSynchronize(t->stream));
+    return GKS_OK;
+}
+
+gks_status gks_trainer_params(const gks_trainer *t, float *params)
+{
+    if (!t || !params) return fail(GKS_EINVAL, "null argument");
+    HIP_OK(hipStreamSynchronize(t->stream));
+    HIP_OK(hipMemcpy(params, t->P, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
+    return GKS_OK;
+}
+
+gks_status gks_trainer_logits(gks_trainer *t, float *logits)
+{
+    if (!t || !logits) return fail(GKS_EINVAL, "null argument");
+    gks_status r = trainer_logits(t);
+    if (r != GKS_OK) return r;
+    HIP_OK(hipStreamSynchronize(t->stream));
+    HIP_OK(hipMemcpy(logits, t->logit, (size_t)t->n * 4, hipMemcpyDeviceToHost));
+    return GKS_OK;
+}
+
+gks_status gks_trainer_threshold(gks_trainer *t, double max_false_skip, float *threshold)
+{
+    if (!t || !threshold || !(max_false_skip >= 0) || !(max_false_skip <= 1))
+        return fail(GKS_EINVAL, "bad threshold arguments");
+    if (t->n == 0) return fail(GKS_EINVAL, "no samples");
+    gks_status r = trainer_logits(t);
+    if (r != GKS_OK) return r;
+    const size_t n = (size_t)t->n;
+    std::vector<float> z(n), y(n);
+    HIP_OK(hipStreamSynchronize(t->stream));
+    HIP_OK(hipMemcpy(z.data(), t->logit, n * 4, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(y.data(), t->Y, n * 4, hipMemcpyDeviceToHost));
+    std::vector<float> neg;
+    for (size_t i = 0; i < n; i++)
+        if (y[i] < 0.5f) neg.push_back(z[i]);
+    const size_t allowed = (size_t)std::floor(max_false_skip * (double)n);
+    if (allowed >= neg.size()) {
+        *threshold = -FLT_MAX;
+        return GKS_OK;
+    }
+    // skip iff z > threshold: at most `allowed` label-0 logits may lie above it
+    std::sort(neg.begin(), neg.end(), [](float a, float b) { return a > b; });
+    *threshold = neg[allowed];
+    return GKS_OK;
+}
+
+}  // extern "C"

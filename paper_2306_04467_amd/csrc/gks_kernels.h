@@ -28,6 +28,7 @@ struct MeshDev {
     const double *area, *Bbar, *gB, *fl, *gg, *eBgp, *gR, *sdxmin;
     // tables in the bulk precision (double or float copies)
     const void *M, *hs, *vtx, *nbc, *en, *egB;
+    const float *igeo;              // [6][T] indicator geometry
     const int32_t *cedge, *sten, *eL, *eR, *eslot, *gsrc;
     const int32_t *cscen, *escen;   // scenario of each cell / edge, nullptr when S == 1
     const int64_t *scell;           // [S + 1] first cell of each scenario

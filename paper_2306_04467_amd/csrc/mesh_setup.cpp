@@ -465,6 +465,15 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
         }
     m.ng = (int64_t)gsrc.size();
     m.gsrc = gsrc;
+    m.igeo.assign(6 * nt, 0);
+    for (int64_t c = 0; c < nt; c++) {
+        for (int l = 0; l < 3; l++) {
+            const int32_t i = m.sten[l * nt + c];
+            const int64_t src = i < nt ? i : m.gsrc[i - nt];
+            m.igeo[l * nt + c] = m.area[src] / m.area[c];
+        }
+        for (int k = 0; k < 3; k++) m.igeo[(3 + k) * nt + c] = std::fabs(m.fl[k * nt + c]) * m.area[c] / m.hs[c];
+    }
     m.gR.assign(4 * std::max<int64_t>(m.ng, 1), 0);
     for (int64_t g = 0; g < m.ng; g++)
         for (int i = 0; i < 4; i++) m.gR[i * m.ng + g] = gR[4 * g + i];
@@ -515,6 +524,7 @@ HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts)
     cells(o.Bbar, 1, &HostMesh::Bbar);
     cells(o.gB, 2, &HostMesh::gB);
     cells(o.M, 153, &HostMesh::M);
+    cells(o.igeo, 6, &HostMesh::igeo);
     edges(o.en, 2, &HostMesh::en);
     edges(o.eBgp, 2, &HostMesh::eBgp);
     edges(o.egB, 2, &HostMesh::egB);

@@ -24,6 +24,8 @@ struct HostMesh {
     std::vector<int32_t> cedge;      // [3][T] edge of local edge k: e (cell is left) or ~e (right)
     std::vector<int32_t> sten;       // [9][T] stencil cells (face neighbours, then second ring)
     std::vector<double> M;           // [153][T] least-squares operator, row k*17+r
+    std::vector<double> igeo;        // [6][T] indicator geometry: area ratios of the 3 face
+                                     // neighbours, then the 3 edge lengths over hs
     // edges
     std::vector<int32_t> eL, eR;     // [E] left / right cell, eR = -1 on walls
     std::vector<int32_t> eslot;      // [E] local edge index in L | (in R << 2)

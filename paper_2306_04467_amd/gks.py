@@ -19,6 +19,8 @@ _dp = ctypes.POINTER(ctypes.c_double)
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _vp = ctypes.c_void_p
+_fp = ctypes.POINTER(ctypes.c_float)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
 
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_EMESH, GKS_ENONFINITE, GKS_EUNSUPPORTED = range(7)
 GKS_BC_WALL, GKS_BC_PERIODIC = 0, 1
@@ -29,10 +31,15 @@ PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_info", "gks_mesh_scenario",
            "gks_state_init", "gks_state_destroy", "gks_stage", "gks_step", "gks_batch_step", "gks_state_read",
            "gks_state_time", "gks_state_mass", "gks_state_buffer", "gks_profile", "gks_profile_read",
-           "gks_last_error")
+           "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
+           "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
+           "gks_trainer_info", "gks_trainer_grad", "gks_trainer_fit", "gks_trainer_params", "gks_trainer_logits",
+           "gks_trainer_threshold", "gks_last_error")
+_VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
+MLP_PARAMS, MLP_FEATURES = 7105, 44
 BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 4, True),
            "eom": (4, 22, False)}
-KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt")
+KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt", "indicator")
 
 
 class GksError(RuntimeError):
@@ -53,6 +60,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    # stream handles come from torch: load torch's HIP runtime first so that the library binds to
+    # the same one
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(LIB_PATH)
     lib.gks_last_error.restype = ctypes.c_char_p
     lib.gks_mesh_create.argtypes = [_dp, ctypes.c_int64, _i32p, ctypes.c_int64, _dp, ctypes.c_int32, _dp,
@@ -74,8 +85,23 @@ def load():
     lib.gks_state_buffer.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64]
     lib.gks_profile.argtypes = [_vp, ctypes.c_int32]
     lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, _i64p]
+    lib.gks_indicator_set.argtypes = [_vp, _fp, ctypes.c_float]
+    lib.gks_indicator_eval.argtypes = [_vp, _fp, _u8p, _i64p]
+    lib.gks_state_features.argtypes = [_vp, _fp]
+    lib.gks_state_labels.argtypes = [_vp, ctypes.c_double, _u8p]
+    lib.gks_trainer_create.argtypes = [ctypes.c_int64, ctypes.c_int32, _fp, _vp, ctypes.POINTER(_vp)]
+    lib.gks_trainer_destroy.argtypes = [_vp]
+    lib.gks_trainer_destroy.restype = None
+    lib.gks_trainer_add.argtypes = [_vp, _fp, _u8p, ctypes.c_int64]
+    lib.gks_trainer_add_state.argtypes = [_vp, _vp, ctypes.c_double, _i64p]
+    lib.gks_trainer_info.argtypes = [_vp, _i64p, _i64p]
+    lib.gks_trainer_grad.argtypes = [_vp, _i32p, ctypes.c_int32, _fp, _fp]
+    lib.gks_trainer_fit.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64, _fp]
+    lib.gks_trainer_params.argtypes = [_vp, _fp]
+    lib.gks_trainer_logits.argtypes = [_vp, _fp]
+    lib.gks_trainer_threshold.argtypes = [_vp, ctypes.c_double, _fp]
     for name in SYMBOLS:
-        if name not in ("gks_mesh_destroy", "gks_state_destroy", "gks_last_error"):
+        if name not in _VOID:
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -92,6 +118,18 @@ def _d(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _pf(a):
+    return a.ctypes.data_as(_fp)
+
+
+def _pu8(a):
+    return a.ctypes.data_as(_u8p)
 
 
 def current_stream():
@@ -241,9 +279,105 @@ class State:
             out[name] = (ms.value, n.value)
         return out
 
+    # learned smoothness indicator
+    def indicator(self, params, threshold=0.0):
+        """Switch the indicator on (params [7105]) or off (params None) for later stages."""
+        if params is None:
+            _check(load().gks_indicator_set(self._h, None, 0.0))
+            return
+        self._ind_params = _f32(params)
+        if self._ind_params.size != MLP_PARAMS:
+            raise ValueError(f"{MLP_PARAMS} parameters expected")
+        _check(load().gks_indicator_set(self._h, _pf(self._ind_params), float(threshold)))
+
+    def indicator_eval(self):
+        """(logits [T], mask [T], n_skip) of the latest state."""
+        T = self.mesh.n_tri
+        z = np.zeros(T, dtype=np.float32)
+        m = np.zeros(T, dtype=np.uint8)
+        k = ctypes.c_int64()
+        _check(load().gks_indicator_eval(self._h, _pf(z), _pu8(m), ctypes.byref(k)))
+        return z, m, k.value
+
+    def features(self):
+        X = np.zeros((self.mesh.n_tri, MLP_FEATURES), dtype=np.float32)
+        _check(load().gks_state_features(self._h, _pf(X)))
+        return X
+
+    def labels(self, tol=1e-7):
+        y = np.zeros(self.mesh.n_tri, dtype=np.uint8)
+        _check(load().gks_state_labels(self._h, float(tol), _pu8(y)))
+        return y
+
     def close(self):
         if getattr(self, "_h", None):
             load().gks_state_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Trainer:
+    """Device-resident sample set and parameters of the indicator network (see include/gks.h)."""
+
+    def __init__(self, capacity, params0, max_batch=4096, stream=None):
+        lib = load()
+        p0 = _f32(params0)
+        if p0.size != MLP_PARAMS:
+            raise ValueError(f"{MLP_PARAMS} parameters expected")
+        if stream is None:
+            stream = current_stream()
+        h = _vp()
+        _check(lib.gks_trainer_create(int(capacity), int(max_batch), _pf(p0), stream, ctypes.byref(h)))
+        self._h = h
+
+    def add(self, X, y):
+        X = _f32(X).reshape(-1, MLP_FEATURES)
+        y = np.ascontiguousarray(y, dtype=np.uint8)
+        _check(load().gks_trainer_add(self._h, _pf(X), _pu8(y), X.shape[0]))
+
+    def add_state(self, state, tol=1e-7):
+        n = ctypes.c_int64()
+        _check(load().gks_trainer_add_state(self._h, state._h, float(tol), ctypes.byref(n)))
+        return n.value
+
+    def info(self):
+        n, p = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().gks_trainer_info(self._h, ctypes.byref(n), ctypes.byref(p)))
+        return n.value, p.value
+
+    def grad(self, idx):
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        loss = ctypes.c_float()
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(load().gks_trainer_grad(self._h, idx.ctypes.data_as(_i32p), idx.size, ctypes.byref(loss), _pf(g)))
+        return loss.value, g
+
+    def fit(self, epochs, batch=1024, lr=1e-3, seed=0):
+        out = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        _check(load().gks_trainer_fit(self._h, int(epochs), int(batch), float(lr), ctypes.c_uint64(seed), _pf(out)))
+        return out[:int(epochs)]
+
+    def params(self):
+        P = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(load().gks_trainer_params(self._h, _pf(P)))
+        return P
+
+    def logits(self):
+        n, _ = self.info()
+        z = np.zeros(n, dtype=np.float32)
+        _check(load().gks_trainer_logits(self._h, _pf(z)))
+        return z
+
+    def threshold(self, max_false_skip=1e-4):
+        t = ctypes.c_float()
+        _check(load().gks_trainer_threshold(self._h, float(max_false_skip), ctypes.byref(t)))
+        return t.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gks_trainer_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -54,6 +54,8 @@ hipError_t upload_f32(const std::vector<double> &h, const void **d, std::vector<
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+size_t rec_bytes(int prec) { return prec == GKS_FP64 ? sizeof(gks::GpRec<double>) : sizeof(gks::GpRec<float>); }
+
 }  // namespace
 
 struct gks_mesh {
@@ -72,8 +74,9 @@ struct gks_state {
     hipStream_t stream = nullptr;
     double *Wh[2] = {nullptr, nullptr};
     void *Wm[2] = {nullptr, nullptr}, *gW[2] = {nullptr, nullptr};
-    double *Wc = nullptr, *rech = nullptr, *hmid = nullptr, *gP1 = nullptr, *eoh = nullptr;
-    void *Gc = nullptr, *recm = nullptr, *r0 = nullptr, *eom = nullptr;
+    double *Wc = nullptr, *hmid = nullptr, *gP1 = nullptr;
+    double *eoh = nullptr;
+    void *Gc = nullptr, *rec = nullptr, *r0 = nullptr, *eom = nullptr;  // rec: GpRec[6T]
     double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
     uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
     int nparts = 0;
@@ -83,8 +86,7 @@ struct gks_state {
     float *ind_P = nullptr, *ind_logit = nullptr;
     short *ind_W1b = nullptr, *ind_W2b = nullptr;
     // second reconstruction (linear) for labels
-    double *lab_rech = nullptr;
-    void *lab_recm = nullptr, *lab_r0 = nullptr;
+    void *lab_rec = nullptr, *lab_r0 = nullptr;
     uint8_t *lab_y = nullptr;
     int half = 0;  // 1 between stage 0 and stage 1: the latest state is W^{n+1/2}
     std::vector<void *> owned;
@@ -155,22 +157,22 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         });
     timed(s, st, GKS_KERNEL_RECON, [&] {
         hipLaunchKernelGGL(gks::k_recon<R>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Whin,
-                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, s->rech, (R *)s->recm, (R *)s->r0);
+                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, (gks::GpRec<R> *)s->rec, (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
-        hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p, s->rech,
-                           (const R *)s->recm, s->hmid);
+        hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p,
+                           (const gks::GpRec<R> *)s->rec, s->hmid);
     });
     timed(s, st, GKS_KERNEL_PLANE, [&] {
         hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
-        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p, s->rech,
-                           (const R *)s->recm, (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p,
+                           (const gks::GpRec<R> *)s->rec, (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
-        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage, s->eoh,
-                           (const R *)s->eom, Whin, Wmin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage,
+                           s->eoh, (const R *)s->eom, Whin, Wmin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
     });
 }
 
@@ -436,8 +438,8 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         size_t bytes;
     } bufs[] = {{(void **)&s->Wh[0], 2 * uTG * 8}, {(void **)&s->Wh[1], 2 * uTG * 8}, {&s->Wm[0], 4 * uTG * rs},
                 {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
-                {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {(void **)&s->rech, 12 * uT * 8},
-                {&s->recm, 96 * uT * rs}, {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
+                {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
+                {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
                 {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
                 {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max(s->nparts, 1024) * 8},
                 {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
@@ -666,24 +668,56 @@ gks_status gks_state_mass(const gks_state *s, int32_t scen, double mass[2])
 
 }  // extern "C"
 
+namespace {
+
+// the record arrays repacked into the component-major layouts documented for gks_state_buffer
+template <typename R>
+gks_status read_buffer(const gks_state *s, int32_t which, void *dst)
+{
+    const int64_t T = s->md.T, E = s->md.E;
+    if (which == GKS_BUF_R0) {
+        HIP_OK(hipMemcpy(dst, s->r0, (size_t)(2 * T) * sizeof(R), hipMemcpyDeviceToHost));
+        return GKS_OK;
+    }
+    if (which == GKS_BUF_RECH || which == GKS_BUF_RECM) {
+        std::vector<gks::GpRec<R>> rec((size_t)(6 * T));
+        HIP_OK(hipMemcpy(rec.data(), s->rec, rec.size() * sizeof(gks::GpRec<R>), hipMemcpyDeviceToHost));
+        for (int64_t c = 0; c < T; c++)
+            for (int slot = 0; slot < 6; slot++) {
+                const gks::GpRec<R> &r = rec[6 * c + slot];
+                if (which == GKS_BUF_RECH)
+                    for (int q = 0; q < 2; q++) static_cast<double *>(dst)[(slot * 2 + q) * T + c] = r.h[q];
+                else
+                    for (int q = 0; q < 16; q++) static_cast<R *>(dst)[(slot * 16 + q) * T + c] = r.q[q];
+            }
+        return GKS_OK;
+    }
+    if (which == GKS_BUF_EOH) {
+        HIP_OK(hipMemcpy(dst, s->eoh, (size_t)(4 * E) * 8, hipMemcpyDeviceToHost));
+    } else {
+        HIP_OK(hipMemcpy(dst, s->eom, (size_t)(22 * E) * sizeof(R), hipMemcpyDeviceToHost));
+    }
+    return GKS_OK;
+}
+
+}  // namespace
+
 extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *dst, int64_t bytes)
 {
     if (!s || !dst || which < 0 || which >= GKS_BUF_COUNT) return fail(GKS_EINVAL, "bad buffer query");
     const int64_t T = s->md.T, E = s->md.E;
     const int64_t rs = s->prec == GKS_FP64 ? 8 : 4;
-    const void *src = nullptr;
     int64_t need = 0;
     switch (which) {
-    case GKS_BUF_RECH: src = s->rech; need = 12 * T * 8; break;
-    case GKS_BUF_RECM: src = s->recm; need = 96 * T * rs; break;
-    case GKS_BUF_R0: src = s->r0; need = 2 * T * rs; break;
-    case GKS_BUF_EOH: src = s->eoh; need = 4 * E * 8; break;
-    default: src = s->eom; need = 22 * E * rs; break;
+    case GKS_BUF_RECH: need = 12 * T * 8; break;
+    case GKS_BUF_RECM: need = 96 * T * rs; break;
+    case GKS_BUF_R0: need = 2 * T * rs; break;
+    case GKS_BUF_EOH: need = 4 * E * 8; break;
+    default: need = 22 * E * rs; break;
     }
     if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
     HIP_OK(hipStreamSynchronize(s->stream));
-    HIP_OK(hipMemcpy(dst, src, (size_t)need, hipMemcpyDeviceToHost));
-    return GKS_OK;
+    return s->prec == GKS_FP64 ? read_buffer<double>(s, which, dst) : read_buffer<float>(s, which, dst);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -733,19 +767,18 @@ void launch_labels(gks_state *s, double tol)
     pl.linear = 1;
     const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
     hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, s->rech, (R *)s->recm, (R *)s->r0);
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, (gks::GpRec<R> *)s->rec, (R *)s->r0);
     hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, s->lab_rech, (R *)s->lab_recm, (R *)s->lab_r0);
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, (gks::GpRec<R> *)s->lab_rec, (R *)s->lab_r0);
     hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
-                       s->rech, (const R *)s->recm, s->lab_rech, (const R *)s->lab_recm, s->lab_y);
+                       (const gks::GpRec<R> *)s->rec, (const gks::GpRec<R> *)s->lab_rec, s->lab_y);
 }
 
 gks_status labels_any(gks_state *s, double tol)
 {
     if (!(tol >= 0) || !std::isfinite(tol)) return fail(GKS_EINVAL, "label tolerance must be finite and >= 0");
     const size_t T = (size_t)s->md.T, rs = s->prec == GKS_FP64 ? 8 : 4;
-    gks_status r = state_alloc(s, (void **)&s->lab_rech, 12 * T * 8);
-    if (r == GKS_OK) r = state_alloc(s, &s->lab_recm, 96 * T * rs);
+    gks_status r = state_alloc(s, &s->lab_rec, 6 * T * rec_bytes(s->prec));
     if (r == GKS_OK) r = state_alloc(s, &s->lab_r0, 2 * T * rs);
     if (r == GKS_OK) r = state_alloc(s, (void **)&s->lab_y, T);
     if (r != GKS_OK) return r;

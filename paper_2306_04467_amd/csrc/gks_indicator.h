@@ -270,24 +270,18 @@ __global__ void k_weights_bf16(const float *__restrict__ P, short *__restrict__ 
 
 template <typename R>
 __global__ void k_label(MeshDev m, double G, double tol, const double *__restrict__ Wh,
-                        const double *__restrict__ rech_nl, const R *__restrict__ recm_nl,
-                        const double *__restrict__ rech_li, const R *__restrict__ recm_li, uint8_t *__restrict__ y)
+                        const GpRec<R> *__restrict__ rec_nl, const GpRec<R> *__restrict__ rec_li, uint8_t *__restrict__ y)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
-    const int64_t T = m.T, TG = m.T + m.NG;
+    const int64_t TG = m.T + m.NG;
     const double h2 = Wh[c], h1 = Wh[TG + c] - m.Bbar[c];
     const double sh[2] = {h2, h1}, sm[2] = {h2 * sqrt(G * h2), h1 * sqrt(G * h1)};
     bool ok = true;
     for (int slot = 0; slot < 6; slot++) {
-        for (int q = 0; q < 2; q++) {
-            const int64_t i = (int64_t)(slot * 2 + q) * T + c;
-            ok = ok && fabs(rech_nl[i] - rech_li[i]) <= tol * sh[q];
-        }
-        for (int q = 0; q < 4; q++) {
-            const int64_t i = (int64_t)(slot * 16 + q) * T + c;
-            ok = ok && fabs((double)recm_nl[i] - (double)recm_li[i]) <= tol * sm[q / 2];
-        }
+        const GpRec<R> &a = rec_nl[6 * c + slot], &b = rec_li[6 * c + slot];
+        for (int q = 0; q < 2; q++) ok = ok && fabs(a.h[q] - b.h[q]) <= tol * sh[q];
+        for (int q = 0; q < 4; q++) ok = ok && fabs((double)a.q[q] - (double)b.q[q]) <= tol * sm[q / 2];
     }
     y[c] = ok ? 1 : 0;
 }

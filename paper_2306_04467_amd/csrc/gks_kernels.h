@@ -7,14 +7,16 @@
 // thickness, and every edge sum of the cell update (flux divergence, Green-Gauss derivatives,
 // sources).  What is computed in R there vanishes exactly at rest by left/right symmetry.
 //
-// Data layout (structure of arrays, index = component * stride + cell/edge):
-//   state  Wh[2][TG] (double: h2, eta1), Wm[4][TG] (R: h2U2, h2V2, h1U1, h1V1),
-//          gW[12][TG] (R: x/y gradients of h2, h2U2, h2V2, eta1, h1U1, h1V1), TG = T + NG ghosts
-//   rech   [6 slots][2][T] double: h2 and eta1 at the cell's Gauss points (slot = 2 edge + point)
-//   recm   [6 slots][16][T] R: the four momenta, then the 12 gradients, at the Gauss points
-//   eoh    [4][E] double: per edge, Gauss points averaged: 1/2 G Wb_h^2 (upper, lower), Wb_h (upper,
-//          lower)
-//   eom    [22][E] R: F0 (6, pressure removed), Ft (6), Wb momenta (4), Wbt (6), global frame
+// Data layout:
+//   state  structure of arrays, index = component * stride + cell: Wh[2][TG] (double: h2, eta1),
+//          Wm[4][TG] (R: h2U2, h2V2, h1U1, h1V1), gW[12][TG] (R: x/y gradients of h2, h2U2, h2V2,
+//          eta1, h1U1, h1V1), TG = T + NG ghosts
+//   rec    GpRec[6 T], cell-major: the reconstruction at each cell's six Gauss points, read by
+//          the edge kernels as whole 16-byte words (one or two cache lines per record)
+//   eoh    [4][E] double: per edge, Gauss points averaged: 1/2 G hb^2 (upper, lower), hb (upper,
+//          lower), hb the interface thickness of the evolution
+//   eom    [22][E] R: F0 (6, hydrostatic part removed), Ft (6), interface momenta (4), interface
+//          time derivatives (6), global frame; read by the cell update's gather
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,6 +65,27 @@ __device__ inline int64_t xcd_block()
 // the four momentum components in paper order 1, 2, 4, 5 -> slots 0..3 of Wm
 __device__ inline int mom_slot(int v) { return v < 3 ? v - 1 : v - 2; }
 
+// Gauss-point record of one cell at one of its six Gauss points (slot = 2 * local edge + point),
+// written by the reconstruction and read by the edge kernels.  Records are stored cell-major,
+// rec[6 c + slot], so that an edge kernel reads each side's record as a few 16-byte loads.
+//   h[0] h2, h[1] eta1 = h1 + B (double in both precisions)
+//   q[0..3]  momenta h2U2, h2V2, h1U1, h1V1
+//   q[4 + 2 v], q[5 + 2 v]  x / y derivative of paper component v (v = 0..5, eta1 in place of h1)
+template <typename R>
+struct alignas(16) GpRec {
+    double h[2];
+    R q[16];
+};
+
+// The leading part of a Gauss-point record (thicknesses and momenta), read by itself where the
+// gradients are not needed.
+template <typename R>
+struct alignas(16) GpHead {
+    double h[2];
+    R q[4];
+};
+
+
 // --------------------------------------------------------------------------------------------
 // ghost mirror cells: state of the source cell seen through an orthogonal map
 
@@ -102,19 +125,23 @@ __global__ void k_ghost_fill(MeshDev m, double *__restrict__ Wh, R *__restrict__
 
 constexpr int RECON_CELLS = 32;
 
+// values of one variable at a cell's six Gauss points and its gradient there
 template <typename R>
-__global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
-                                               const R *__restrict__ Wm, const R *__restrict__ gW,
-                                               const uint8_t *__restrict__ smooth, double *__restrict__ rech,
-                                               R *__restrict__ recm, R *__restrict__ r0)
+struct ReconOut {
+    double h[6];  // thicknesses (h2, eta1) in double
+    R val[6];     // momenta
+    R gx[6], gy[6];
+};
+
+// reconstruction of variable v of cell c; Ms points at the cell's least-squares operator in LDS
+// (entry j at Ms[32 j])
+template <typename R>
+__device__ inline void recon_cell(const MeshDev &m, const Phys &p, const double *__restrict__ Wh,
+                                  const R *__restrict__ Wm, const R *__restrict__ gW,
+                                  const uint8_t *__restrict__ smooth, R *__restrict__ r0, int v, bool thick,
+                                  int64_t c, const R *Ms, ReconOut<R> &out)
 {
-    const int lane = threadIdx.x & 31, wv = threadIdx.x >> 5;
-    const int v = (wv == 0) ? 0 : (wv == 1) ? 3 : (wv == 2) ? 1 : (wv == 3) ? 2 : (wv == 4) ? 4 : 5;
-    const bool thick = (v == 0 || v == 3);
-    const int64_t c = xcd_block() * RECON_CELLS + lane;
     const int64_t T = m.T, TG = m.T + m.NG;
-    if (c >= T) return;
-    const R *M = tab<R>(m.M);
     const R hs = tab<R>(m.hs)[c];
     // right-hand side of the least-squares system: average differences, then scaled gradients
     // (differences of thicknesses are taken in FP64 before rounding)
@@ -148,7 +175,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     for (int k = 0; k < 9; k++) {
         R s = 0;
 #pragma unroll
-        for (int r = 0; r < 17; r++) s = fma(M[(int64_t)(k * 17 + r) * T + c], rhs[r], s);
+        for (int r = 0; r < 17; r++) s = fma(Ms[(k * 17 + r) * RECON_CELLS], rhs[r], s);
         a[k] = s;
     }
     // scaled vertices (centroid at the origin) and the cell means of the basis
@@ -272,12 +299,73 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
             const R dev = ratio * P + sbx * x + sby * y;
             const int slot = 2 * k + g;
             if (thick)
-                rech[(int64_t)(slot * 2 + (v == 3)) * T + c] = Q0h + (double)dev;
+                out.h[slot] = Q0h + (double)dev;
             else
-                recm[(int64_t)(slot * 16 + mom_slot(v)) * T + c] = Q0 + dev;
-            recm[(int64_t)(slot * 16 + gbase) * T + c] = (ratio * Px + sbx) * ihs;
-            recm[(int64_t)(slot * 16 + gbase + 1) * T + c] = (ratio * Py + sby) * ihs;
+                out.val[slot] = Q0 + dev;
+            out.gx[slot] = (ratio * Px + sbx) * ihs;
+            out.gy[slot] = (ratio * Py + sby) * ihs;
         }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
+                                               const R *__restrict__ Wm, const R *__restrict__ gW,
+                                               const uint8_t *__restrict__ smooth, GpRec<R> *__restrict__ rec,
+                                               R *__restrict__ r0)
+{
+    // LDS: first the block's 32 least-squares operators, loaded once with coalesced reads and
+    // shared by the six variable threads of each cell; then, in the same space, the block's 32 x 6
+    // Gauss-point records, written out as one contiguous span
+    constexpr int MBYTES = 153 * RECON_CELLS * (int)sizeof(R);
+    constexpr int OBYTES = RECON_CELLS * 6 * (int)sizeof(GpRec<R>);
+    __shared__ uint4 lds[(MBYTES > OBYTES ? MBYTES : OBYTES) / 16];
+    R *Ms = reinterpret_cast<R *>(lds);
+    GpRec<R> *tile = reinterpret_cast<GpRec<R> *>(lds);
+    const int lane = threadIdx.x & 31, wv = threadIdx.x >> 5;
+    const int v = (wv == 0) ? 0 : (wv == 1) ? 3 : (wv == 2) ? 1 : (wv == 3) ? 2 : (wv == 4) ? 4 : 5;
+    const bool thick = (v == 0 || v == 3);
+    const int64_t c0 = xcd_block() * RECON_CELLS, c = c0 + lane;
+    const int64_t T = m.T;
+    const int ncell = T - c0 < RECON_CELLS ? (int)(T - c0) : RECON_CELLS;
+    {
+        // every load of the staging is issued before the first LDS write
+        constexpr int NM = 153 * RECON_CELLS, IT = (NM + 191) / 192;
+        const R *M = tab<R>(m.M);
+        R buf[IT];
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int i = (int)threadIdx.x + 192 * it, j = i / RECON_CELLS, l = i % RECON_CELLS;
+            buf[it] = (i < NM && l < ncell) ? M[(int64_t)j * T + c0 + l] : R(0);
+        }
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int i = (int)threadIdx.x + 192 * it;
+            if (i < NM) Ms[i] = buf[it];
+        }
+    }
+    __syncthreads();
+    ReconOut<R> out;
+    if (lane < ncell) recon_cell<R>(m, p, Wh, Wm, gW, smooth, r0, v, thick, c, Ms + lane, out);
+    __syncthreads();  // the operators are no longer needed: the space becomes the record tile
+    if (lane < ncell) {
+        GpRec<R> *o = tile + 6 * lane;
+        const int gbase = 4 + 2 * v;
+#pragma unroll
+        for (int slot = 0; slot < 6; slot++) {
+            if (thick)
+                o[slot].h[v == 3] = out.h[slot];
+            else
+                o[slot].q[mom_slot(v)] = out.val[slot];
+            o[slot].q[gbase] = out.gx[slot];
+            o[slot].q[gbase + 1] = out.gy[slot];
+        }
+    }
+    __syncthreads();
+    // copy out: 16-byte words of the valid cells' records
+    const int nw = (int)(ncell * 6 * sizeof(GpRec<R>) / 16);
+    const uint4 *src = reinterpret_cast<const uint4 *>(tile);
+    uint4 *dst = reinterpret_cast<uint4 *>(rec + 6 * c0);
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
 }
 
 // --------------------------------------------------------------------------------------------
@@ -286,8 +374,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
 // plane through them must be flat at rest)
 
 template <typename R>
-__global__ void k_hhat(MeshDev m, Phys p, const double *__restrict__ rech, const R *__restrict__ recm,
-                       double *__restrict__ hmid)
+__global__ void k_hhat(MeshDev m, Phys p, const GpRec<R> *__restrict__ rec, double *__restrict__ hmid)
 {
     int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
@@ -301,20 +388,21 @@ __global__ void k_hhat(MeshDev m, Phys p, const double *__restrict__ rech, const
     for (int g = 0; g < 2; g++) {
         const double Bg = m.eBgp[g * E + e];
         const int sL = 2 * kL + g, sR = 2 * kR + 1 - g;
+        const GpHead<R> ql = *reinterpret_cast<const GpHead<R> *>(rec + 6 * (int64_t)L + sL);
+        GpHead<R> qr = ql;
+        if (Rc >= 0) qr = *reinterpret_cast<const GpHead<R> *>(rec + 6 * (int64_t)Rc + sR);
 #pragma unroll
         for (int f = 0; f < 2; f++) {
             // f = 0: eta1 with the lower layer's momentum; f = 1: h2 with the upper layer's
             const int hq = f == 0 ? 1 : 0, mq = f == 0 ? 2 : 0;
-            const double zl = rech[(int64_t)(sL * 2 + hq) * T + L];
+            const double zl = ql.h[hq];
             const double hl = f == 0 ? zl - Bg : zl;
-            const double unl = ((double)recm[(int64_t)(sL * 16 + mq) * T + L] * nx +
-                                (double)recm[(int64_t)(sL * 16 + mq + 1) * T + L] * ny) / hl;
+            const double unl = ((double)ql.q[mq] * nx + (double)ql.q[mq + 1] * ny) / hl;
             double zr, hr, unr;
             if (Rc >= 0) {
-                zr = rech[(int64_t)(sR * 2 + hq) * T + Rc];
+                zr = qr.h[hq];
                 hr = f == 0 ? zr - Bg : zr;
-                unr = ((double)recm[(int64_t)(sR * 16 + mq) * T + Rc] * nx +
-                       (double)recm[(int64_t)(sR * 16 + mq + 1) * T + Rc] * ny) / hr;
+                unr = ((double)qr.q[mq] * nx + (double)qr.q[mq + 1] * ny) / hr;
             } else {  // mirror state across the wall
                 zr = zl;
                 hr = hl;
@@ -595,10 +683,9 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 
 // one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
 template <typename R>
-__global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const double *__restrict__ rech,
-                                              const R *__restrict__ recm, const R *__restrict__ r0,
-                                              const double *__restrict__ gP1, double *__restrict__ eoh,
-                                              R *__restrict__ eom)
+__global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const GpRec<R> *__restrict__ rec,
+                                              const R *__restrict__ r0, const double *__restrict__ gP1,
+                                              double *__restrict__ eoh, R *__restrict__ eom)
 {
     const int64_t idx = xcd_block() * blockDim.x + threadIdx.x;
     const int64_t e = idx >> 2;
@@ -615,8 +702,8 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const double *_
     const R nx = en[e], ny = en[E + e], tx = -ny, ty = nx;
     const double Bg = m.eBgp[g * E + e];
     const R gBx = egB[e], gBy = egB[E + e];
-    const int hq = lay == 0 ? 1 : 0;   // own thickness in rech (eta1 / h2)
-    const int mq = lay == 0 ? 2 : 0;   // own momenta in recm
+    const int hq = lay == 0 ? 1 : 0;   // own thickness in the record (eta1 / h2)
+    const int mq = lay == 0 ? 2 : 0;   // own momenta in the record
     const int gv = lay == 0 ? 3 : 0;   // own variables' gradients start at paper component gv
     const int fv = lay == 0 ? 0 : 3;   // the other layer's height drives this layer's force
     const int ff = lay == 0 ? 1 : 0;   // modelled field index (0: eta1, 1: h2)
@@ -630,9 +717,10 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const double *_
         if (s == 1 && Rc < 0) break;
         const int64_t cell = s == 0 ? L : Rc;
         const int slot = s == 0 ? sL : sR;
-        const R *rm = recm + (int64_t)slot * 16 * T + cell;
-        double hh = rech[(int64_t)(slot * 2 + hq) * T + cell];
-        const R ex = rm[(4 + 2 * gv) * T], ey = rm[(5 + 2 * gv) * T];  // slope of h2, or of eta1
+        const GpRec<R> *rp = rec + 6 * cell + slot;
+        const R *rm = rp->q;
+        double hh = rp->h[hq];
+        const R ex = rm[4 + 2 * gv], ey = rm[5 + 2 * gv];  // slope of h2, or of eta1
         R hx = ex, hy = ey;
         if (lay == 0) {  // eta1 -> h1 with the single-valued bottom at the Gauss point
             hh -= Bg;
@@ -640,10 +728,10 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const double *_
             hy -= gBy;
         }
         h64[s] = hh;
-        const R mx = rm[mq * T], my = rm[(mq + 1) * T];
-        const R mxx = rm[(6 + 2 * gv) * T], mxy = rm[(7 + 2 * gv) * T];
-        const R myx = rm[(8 + 2 * gv) * T], myy = rm[(9 + 2 * gv) * T];
-        const R fx = rm[(4 + 2 * fv) * T], fy = rm[(5 + 2 * fv) * T];
+        const R mx = rm[mq], my = rm[mq + 1];
+        const R mxx = rm[6 + 2 * gv], mxy = rm[7 + 2 * gv];
+        const R myx = rm[8 + 2 * gv], myy = rm[9 + 2 * gv];
+        const R fx = rm[4 + 2 * fv], fy = rm[5 + 2 * fv];
         const R px1 = (R)gP1[(2 * ff) * T + cell], py1 = (R)gP1[(2 * ff + 1) * T + cell];
         const R dfx = wf * fx + (1 - wf) * px1, dfy = wf * fy + (1 - wf) * py1;
         R ax, ay;

@@ -54,7 +54,20 @@ hipError_t upload_f32(const std::vector<double> &h, const void **d, std::vector<
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-size_t rec_bytes(int prec) { return prec == GKS_FP64 ? sizeof(gks::GpRec<double>) : sizeof(gks::GpRec<float>); }
+// bytes of the head and of the tail of one Gauss-point record
+size_t head_bytes(int prec) { return prec == GKS_FP64 ? sizeof(gks::GpHead<double>) : sizeof(gks::GpHead<float>); }
+size_t rec_bytes(int prec)
+{
+    return head_bytes(prec) + (prec == GKS_FP64 ? sizeof(gks::GpTail<double>) : sizeof(gks::GpTail<float>));
+}
+
+// the two record arrays inside one allocation of 6 T records: heads, then tails
+template <typename R>
+gks::GpRecs<R> recs_of(void *base, int64_t T)
+{
+    gks::GpHead<R> *h = static_cast<gks::GpHead<R> *>(base);
+    return {h, reinterpret_cast<gks::GpTail<R> *>(h + 6 * T)};
+}
 
 }  // namespace
 
@@ -157,18 +170,18 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         });
     timed(s, st, GKS_KERNEL_RECON, [&] {
         hipLaunchKernelGGL(gks::k_recon<R>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Whin,
-                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, (gks::GpRec<R> *)s->rec, (R *)s->r0);
+                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, recs_of<R>(s->rec, m.T), (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
         hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p,
-                           (const gks::GpRec<R> *)s->rec, s->hmid);
+                           (const gks::GpHead<R> *)s->rec, s->hmid);
     });
     timed(s, st, GKS_KERNEL_PLANE, [&] {
         hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
         hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p,
-                           (const gks::GpRec<R> *)s->rec, (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+                           recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
         hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage,
@@ -680,15 +693,22 @@ gks_status read_buffer(const gks_state *s, int32_t which, void *dst)
         return GKS_OK;
     }
     if (which == GKS_BUF_RECH || which == GKS_BUF_RECM) {
-        std::vector<gks::GpRec<R>> rec((size_t)(6 * T));
-        HIP_OK(hipMemcpy(rec.data(), s->rec, rec.size() * sizeof(gks::GpRec<R>), hipMemcpyDeviceToHost));
+        std::vector<gks::GpHead<R>> hd((size_t)(6 * T));
+        std::vector<gks::GpTail<R>> tl((size_t)(6 * T));
+        const gks::GpRecs<R> rr = recs_of<R>(s->rec, T);
+        HIP_OK(hipMemcpy(hd.data(), rr.head, hd.size() * sizeof(gks::GpHead<R>), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(tl.data(), rr.tail, tl.size() * sizeof(gks::GpTail<R>), hipMemcpyDeviceToHost));
         for (int64_t c = 0; c < T; c++)
             for (int slot = 0; slot < 6; slot++) {
-                const gks::GpRec<R> &r = rec[6 * c + slot];
-                if (which == GKS_BUF_RECH)
-                    for (int q = 0; q < 2; q++) static_cast<double *>(dst)[(slot * 2 + q) * T + c] = r.h[q];
-                else
-                    for (int q = 0; q < 16; q++) static_cast<R *>(dst)[(slot * 16 + q) * T + c] = r.q[q];
+                const gks::GpHead<R> &h = hd[6 * c + slot];
+                const gks::GpTail<R> &t = tl[6 * c + slot];
+                if (which == GKS_BUF_RECH) {
+                    for (int q = 0; q < 2; q++) static_cast<double *>(dst)[(slot * 2 + q) * T + c] = h.h[q];
+                } else {
+                    R *d = static_cast<R *>(dst);
+                    for (int q = 0; q < 4; q++) d[(slot * 16 + q) * T + c] = h.q[q];
+                    for (int q = 0; q < 12; q++) d[(slot * 16 + 4 + q) * T + c] = t.g[q];
+                }
             }
         return GKS_OK;
     }
@@ -767,11 +787,11 @@ void launch_labels(gks_state *s, double tol)
     pl.linear = 1;
     const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
     hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, (gks::GpRec<R> *)s->rec, (R *)s->r0);
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, recs_of<R>(s->rec, m.T), (R *)s->r0);
     hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, (gks::GpRec<R> *)s->lab_rec, (R *)s->lab_r0);
+                       (const R *)s->gW[b], (const uint8_t *)nullptr, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0);
     hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
-                       (const gks::GpRec<R> *)s->rec, (const gks::GpRec<R> *)s->lab_rec, s->lab_y);
+                       (const gks::GpHead<R> *)s->rec, (const gks::GpHead<R> *)s->lab_rec, s->lab_y);
 }
 
 gks_status labels_any(gks_state *s, double tol)

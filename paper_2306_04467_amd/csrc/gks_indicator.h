@@ -270,7 +270,7 @@ __global__ void k_weights_bf16(const float *__restrict__ P, short *__restrict__ 
 
 template <typename R>
 __global__ void k_label(MeshDev m, double G, double tol, const double *__restrict__ Wh,
-                        const GpRec<R> *__restrict__ rec_nl, const GpRec<R> *__restrict__ rec_li, uint8_t *__restrict__ y)
+                        const GpHead<R> *__restrict__ rec_nl, const GpHead<R> *__restrict__ rec_li, uint8_t *__restrict__ y)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
@@ -279,7 +279,7 @@ __global__ void k_label(MeshDev m, double G, double tol, const double *__restric
     const double sh[2] = {h2, h1}, sm[2] = {h2 * sqrt(G * h2), h1 * sqrt(G * h1)};
     bool ok = true;
     for (int slot = 0; slot < 6; slot++) {
-        const GpRec<R> &a = rec_nl[6 * c + slot], &b = rec_li[6 * c + slot];
+        const GpHead<R> &a = rec_nl[6 * c + slot], &b = rec_li[6 * c + slot];
         for (int q = 0; q < 2; q++) ok = ok && fabs(a.h[q] - b.h[q]) <= tol * sh[q];
         for (int q = 0; q < 4; q++) ok = ok && fabs((double)a.q[q] - (double)b.q[q]) <= tol * sm[q / 2];
     }

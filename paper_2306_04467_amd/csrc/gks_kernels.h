@@ -11,8 +11,8 @@
 //   state  structure of arrays, index = component * stride + cell: Wh[2][TG] (double: h2, eta1),
 //          Wm[4][TG] (R: h2U2, h2V2, h1U1, h1V1), gW[12][TG] (R: x/y gradients of h2, h2U2, h2V2,
 //          eta1, h1U1, h1V1), TG = T + NG ghosts
-//   rec    GpRec[6 T], cell-major: the reconstruction at each cell's six Gauss points, read by
-//          the edge kernels as whole 16-byte words (one or two cache lines per record)
+//   rec    GpHead[6 T] and GpTail[6 T], cell-major: the reconstruction at each cell's six Gauss
+//          points, read by the edge kernels as 16-byte words (one cache line per record)
 //   eoh    [4][E] double: per edge, Gauss points averaged: 1/2 G hb^2 (upper, lower), hb (upper,
 //          lower), hb the interface thickness of the evolution
 //   eom    [22][E] R: F0 (6, hydrostatic part removed), Ft (6), interface momenta (4), interface
@@ -65,24 +65,28 @@ __device__ inline int64_t xcd_block()
 // the four momentum components in paper order 1, 2, 4, 5 -> slots 0..3 of Wm
 __device__ inline int mom_slot(int v) { return v < 3 ? v - 1 : v - 2; }
 
-// Gauss-point record of one cell at one of its six Gauss points (slot = 2 * local edge + point),
+// Gauss-point records of one cell at one of its six Gauss points (slot = 2 * local edge + point),
 // written by the reconstruction and read by the edge kernels.  Records are stored cell-major,
-// rec[6 c + slot], so that an edge kernel reads each side's record as a few 16-byte loads.
-//   h[0] h2, h[1] eta1 = h1 + B (double in both precisions)
-//   q[0..3]  momenta h2U2, h2V2, h1U1, h1V1
-//   q[4 + 2 v], q[5 + 2 v]  x / y derivative of paper component v (v = 0..5, eta1 in place of h1)
-template <typename R>
-struct alignas(16) GpRec {
-    double h[2];
-    R q[16];
-};
-
-// The leading part of a Gauss-point record (thicknesses and momenta), read by itself where the
-// gradients are not needed.
+// index 6 c + slot, in two arrays: the head (thicknesses and momenta, all that the force model's
+// edge kernel reads) and the tail (gradients), so that each is read as a few 16-byte words.
+//   head.h[0] h2, head.h[1] eta1 = h1 + B (double in both precisions)
+//   head.q[0..3]  momenta h2U2, h2V2, h1U1, h1V1
+//   tail.g[2 v], tail.g[2 v + 1]  x / y derivative of paper component v (v = 0..5, eta1 for h1)
 template <typename R>
 struct alignas(16) GpHead {
     double h[2];
     R q[4];
+};
+
+template <typename R>
+struct alignas(16) GpTail {
+    R g[12];
+};
+
+template <typename R>
+struct GpRecs {
+    GpHead<R> *head;
+    GpTail<R> *tail;
 };
 
 
@@ -310,17 +314,19 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, const double 
 template <typename R>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
                                                const R *__restrict__ Wm, const R *__restrict__ gW,
-                                               const uint8_t *__restrict__ smooth, GpRec<R> *__restrict__ rec,
+                                               const uint8_t *__restrict__ smooth, GpRecs<R> rec,
                                                R *__restrict__ r0)
 {
     // LDS: first the block's 32 least-squares operators, loaded once with coalesced reads and
     // shared by the six variable threads of each cell; then, in the same space, the block's 32 x 6
-    // Gauss-point records, written out as one contiguous span
+    // Gauss-point records (heads, then tails), each array written out as one contiguous span
+    constexpr int NR = RECON_CELLS * 6;
     constexpr int MBYTES = 153 * RECON_CELLS * (int)sizeof(R);
-    constexpr int OBYTES = RECON_CELLS * 6 * (int)sizeof(GpRec<R>);
+    constexpr int OBYTES = NR * (int)(sizeof(GpHead<R>) + sizeof(GpTail<R>));
     __shared__ uint4 lds[(MBYTES > OBYTES ? MBYTES : OBYTES) / 16];
     R *Ms = reinterpret_cast<R *>(lds);
-    GpRec<R> *tile = reinterpret_cast<GpRec<R> *>(lds);
+    GpHead<R> *th = reinterpret_cast<GpHead<R> *>(lds);
+    GpTail<R> *tt = reinterpret_cast<GpTail<R> *>(th + NR);
     const int lane = threadIdx.x & 31, wv = threadIdx.x >> 5;
     const int v = (wv == 0) ? 0 : (wv == 1) ? 3 : (wv == 2) ? 1 : (wv == 3) ? 2 : (wv == 4) ? 4 : 5;
     const bool thick = (v == 0 || v == 3);
@@ -348,24 +354,24 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     if (lane < ncell) recon_cell<R>(m, p, Wh, Wm, gW, smooth, r0, v, thick, c, Ms + lane, out);
     __syncthreads();  // the operators are no longer needed: the space becomes the record tile
     if (lane < ncell) {
-        GpRec<R> *o = tile + 6 * lane;
-        const int gbase = 4 + 2 * v;
 #pragma unroll
         for (int slot = 0; slot < 6; slot++) {
+            const int i = 6 * lane + slot;
             if (thick)
-                o[slot].h[v == 3] = out.h[slot];
+                th[i].h[v == 3] = out.h[slot];
             else
-                o[slot].q[mom_slot(v)] = out.val[slot];
-            o[slot].q[gbase] = out.gx[slot];
-            o[slot].q[gbase + 1] = out.gy[slot];
+                th[i].q[mom_slot(v)] = out.val[slot];
+            tt[i].g[2 * v] = out.gx[slot];
+            tt[i].g[2 * v + 1] = out.gy[slot];
         }
     }
     __syncthreads();
     // copy out: 16-byte words of the valid cells' records
-    const int nw = (int)(ncell * 6 * sizeof(GpRec<R>) / 16);
-    const uint4 *src = reinterpret_cast<const uint4 *>(tile);
-    uint4 *dst = reinterpret_cast<uint4 *>(rec + 6 * c0);
-    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+    const int nh = (int)(ncell * 6 * sizeof(GpHead<R>) / 16), nt = (int)(ncell * 6 * sizeof(GpTail<R>) / 16);
+    const uint4 *sh = reinterpret_cast<const uint4 *>(th), *st = reinterpret_cast<const uint4 *>(tt);
+    uint4 *dh = reinterpret_cast<uint4 *>(rec.head + 6 * c0), *dtl = reinterpret_cast<uint4 *>(rec.tail + 6 * c0);
+    for (int i = threadIdx.x; i < nh; i += blockDim.x) dh[i] = sh[i];
+    for (int i = threadIdx.x; i < nt; i += blockDim.x) dtl[i] = st[i];
 }
 
 // --------------------------------------------------------------------------------------------
@@ -374,7 +380,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
 // plane through them must be flat at rest)
 
 template <typename R>
-__global__ void k_hhat(MeshDev m, Phys p, const GpRec<R> *__restrict__ rec, double *__restrict__ hmid)
+__global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, double *__restrict__ hmid)
 {
     int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
@@ -388,9 +394,9 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpRec<R> *__restrict__ rec, doub
     for (int g = 0; g < 2; g++) {
         const double Bg = m.eBgp[g * E + e];
         const int sL = 2 * kL + g, sR = 2 * kR + 1 - g;
-        const GpHead<R> ql = *reinterpret_cast<const GpHead<R> *>(rec + 6 * (int64_t)L + sL);
+        const GpHead<R> ql = head[6 * (int64_t)L + sL];
         GpHead<R> qr = ql;
-        if (Rc >= 0) qr = *reinterpret_cast<const GpHead<R> *>(rec + 6 * (int64_t)Rc + sR);
+        if (Rc >= 0) qr = head[6 * (int64_t)Rc + sR];
 #pragma unroll
         for (int f = 0; f < 2; f++) {
             // f = 0: eta1 with the lower layer's momentum; f = 1: h2 with the upper layer's
@@ -683,7 +689,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 
 // one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
 template <typename R>
-__global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const GpRec<R> *__restrict__ rec,
+__global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
                                               const R *__restrict__ r0, const double *__restrict__ gP1,
                                               double *__restrict__ eoh, R *__restrict__ eom)
 {
@@ -717,10 +723,10 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const GpRec<R> 
         if (s == 1 && Rc < 0) break;
         const int64_t cell = s == 0 ? L : Rc;
         const int slot = s == 0 ? sL : sR;
-        const GpRec<R> *rp = rec + 6 * cell + slot;
-        const R *rm = rp->q;
-        double hh = rp->h[hq];
-        const R ex = rm[4 + 2 * gv], ey = rm[5 + 2 * gv];  // slope of h2, or of eta1
+        const GpHead<R> *hp = rec.head + 6 * cell + slot;
+        const R *rm = hp->q, *rg = rec.tail[6 * cell + slot].g;
+        double hh = hp->h[hq];
+        const R ex = rg[2 * gv], ey = rg[2 * gv + 1];  // slope of h2, or of eta1
         R hx = ex, hy = ey;
         if (lay == 0) {  // eta1 -> h1 with the single-valued bottom at the Gauss point
             hh -= Bg;
@@ -729,9 +735,9 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, const GpRec<R> 
         }
         h64[s] = hh;
         const R mx = rm[mq], my = rm[mq + 1];
-        const R mxx = rm[6 + 2 * gv], mxy = rm[7 + 2 * gv];
-        const R myx = rm[8 + 2 * gv], myy = rm[9 + 2 * gv];
-        const R fx = rm[4 + 2 * fv], fy = rm[5 + 2 * fv];
+        const R mxx = rg[2 + 2 * gv], mxy = rg[3 + 2 * gv];
+        const R myx = rg[4 + 2 * gv], myy = rg[5 + 2 * gv];
+        const R fx = rg[2 * fv], fy = rg[2 * fv + 1];
         const R px1 = (R)gP1[(2 * ff) * T + cell], py1 = (R)gP1[(2 * ff + 1) * T + cell];
         const R dfx = wf * fx + (1 - wf) * px1, dfy = wf * fy + (1 - wf) * py1;
         R ax, ay;

@@ -137,21 +137,24 @@ struct ReconOut {
     R gx[6], gy[6];
 };
 
-// reconstruction of variable v of cell c; Ms points at the cell's least-squares operator in LDS
-// (entry j at Ms[32 j])
+// right-hand side of the least-squares system of variable v of cell c
 template <typename R>
-__device__ inline void recon_cell(const MeshDev &m, const Phys &p, const double *__restrict__ Wh,
-                                  const R *__restrict__ Wm, const R *__restrict__ gW,
-                                  const uint8_t *__restrict__ smooth, R *__restrict__ r0, int v, bool thick,
-                                  int64_t c, const R *Ms, ReconOut<R> &out)
+struct ReconRhs {
+    R rhs[17];  // average differences, then scaled gradients of the cell and its face neighbours
+    R hs, Q0;
+    double Q0h;  // cell average of a thickness in double
+};
+
+template <typename R>
+__device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh, const R *__restrict__ Wm,
+                                 const R *__restrict__ gW, int v, bool thick, int64_t c, ReconRhs<R> &q)
 {
     const int64_t T = m.T, TG = m.T + m.NG;
     const R hs = tab<R>(m.hs)[c];
-    // right-hand side of the least-squares system: average differences, then scaled gradients
-    // (differences of thicknesses are taken in FP64 before rounding)
+    // differences of thicknesses are taken in FP64 before rounding
     double Q0h = 0;
     R Q0 = 0;
-    R rhs[17];
+    R *rhs = q.rhs;
     int32_t nb[9];
 #pragma unroll
     for (int s = 0; s < 9; s++) nb[s] = m.sten[s * T + c];
@@ -174,6 +177,22 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, const double 
         rhs[11 + 2 * l] = hs * gW[(2 * v) * TG + nb[l]];
         rhs[12 + 2 * l] = hs * gW[(2 * v + 1) * TG + nb[l]];
     }
+    q.hs = hs;
+    q.Q0 = Q0;
+    q.Q0h = Q0h;
+}
+
+// reconstruction of variable v of cell c from its right-hand side; Ms points at the cell's
+// least-squares operator in LDS (entry j at Ms[32 j])
+template <typename R>
+__device__ inline void recon_cell(const MeshDev &m, const Phys &p, const uint8_t *__restrict__ smooth,
+                                  R *__restrict__ r0, int v, bool thick, int64_t c, const ReconRhs<R> &q,
+                                  const R *Ms, ReconOut<R> &out)
+{
+    const int64_t T = m.T;
+    const R *rhs = q.rhs;
+    const R hs = q.hs, Q0 = q.Q0;
+    const double Q0h = q.Q0h;
     R a[9];
 #pragma unroll
     for (int k = 0; k < 9; k++) {
@@ -333,6 +352,9 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     const int64_t c0 = xcd_block() * RECON_CELLS, c = c0 + lane;
     const int64_t T = m.T;
     const int ncell = T - c0 < RECON_CELLS ? (int)(T - c0) : RECON_CELLS;
+    // the cell's own gathers are issued first, so that they overlap the operator staging
+    ReconRhs<R> q;
+    if (lane < ncell) recon_rhs<R>(m, Wh, Wm, gW, v, thick, c, q);
     {
         // every load of the staging is issued before the first LDS write
         constexpr int NM = 153 * RECON_CELLS, IT = (NM + 191) / 192;
@@ -351,7 +373,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     }
     __syncthreads();
     ReconOut<R> out;
-    if (lane < ncell) recon_cell<R>(m, p, Wh, Wm, gW, smooth, r0, v, thick, c, Ms + lane, out);
+    if (lane < ncell) recon_cell<R>(m, p, smooth, r0, v, thick, c, q, Ms + lane, out);
     __syncthreads();  // the operators are no longer needed: the space becomes the record tile
     if (lane < ncell) {
 #pragma unroll

@@ -92,6 +92,7 @@ struct gks_state {
     void *Gc = nullptr, *rec = nullptr, *r0 = nullptr, *eom = nullptr;  // rec: GpRec[6T]
     double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
     uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
+    uint8_t *need = nullptr;    // cells whose plane gradient of the force model is used
     int nparts = 0;
     // learned indicator: parameters, bf16 copies of the weight matrices, threshold
     bool ind_on = false;
@@ -173,11 +174,12 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
                            Wmin, gWin, s->ind_on ? s->smooth : nullptr, recs_of<R>(s->rec, m.T), (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
+        hipLaunchKernelGGL(gks::k_need<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, (const R *)s->r0, s->need);
         hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p,
-                           (const gks::GpHead<R> *)s->rec, s->hmid);
+                           (const gks::GpHead<R> *)s->rec, s->need, s->hmid);
     });
     timed(s, st, GKS_KERNEL_PLANE, [&] {
-        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->hmid, s->gP1);
+        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->need, s->hmid, s->gP1);
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
         hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p,
@@ -453,7 +455,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                 {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
                 {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
                 {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
-                {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
+                {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
                 {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max(s->nparts, 1024) * 8},
                 {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
     for (auto &b : bufs) {

@@ -288,7 +288,13 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, const uint8_t
             tm[s] = dm * (1 + tz / (bm[s] + epsw));
             sum += tm[s];
         }
-        const R isum = R(1) / sum;
+        // where every unnormalised weight equals its linear weight (tau = 0, or tau / (beta + eps)
+        // below the rounding of 1), the weights are the linear ones, which sum to one: take them
+        // exactly instead of dividing by their rounded sum
+        bool lin = t0 == d0;
+#pragma unroll
+        for (int s = 0; s < 4; s++) lin = lin && tm[s] == dm;
+        const R isum = lin ? R(1) : R(1) / sum;
         w0 = t0 * isum;
 #pragma unroll
         for (int s = 0; s < 4; s++) wm[s] = tm[s] * isum;
@@ -401,13 +407,33 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
 // h2 (upper-layer velocity) from the two Gauss points' convex combinations (FP64: cheap, and the
 // plane through them must be flat at rest)
 
+// Cells whose plane gradient the flux can read: the force model blends it in with weight 1 - w,
+// w = min(1, omega0/d0 of both sides), so only next to a cell whose weight ratio is below 1.  A
+// face neighbour beyond a wall is the cell's own mirror image.
 template <typename R>
-__global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, double *__restrict__ hmid)
+__global__ void k_need(MeshDev m, const R *__restrict__ r0, uint8_t *__restrict__ need)
+{
+    const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
+    if (c >= m.T) return;
+    const int64_t T = m.T;
+    bool bad = r0[c] < R(1) || r0[T + c] < R(1);
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        const int32_t i = m.sten[l * T + c];
+        if (i < T) bad = bad || r0[i] < R(1) || r0[T + i] < R(1);
+    }
+    need[c] = bad ? 1 : 0;
+}
+
+template <typename R>
+__global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, const uint8_t *__restrict__ need,
+                       double *__restrict__ hmid)
 {
     int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
     const int64_t T = m.T, E = m.E;
     const int32_t L = m.eL[e], Rc = m.eR[e], sl = m.eslot[e];
+    if (!need[L] && (Rc < 0 || !need[Rc])) return;  // no plane gradient uses this edge
     const int kL = sl & 3, kR = sl >> 2;
     const R *en = tab<R>(m.en);
     const double nx = en[e], ny = en[E + e];
@@ -448,10 +474,11 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, do
 }
 
 // gradient of the plane through the three edge-centre heights (Green-Gauss, exact for planes)
-__global__ void k_plane(MeshDev m, const double *__restrict__ hmid, double *__restrict__ gP1)
+__global__ void k_plane(MeshDev m, const uint8_t *__restrict__ need, const double *__restrict__ hmid,
+                        double *__restrict__ gP1)
 {
     int64_t c = xcd_block() * blockDim.x + threadIdx.x;
-    if (c >= m.T) return;
+    if (c >= m.T || !need[c]) return;
     const int64_t T = m.T, E = m.E;
     double s[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -760,8 +787,13 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
         const R mxx = rg[2 + 2 * gv], mxy = rg[3 + 2 * gv];
         const R myx = rg[4 + 2 * gv], myy = rg[5 + 2 * gv];
         const R fx = rg[2 * fv], fy = rg[2 * fv + 1];
-        const R px1 = (R)gP1[(2 * ff) * T + cell], py1 = (R)gP1[(2 * ff + 1) * T + cell];
-        const R dfx = wf * fx + (1 - wf) * px1, dfy = wf * fy + (1 - wf) * py1;
+        // the plane gradient enters only where the weight is below 1 (it is not computed elsewhere)
+        R dfx = fx, dfy = fy;
+        if (wf < R(1)) {
+            const R px1 = (R)gP1[(2 * ff) * T + cell], py1 = (R)gP1[(2 * ff + 1) * T + cell];
+            dfx = wf * fx + (1 - wf) * px1;
+            dfy = wf * fy + (1 - wf) * py1;
+        }
         R ax, ay;
         if (lay == 0) {  // lower layer: upper-layer thickness (chi weighted); the bottom part -G gB
             ax = -chi * G * dfx;  // of its acceleration enters through bottom_moments

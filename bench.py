@@ -175,6 +175,110 @@ def run_ensemble(n_scen, steps, warmup, with_error):
     return out
 
 
+def he_init(seed, n_in=44, n_h=64):
+    """Initial indicator parameters: He-normal weights, zero biases (seeded)."""
+    import numpy as np
+
+    rng = np.random.default_rng(seed)
+    P = [rng.normal(0, np.sqrt(2.0 / n_in), n_in * n_h), np.zeros(n_h),
+         rng.normal(0, np.sqrt(2.0 / n_h), n_h * n_h), np.zeros(n_h),
+         rng.normal(0, np.sqrt(1.0 / n_h), n_h), np.zeros(1)]
+    return np.concatenate(P).astype(np.float32)
+
+
+def train_indicator(label_tol=1e-7, snapshots=6, every=10, epochs=8, batch=2048, max_false_skip=1e-4):
+    """Train the smoothness indicator on FP64 snapshots of small instances of the three workload
+    shapes (smooth periodic waves, perturbed lake at rest, dam break), labelled by the library's
+    own nonlinear-vs-linear reconstruction; returns (params, threshold, info)."""
+    import workloads
+    from paper_2306_04467_amd import Mesh, State, Trainer
+
+    t0 = time.time()
+    train = [workloads.smooth_periodic(20), workloads.lake_at_rest(128, seed=20230611, perturb=1e-3),
+             workloads.dam_break(128, seed=20230612, bump_amp=0.2)]
+    tr = Trainer(sum(sc.n_tri for sc in train) * snapshots, he_init(20230613), max_batch=batch)
+    for sc in train:
+        st = State.from_scenario(Mesh.from_scenario(sc), sc, precision="fp64")
+        for _ in range(snapshots):
+            tr.add_state(st, label_tol)
+            st.step(every)
+    n, npos = tr.info()
+    t1 = time.time()
+    losses = tr.fit(epochs, batch=batch, lr=2e-3, seed=20230614)
+    thr = tr.threshold(max_false_skip)
+    t2 = time.time()
+    info = {"samples": n, "label1": npos, "epochs": epochs, "batch": batch, "loss_first_last": [float(losses[0]),
+            float(losses[-1])], "threshold": thr, "max_false_skip": max_false_skip, "label_tol": label_tol,
+            "data_s": round(t1 - t0, 1), "train_s": round(t2 - t1, 1)}
+    log(f"indicator trained: {json.dumps(info)}")
+    return tr.params(), thr, info
+
+
+def run_indicator(n, steps, warmup, err_n, with_error):
+    """Gain case: dam break plus bump on a 2 n^2-triangle mesh, FP32 mixed, with and without the
+    learned indicator; rel-L1 error of both against the FP64 oracle after 20 steps on a smaller
+    mesh of the same shape."""
+    import numpy as np
+
+    import workloads
+    from paper_2306_04467_amd import Mesh, State
+
+    P, thr, info = train_indicator()
+    t0 = time.time()
+    sc = workloads.dam_break(n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
+    mesh = Mesh.from_scenario(sc)
+    log(f"gain workload: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
+    out = {"workload": f"dam break + bump, jittered Delaunay [0,1]^2, {sc.n_tri} triangles, FP32 mixed",
+           "n_tri": sc.n_tri, "steps": steps, "training": info}
+    for name in ("full_weno", "indicator"):
+        st = State.from_scenario(mesh, sc, precision="fp32")
+        if name == "indicator":
+            st.indicator(P, thr)
+        ms = timed_steps(st, steps, warmup, graph=True)
+        value = sc.n_tri * 2 * steps / (ms / 1e3)
+        rec = {"value": round(value, 1), "ms_per_step": round(ms / steps, 5)}
+        if name == "indicator":
+            _, _, k = st.indicator_eval()
+            rec["skipped_fraction_end"] = round(k / sc.n_tri, 4)
+            st.profile(True)
+            st.step(2)
+            prof = st.profile_read()
+            st.profile(False)
+            rec["kernel_ms"] = {kk: round(v[0] / v[1], 5) for kk, v in prof.items() if v[1]}
+        log(f"gain {name}: {value / 1e9:.3f} G tri-stage/s {json.dumps(rec)}")
+        out[name] = rec
+        st.close()
+    out["speedup"] = round(out["indicator"]["value"] / out["full_weno"]["value"], 3)
+    if with_error:
+        import oracle
+
+        se = workloads.dam_break(err_n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
+        om = oracle.Mesh.from_scenario(se)
+        p = oracle.params_of(se)
+        m2 = Mesh.from_scenario(se)
+        full = State.from_scenario(m2, se, precision="fp32")
+        ind = State.from_scenario(m2, se, precision="fp32")
+        ind.indicator(P, thr)
+        W, gW = se.W0.copy(), se.gradW0.copy()
+        skipped = []
+        tc = time.time()
+        for _ in range(20):
+            dt = oracle.dt(om, p, W)
+            for st in (full, ind):
+                st.stage(0, dt)
+                st.stage(1)
+            skipped.append(ind.indicator_eval()[2] / se.n_tri)
+            W, gW = oracle.step(om, p, dt, W, gW)
+        a = sc_area(se)
+        out["error_case"] = {"n_tri": se.n_tri, "steps": 20,
+                             "rel_l1_full_weno": rel_l1(full.read()[0], W, a, se.G),
+                             "rel_l1_indicator": rel_l1(ind.read()[0], W, a, se.G),
+                             "skipped_fraction_mean": round(float(np.mean(skipped)), 4),
+                             "oracle_s": round(time.time() - tc, 1)}
+        log(f"gain error case: {json.dumps(out['error_case'])}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +288,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default=None,
                     help="run only this precision on the headline workload")
     ap.add_argument("--ensemble", type=int, default=256, help="scenarios in the ensemble leg (0: skip)")
+    ap.add_argument("--indicator-n", type=int, default=1000,
+                    help="lattice size of the learned-indicator gain case (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -244,6 +350,8 @@ def main():
                                "roofline": r32, "kernels": k32}
     if args.ensemble > 0:
         extra["ensemble"] = run_ensemble(args.ensemble, 50, 5, not args.no_cpu_baseline)
+    if args.indicator_n > 0:
+        extra["fp32_learned_indicator"] = run_indicator(args.indicator_n, 50, 5, 160, not args.no_cpu_baseline)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "triangle-stage/s", "n_gpus": 1,

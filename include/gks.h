@@ -137,7 +137,9 @@ typedef enum {
                           points averaged, hb the interface thickness of the evolution solution */
     GKS_BUF_EOM = 4,   /* real [22][n_edges]: flux F0 without 1/2 G hb^2 n (6), its time derivative
                           (6), interface momenta (4), interface time derivatives (6), global frame */
-    GKS_BUF_COUNT = 5
+    GKS_BUF_SKIP = 5,  /* uint8 [n_tri]: the learned indicator's decisions of the last stage that ran
+                          with it (1 = linear weights); unspecified before the first such stage */
+    GKS_BUF_COUNT = 6
 } gks_buffer;
 /* Copy one intermediate array to host memory `dst` of `bytes` bytes (synchronising); "real" is
  * double for GKS_FP64 states and float for GKS_FP32_MIXED.  GKS_EINVAL if bytes is too small. */

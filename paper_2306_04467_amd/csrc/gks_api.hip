@@ -163,15 +163,15 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         timed(s, st, GKS_KERNEL_GHOST, [&] {
             hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Whin, Wmin, gWin);
         });
-    if (s->ind_on)
-        timed(s, st, GKS_KERNEL_INDICATOR, [&] {
-            hipLaunchKernelGGL(gks::k_indicator<R>, dim3(blocks(m.T, 32 * gks::IND_WAVES)), dim3(64 * gks::IND_WAVES),
-                               0, st, m, s->p.G, Whin, Wmin, gWin, s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr,
-                               s->smooth, (float *)nullptr);
-        });
     timed(s, st, GKS_KERNEL_RECON, [&] {
-        hipLaunchKernelGGL(gks::k_recon<R>, dim3(blocks(m.T, gks::RECON_CELLS)), dim3(192), 0, st, m, s->p, Whin,
-                           Wmin, gWin, s->ind_on ? s->smooth : nullptr, recs_of<R>(s->rec, m.T), (R *)s->r0);
+        const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
+        if (s->ind_on)
+            hipLaunchKernelGGL((gks::k_recon<R, true>), g, t, 0, st, m, s->p, Whin, Wmin, gWin,
+                               gks::IndArgs{s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth},
+                               recs_of<R>(s->rec, m.T), (R *)s->r0);
+        else
+            hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, gks::IndArgs{},
+                               recs_of<R>(s->rec, m.T), (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
         hipLaunchKernelGGL(gks::k_need<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, (const R *)s->r0, s->need);
@@ -735,10 +735,16 @@ extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *
     case GKS_BUF_RECM: need = 96 * T * rs; break;
     case GKS_BUF_R0: need = 2 * T * rs; break;
     case GKS_BUF_EOH: need = 4 * E * 8; break;
+    case GKS_BUF_SKIP: need = T; break;
     default: need = 22 * E * rs; break;
     }
     if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
     HIP_OK(hipStreamSynchronize(s->stream));
+    if (which == GKS_BUF_SKIP) {
+        if (!s->smooth) return fail(GKS_EINVAL, "the indicator has never been switched on");
+        HIP_OK(hipMemcpy(dst, s->smooth, (size_t)T, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    }
     return s->prec == GKS_FP64 ? read_buffer<double>(s, which, dst) : read_buffer<float>(s, which, dst);
 }
 
@@ -788,10 +794,10 @@ void launch_labels(gks_state *s, double tol)
     pn.linear = 0;
     pl.linear = 1;
     const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
-    hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, recs_of<R>(s->rec, m.T), (R *)s->r0);
-    hipLaunchKernelGGL(gks::k_recon<R>, g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], (const uint8_t *)nullptr, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0);
+    hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
+                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->rec, m.T), (R *)s->r0);
+    hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
+                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0);
     hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
                        (const gks::GpHead<R> *)s->rec, (const gks::GpHead<R> *)s->lab_rec, s->lab_y);
 }

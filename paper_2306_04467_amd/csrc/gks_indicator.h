@@ -16,53 +16,26 @@
 #include <stdint.h>
 
 #include "gks_kernels.h"
+#include "gks_mlp.h"
 
 namespace gks {
 
-constexpr int MLP_IN = 44, MLP_K = 48, MLP_H = 64;
-constexpr int MLP_NP = MLP_IN * MLP_H + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;  // 7105
-constexpr int OFF_B1 = MLP_IN * MLP_H, OFF_W2 = OFF_B1 + MLP_H, OFF_B2 = OFF_W2 + MLP_H * MLP_H,
-              OFF_W3 = OFF_B2 + MLP_H, OFF_B3 = OFF_W3 + MLP_H;
-
 // Features of field f of cell c (f = 0: eta1 with the lower layer's momenta, f = 1: h2 with the
 // upper layer's): x[0..16] the stencil differences and scaled gradients, x[17] the size of the
-// variation, x[18] the size of the momentum variation.
+// variation, x[18] the size of the momentum variation.  Computed from the reconstruction's own
+// right-hand sides, with the arithmetic of the reconstruction kernel's fused indicator.
 template <typename R>
 __device__ inline void field_features(const MeshDev &m, double G, const double *__restrict__ Wh,
-                                      const R *__restrict__ Wm, const R *__restrict__ gW, int f, int64_t c,
-                                      const int32_t *nb, float *x)
+                                      const R *__restrict__ Wm, const R *__restrict__ gW, int f, int64_t c, float *x)
 {
-    const int64_t T = m.T, TG = m.T + m.NG;
-    const double *Q = Wh + (f == 0 ? TG : 0);
-    const int v = f == 0 ? 3 : 0;
-    const double Q0 = Q[c];
-    const double h = f == 0 ? Q0 - m.Bbar[c] : Q0;
-    double d[9], s = 0;
-#pragma unroll
-    for (int l = 0; l < 9; l++) {
-        d[l] = Q[nb[l]] - Q0;
-        s = fmax(s, fabs(d[l]));
-    }
-    s += 1e-12 * fabs(Q0);
-    const double is = 1.0 / s, hs = (double)tab<R>(m.hs)[c];
-#pragma unroll
-    for (int l = 0; l < 9; l++) x[l] = (float)(d[l] * is);
-    x[9] = (float)(hs * (double)gW[(2 * v) * TG + c] * is);
-    x[10] = (float)(hs * (double)gW[(2 * v + 1) * TG + c] * is);
-#pragma unroll
-    for (int l = 0; l < 3; l++) {
-        x[11 + 2 * l] = (float)(hs * (double)gW[(2 * v) * TG + nb[l]] * is);
-        x[12 + 2 * l] = (float)(hs * (double)gW[(2 * v + 1) * TG + nb[l]] * is);
-    }
-    x[17] = (float)(log10(s / h) * 0.25);
-    // momentum slots: upper layer 0, 1; lower layer 2, 3
-    const R *mu = Wm + (f == 0 ? 2 : 0) * TG, *mv = mu + TG;
-    const double mu0 = (double)mu[c], mv0 = (double)mv[c];
-    double sm = 0;
-#pragma unroll
-    for (int l = 0; l < 9; l++) sm = fmax(sm, fmax(fabs((double)mu[nb[l]] - mu0), fabs((double)mv[nb[l]] - mv0)));
-    const double cm = h * sqrt(G * h);
-    x[18] = (float)(log10((sm + 1e-12 * cm) / cm) * 0.25);
+    const int vt = f == 0 ? 3 : 0, vu = f == 0 ? 4 : 1;
+    ReconRhs<R> q, qu, qv;
+    recon_rhs<R>(m, Wh, Wm, gW, vt, true, c, q);
+    recon_rhs<R>(m, Wh, Wm, gW, vu, false, c, qu);
+    recon_rhs<R>(m, Wh, Wm, gW, vu + 1, false, c, qv);
+    const double h = f == 0 ? q.Q0h - m.Bbar[c] : q.Q0h;
+    thick_features<R>(q.rhs, q.Q0h, h, x);
+    x[18] = mom_feature(fmax(max_diff<R>(qu.rhs), max_diff<R>(qv.rhs)), h, G);
 }
 
 // all 44 features of cell c (training export)
@@ -72,106 +45,25 @@ __global__ void k_features(MeshDev m, double G, const double *__restrict__ Wh, c
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
-    const int64_t T = m.T;
-    int32_t nb[9];
-#pragma unroll
-    for (int s = 0; s < 9; s++) nb[s] = m.sten[s * T + c];
     float *x = X + c * MLP_IN;
 #pragma unroll
     for (int f = 0; f < 2; f++) {
         float y[19];
-        field_features<R>(m, G, Wh, Wm, gW, f, c, nb, y);
+        field_features<R>(m, G, Wh, Wm, gW, f, c, y);
 #pragma unroll
         for (int k = 0; k < 17; k++) x[17 * f + k] = y[k];
         x[34 + f] = y[17];
         x[36 + f] = y[18];
     }
 #pragma unroll
-    for (int k = 0; k < 6; k++) x[38 + k] = m.igeo[k * T + c];
+    for (int k = 0; k < 6; k++) x[38 + k] = m.igeo[k * m.T + c];
 }
 
 // ---------------------------------------------------------------------------------------------
-// inference: 4 waves per block, one wave per 32 cells
+// inference: 4 waves per block, one wave per 32 cells (the network itself is in gks_mlp.h)
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-
-__device__ inline short to_bf16(float x)
-{
-    unsigned u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return (short)(u >> 16);
-}
-
-constexpr int IND_WAVES = 4;
-
-// One wave evaluates the MLP on 32 feature rows held in LDS (feat[32][49], hid[32][65] are the
-// wave's own slices).  The matrix products use v_mfma_f32_32x32x8_bf16: lane l supplies row l%32
-// of A and column l%32 of B for k = 4 (l/32) + 0..3; accumulator register r of lane l holds row
-// 8 (r/4) + 4 (l/32) + r%4, column l%32.  The caller synchronises between the two halves.
-__device__ inline void mlp_layer1(const float (*feat)[MLP_K + 1], float (*hid)[MLP_H + 1], int lane,
-                                  const short *__restrict__ W1b, const float *__restrict__ P)
-{
-    const int row = lane & 31, half = lane >> 5;
-#pragma unroll
-    for (int nbk = 0; nbk < 2; nbk++) {
-        f32x16 acc = f32x16{0};
-#pragma unroll
-        for (int s = 0; s < MLP_K / 8; s++) {
-            bf16x4 a, b;
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int k = 8 * s + 4 * half + i;
-                a[i] = to_bf16(feat[row][k]);
-                b[i] = W1b[k * MLP_H + 32 * nbk + row];
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
-        }
-        const float bias = P[OFF_B1 + 32 * nbk + row];
-#pragma unroll
-        for (int r = 0; r < 16; r++) hid[8 * (r / 4) + 4 * half + (r % 4)][32 * nbk + row] = fmaxf(acc[r] + bias, 0.f);
-    }
-}
-
-// second hidden layer and the output unit; on return lanes 0 and 32 hold the logits of rows
-// 8 (r/4) + 4 (l/32) + r%4 in z[r]
-__device__ inline void mlp_layer2_out(const float (*hid)[MLP_H + 1], int lane, const short *__restrict__ W2b,
-                                      const float *__restrict__ P, float z[16])
-{
-    const int row = lane & 31, half = lane >> 5;
-    f32x16 acc[2];
-#pragma unroll
-    for (int nbk = 0; nbk < 2; nbk++) {
-        acc[nbk] = f32x16{0};
-#pragma unroll
-        for (int s = 0; s < MLP_H / 8; s++) {
-            bf16x4 a, b;
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                const int k = 8 * s + 4 * half + i;
-                a[i] = to_bf16(hid[row][k]);
-                b[i] = W2b[k * MLP_H + 32 * nbk + row];
-            }
-            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[nbk], 0, 0, 0);
-        }
-    }
-    // z_i = b3 + sum_j relu(acc_ij + b2_j) w3_j: column j lives in lane j (and j + 32 of the
-    // second block), so reduce over the 32 lanes of each half
-    const float b2a = P[OFF_B2 + row], b2b = P[OFF_B2 + 32 + row];
-    const float w3a = P[OFF_W3 + row], w3b = P[OFF_W3 + 32 + row];
-#pragma unroll
-    for (int r = 0; r < 16; r++) z[r] = fmaxf(acc[0][r] + b2a, 0.f) * w3a + fmaxf(acc[1][r] + b2b, 0.f) * w3b;
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1)
-#pragma unroll
-        for (int r = 0; r < 16; r++) z[r] += __shfl_xor(z[r], off);
-    const float b3 = P[OFF_B3];
-#pragma unroll
-    for (int r = 0; r < 16; r++) z[r] += b3;
-}
-
-// W1b: bf16 [48][64] (zero rows 44..47), W2b: bf16 [64][64]; P: FP32 parameters (biases and the
-// output layer).
+// W1b, W2b: the weight matrices in operand order (k_weights_bf16); P: FP32 parameters (biases and
+// the output layer).
 // Writes mask[c] = (logit > thr) and, when logit is not null, the logit.
 template <typename R>
 __global__ void __launch_bounds__(64 * IND_WAVES) k_indicator(MeshDev m, double G, const double *__restrict__ Wh,
@@ -181,10 +73,10 @@ __global__ void __launch_bounds__(64 * IND_WAVES) k_indicator(MeshDev m, double 
                                                                const float *__restrict__ P, float thr,
                                                                uint8_t *__restrict__ mask, float *__restrict__ logit)
 {
-    __shared__ float feat[IND_WAVES][32][MLP_K + 1];
-    __shared__ float hid[IND_WAVES][32][MLP_H + 1];
+    __shared__ __align__(16) short feat[IND_WAVES][32][FB];
+    __shared__ __align__(16) short hid[IND_WAVES][32][HB];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 31, half = lane >> 5;
-    const int64_t T = m.T, TG = m.T + m.NG;
+    const int64_t T = m.T;
     const int64_t base = ((int64_t)blockIdx.x * IND_WAVES + wv) * 32;
     const int64_t c = base + row;
     // features: lanes 0..31 the interface level (and the geometry), lanes 32..63 h2 (and the
@@ -192,28 +84,26 @@ __global__ void __launch_bounds__(64 * IND_WAVES) k_indicator(MeshDev m, double 
     {
         float x[19];
         if (c < T) {
-            int32_t nb[9];
-#pragma unroll
-            for (int s = 0; s < 9; s++) nb[s] = m.sten[s * T + c];
-            field_features<R>(m, G, Wh, Wm, gW, half, c, nb, x);
+            field_features<R>(m, G, Wh, Wm, gW, half, c, x);
         } else {
 #pragma unroll
             for (int k = 0; k < 19; k++) x[k] = 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < 17; k++) feat[wv][row][17 * half + k] = x[k];
-        feat[wv][row][34 + half] = x[17];
-        feat[wv][row][36 + half] = x[18];
+        for (int k = 0; k < 17; k++) feat[wv][row][17 * half + k] = to_bf16(x[k]);
+        feat[wv][row][34 + half] = to_bf16(x[17]);
+        feat[wv][row][36 + half] = to_bf16(x[18]);
         if (!half) {
 #pragma unroll
-            for (int k = 0; k < 6; k++) feat[wv][row][38 + k] = c < T ? m.igeo[k * T + c] : 0.f;
+            for (int k = 0; k < 6; k++) feat[wv][row][38 + k] = to_bf16(c < T ? m.igeo[k * T + c] : 0.f);
         } else {
 #pragma unroll
-            for (int k = MLP_IN; k < MLP_K; k++) feat[wv][row][k] = 0.f;
+            for (int k = MLP_IN; k < MLP_K; k++) feat[wv][row][k] = 0;
         }
     }
     __syncthreads();
-    mlp_layer1(feat[wv], hid[wv], lane, W1b, P);
+    mlp_layer1(feat[wv], hid[wv], lane, 0, W1b, P);
+    mlp_layer1(feat[wv], hid[wv], lane, 1, W1b, P);
     __syncthreads();
     float z[16];
     mlp_layer2_out(hid[wv], lane, W2b, P, z);
@@ -235,14 +125,15 @@ __global__ void __launch_bounds__(64 * IND_WAVES) k_mlp_infer(const float *__res
                                                                const short *__restrict__ W2b,
                                                                const float *__restrict__ P, float *__restrict__ logit)
 {
-    __shared__ float feat[IND_WAVES][32][MLP_K + 1];
-    __shared__ float hid[IND_WAVES][32][MLP_H + 1];
+    __shared__ __align__(16) short feat[IND_WAVES][32][FB];
+    __shared__ __align__(16) short hid[IND_WAVES][32][HB];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, row = lane & 31, half = lane >> 5;
     const int64_t base = ((int64_t)blockIdx.x * IND_WAVES + wv) * 32;
     for (int k = half; k < MLP_K; k += 2)
-        feat[wv][row][k] = (base + row < n && k < MLP_IN) ? X[(base + row) * MLP_IN + k] : 0.f;
+        feat[wv][row][k] = to_bf16((base + row < n && k < MLP_IN) ? X[(base + row) * MLP_IN + k] : 0.f);
     __syncthreads();
-    mlp_layer1(feat[wv], hid[wv], lane, W1b, P);
+    mlp_layer1(feat[wv], hid[wv], lane, 0, W1b, P);
+    mlp_layer1(feat[wv], hid[wv], lane, 1, W1b, P);
     __syncthreads();
     float z[16];
     mlp_layer2_out(hid[wv], lane, W2b, P, z);
@@ -253,15 +144,6 @@ __global__ void __launch_bounds__(64 * IND_WAVES) k_mlp_infer(const float *__res
             if (i < n) logit[i] = z[r];
         }
     }
-}
-
-// round the two weight matrices of P to bf16 (round to nearest even); W1b [48][64] carries zero
-// rows for the input padding
-__global__ void k_weights_bf16(const float *__restrict__ P, short *__restrict__ W1b, short *__restrict__ W2b)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < MLP_K * MLP_H) W1b[i] = i < MLP_IN * MLP_H ? to_bf16(P[i]) : (short)0;
-    if (i < MLP_H * MLP_H) W2b[i] = to_bf16(P[OFF_W2 + i]);
 }
 
 // ---------------------------------------------------------------------------------------------

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gks_mlp.h"
+
 namespace gks {
 
 struct MeshDev {
@@ -182,25 +184,31 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
     q.Q0h = Q0h;
 }
 
-// reconstruction of variable v of cell c from its right-hand side; Ms points at the cell's
-// least-squares operator in LDS (entry j at Ms[32 j])
+// reconstruction of variable v of cell c: P^3 coefficients from its right-hand side (Ms points
+// at the cell's least-squares operator in LDS, entry j at Ms[32 j]), then the weights and the
+// Gauss-point values
 template <typename R>
-__device__ inline void recon_cell(const MeshDev &m, const Phys &p, const uint8_t *__restrict__ smooth,
-                                  R *__restrict__ r0, int v, bool thick, int64_t c, const ReconRhs<R> &q,
-                                  const R *Ms, ReconOut<R> &out)
+__device__ inline void recon_coeffs(const ReconRhs<R> &q, const R *Ms, R a[9])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        R s = 0;
+#pragma unroll
+        for (int r = 0; r < 17; r++) s = fma(Ms[(k * 17 + r) * RECON_CELLS], q.rhs[r], s);
+        a[k] = s;
+    }
+}
+
+// the reconstruction from the P^3 coefficients a; lin: take the linear weights (no smoothness
+// indicators)
+template <typename R>
+__device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *__restrict__ r0, int v, bool thick,
+                                  int64_t c, const ReconRhs<R> &q, const R a[9], ReconOut<R> &out)
 {
     const int64_t T = m.T;
     const R *rhs = q.rhs;
     const R hs = q.hs, Q0 = q.Q0;
     const double Q0h = q.Q0h;
-    R a[9];
-#pragma unroll
-    for (int k = 0; k < 9; k++) {
-        R s = 0;
-#pragma unroll
-        for (int r = 0; r < 17; r++) s = fma(Ms[(k * 17 + r) * RECON_CELLS], rhs[r], s);
-        a[k] = s;
-    }
     // scaled vertices (centroid at the origin) and the cell means of the basis
     const R *vt = tab<R>(m.vtx);
     R vx[3], vy[3];
@@ -241,7 +249,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, const uint8_t
     by[3] = rhs[10];
     const R d0 = R(0.8), dm = R(0.05);
     R w0 = d0, wm[4] = {dm, dm, dm, dm};
-    const bool nonlinear = !p.linear && !(smooth && smooth[c]);
+    const bool nonlinear = !p.linear && !lin;
     if (nonlinear) {
         // smoothness indicator of P^3 in scaled coordinates: the cell has area 1/2 there, so the
         // |Omega|^(|alpha|-1) weights become (1/2)^(|alpha|-1) and integrals are averages / 2.
@@ -336,19 +344,33 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, const uint8_t
         }
 }
 
-template <typename R>
+// the learned indicator inside the reconstruction: bf16 weight matrices, FP32 parameters, logit
+// threshold, and where to leave the decisions (1 = linear weights) for inspection
+struct IndArgs {
+    const short *W1b, *W2b;
+    const float *P;
+    float thr;
+    uint8_t *mask;
+};
+
+// IND: the learned indicator decides per cell whether the smoothness indicators are computed.
+// Its 44 features come from the right-hand sides the block has gathered anyway; one wave
+// evaluates the network for the block's 32 cells on the matrix cores.
+template <typename R, bool IND>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
-                                               const R *__restrict__ Wm, const R *__restrict__ gW,
-                                               const uint8_t *__restrict__ smooth, GpRecs<R> rec,
-                                               R *__restrict__ r0)
+                                               const R *__restrict__ Wm, const R *__restrict__ gW, IndArgs ind,
+                                               GpRecs<R> rec, R *__restrict__ r0)
 {
     // LDS: first the block's 32 least-squares operators, loaded once with coalesced reads and
-    // shared by the six variable threads of each cell; then, in the same space, the block's 32 x 6
-    // Gauss-point records (heads, then tails), each array written out as one contiguous span
+    // shared by the six variable threads of each cell; then, in the same space, the indicator's
+    // features and hidden activations (with IND); then the block's 32 x 6 Gauss-point records
+    // (heads, then tails), each array written out as one contiguous span
     constexpr int NR = RECON_CELLS * 6;
     constexpr int MBYTES = 153 * RECON_CELLS * (int)sizeof(R);
     constexpr int OBYTES = NR * (int)(sizeof(GpHead<R>) + sizeof(GpTail<R>));
-    __shared__ uint4 lds[(MBYTES > OBYTES ? MBYTES : OBYTES) / 16];
+    constexpr int IBYTES = IND ? RECON_CELLS * (FB + HB) * 2 + 4 * RECON_CELLS * 8 + RECON_CELLS : 0;
+    constexpr int B1 = MBYTES > OBYTES ? MBYTES : OBYTES, LBYTES = B1 > IBYTES ? B1 : IBYTES;
+    __shared__ uint4 lds[(LBYTES + 15) / 16];
     R *Ms = reinterpret_cast<R *>(lds);
     GpHead<R> *th = reinterpret_cast<GpHead<R> *>(lds);
     GpTail<R> *tt = reinterpret_cast<GpTail<R> *>(th + NR);
@@ -358,9 +380,10 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     const int64_t c0 = xcd_block() * RECON_CELLS, c = c0 + lane;
     const int64_t T = m.T;
     const int ncell = T - c0 < RECON_CELLS ? (int)(T - c0) : RECON_CELLS;
+    const bool valid = lane < ncell;
     // the cell's own gathers are issued first, so that they overlap the operator staging
     ReconRhs<R> q;
-    if (lane < ncell) recon_rhs<R>(m, Wh, Wm, gW, v, thick, c, q);
+    if (valid) recon_rhs<R>(m, Wh, Wm, gW, v, thick, c, q);
     {
         // every load of the staging is issued before the first LDS write
         constexpr int NM = 153 * RECON_CELLS, IT = (NM + 191) / 192;
@@ -378,10 +401,79 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         }
     }
     __syncthreads();
+    R a[9];
+    if (valid) recon_coeffs<R>(q, Ms + lane, a);
+    bool lin = false;
+    if constexpr (IND) {
+        __syncthreads();  // the operators are no longer needed: the space holds the network's data
+        short(*feat)[FB] = reinterpret_cast<short(*)[FB]>(lds);
+        short(*hid)[HB] = reinterpret_cast<short(*)[HB]>(&feat[RECON_CELLS][0]);
+        double *msc = reinterpret_cast<double *>(&hid[RECON_CELLS][0]);  // [4][32] momentum differences
+        uint8_t *skip = reinterpret_cast<uint8_t *>(msc + 4 * RECON_CELLS);
+        // thickness threads: their field's 17 features and size; momentum threads: their largest
+        // stencil difference
+        if (thick) {
+            const int f = v == 3 ? 0 : 1;
+            float x[18];
+            if (valid) {
+                const double h = f == 0 ? q.Q0h - m.Bbar[c] : q.Q0h;
+                thick_features<R>(q.rhs, q.Q0h, h, x);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 18; k++) x[k] = 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < 17; k++) feat[lane][17 * f + k] = to_bf16(x[k]);
+            feat[lane][34 + f] = to_bf16(x[17]);
+            if (f == 0) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) feat[lane][38 + k] = to_bf16(valid ? m.igeo[k * T + c] : 0.f);
+            } else {
+#pragma unroll
+                for (int k = MLP_IN; k < MLP_K; k++) feat[lane][k] = 0;
+            }
+        } else {
+            msc[mom_slot(v) * RECON_CELLS + lane] = valid ? max_diff<R>(q.rhs) : 0.0;
+        }
+        __syncthreads();
+        if (thick) {  // the layer's momentum feature: lower layer with eta1, upper with h2
+            const int f = v == 3 ? 0 : 1, s0 = f == 0 ? 2 : 0;
+            float y = 0.f;
+            if (valid) {
+                const double h = f == 0 ? q.Q0h - m.Bbar[c] : q.Q0h;
+                const double sm = fmax(msc[s0 * RECON_CELLS + lane], msc[(s0 + 1) * RECON_CELLS + lane]);
+                y = mom_feature(sm, h, p.G);
+            }
+            feat[lane][36 + f] = to_bf16(y);
+        }
+        __syncthreads();
+        // waves 0 and 1 take one block of 32 hidden units each
+        const int hw = threadIdx.x >> 6, hl = threadIdx.x & 63;
+        if (hw < 2) mlp_layer1(feat, hid, hl, hw, ind.W1b, ind.P);
+        __syncthreads();
+        float *zp = reinterpret_cast<float *>(msc);  // [2][32] partial logits (msc is no longer read)
+        if (hw < 2) {
+            float z[16];
+            mlp_layer2(hid, hl, hw, ind.W2b, ind.P, z);
+            if ((hl & 31) == 0) {
+                const int half = hl >> 5;
+#pragma unroll
+                for (int r = 0; r < 16; r++) zp[hw * RECON_CELLS + 8 * (r / 4) + 4 * half + (r % 4)] = z[r];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < RECON_CELLS) {
+            const float z = zp[threadIdx.x] + zp[RECON_CELLS + threadIdx.x] + ind.P[OFF_B3];
+            skip[threadIdx.x] = z > ind.thr ? 1 : 0;
+        }
+        __syncthreads();
+        lin = skip[lane] != 0;
+        if (threadIdx.x < 32 && valid && ind.mask) ind.mask[c] = lin ? 1 : 0;
+    }
     ReconOut<R> out;
-    if (lane < ncell) recon_cell<R>(m, p, smooth, r0, v, thick, c, q, Ms + lane, out);
-    __syncthreads();  // the operators are no longer needed: the space becomes the record tile
-    if (lane < ncell) {
+    if (valid) recon_cell<R>(m, p, lin, r0, v, thick, c, q, a, out);
+    __syncthreads();  // the space becomes the record tile
+    if (valid) {
 #pragma unroll
         for (int slot = 0; slot < 6; slot++) {
             const int i = 6 * lane + slot;

@@ -38,7 +38,7 @@ SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_in
 _VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
 MLP_PARAMS, MLP_FEATURES = 7105, 44
 BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 4, True),
-           "eom": (4, 22, False)}
+           "eom": (4, 22, False), "skip": (5, 1, None)}
 KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt", "indicator")
 
 
@@ -262,7 +262,10 @@ class State:
         """Intermediate array of the last stage (see gks_buffer in include/gks.h)."""
         which, rows, fp64 = BUFFERS[name]
         n = self.mesh.n_edges if name in ("eoh", "eom") else self.mesh.n_tri
-        dt = np.float64 if (fp64 or self._params[0].precision == GKS_FP64) else np.float32
+        if fp64 is None:
+            dt = np.uint8
+        else:
+            dt = np.float64 if (fp64 or self._params[0].precision == GKS_FP64) else np.float32
         out = np.zeros((rows, n), dtype=dt)
         _check(load().gks_state_buffer(self._h, which, out.ctypes.data_as(_vp), out.nbytes))
         return out

@@ -167,6 +167,26 @@ def test_indicator_logits_and_mask(gks, case):
     assert n_skip == int(mask.sum())
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fused_indicator_matches_standalone_evaluation(gks, precision):
+    """The reconstruction kernel's fused indicator takes, for every cell, the decision of the
+    stand-alone network evaluation on the same state (same features, same arithmetic)."""
+    sc = w.dam_break(20, bump_amp=0.2)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, precision=precision)
+    st.step(3)
+    P = _random_params(17)
+    st.indicator(P, 0.0)
+    z, _, _ = st.indicator_eval()
+    thr = float(np.median(z))
+    st.indicator(P, thr)
+    _, mask, _ = st.indicator_eval()
+    st.stage(0)
+    fused = st.buffer("skip")[0]
+    assert np.array_equal(fused, mask)
+    assert 0 < mask.sum() < sc.n_tri
+
+
 def test_network_inference_matches_bf16_oracle(gks):
     """The matrix-core inference against the oracle's forward pass with the same bf16 operand
     rounding, on identical float inputs (1000 rows: 31 full 32-row tiles and a ragged one)."""

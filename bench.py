@@ -90,6 +90,35 @@ def timed_steps(st, steps, warmup, graph=False):
     return e0.elapsed_time(e1)
 
 
+def source_hash():
+    """sha256 prefix over the kernel sources (names and bytes), as written into the profiles."""
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_2306_04467_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(kernel, prec):
+    """(bytes read, bytes written) per launch from the committed HBM-counter profile of this
+    workload, or None if the profile is missing or was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "gks_hbm_traffic_520k.md")
+    if not os.path.exists(path):
+        return None
+    src = source_hash()
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 6 and t[0] == "traffic" and t[1] == kernel and t[2] == prec and t[5] == f"src={src}":
+                return int(t[3]), int(t[4])
+    return None
+
+
 def kernel_roofline(st, mesh, steps, prec):
     st.profile(True)
     st.step(steps)
@@ -106,6 +135,12 @@ def kernel_roofline(st, mesh, steps, prec):
     achieved = alg[dom] / (avg / 1e3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "alg_bytes_per_launch": int(alg[dom])}
+    tr = profiled_traffic(dom, prec) if mesh.n_tri == 520200 else None
+    if tr is not None:
+        roof["traffic"] = tr[0] + tr[1]
+        roof["traffic_read_write"] = [tr[0], tr[1]]
+        roof["traffic_GBs"] = round((tr[0] + tr[1]) / (avg / 1e3) / 1e9, 1)
+        roof["traffic_source"] = "profiles/gks_hbm_traffic_520k.md (FETCH_SIZE x2, WRITE_SIZE x1 per launch)"
     return kernels, roof
 
 

@@ -147,17 +147,34 @@ def kernel_roofline(st, mesh, steps, prec):
     return kernels, roof
 
 
+AUTOTUNE = True
+
+
+def tune(st):
+    """Launch shapes chosen by the library's autotuner (outside the timed region)."""
+    if not AUTOTUNE:
+        return None
+    t0 = time.time()
+    chosen = st.autotune(reps=3)
+    out = {k: v for k, v in chosen.items() if k in ("ghost", "hhat", "plane", "flux", "update")}
+    log(f"autotune {json.dumps(out)} ({time.time() - t0:.1f}s)")
+    return out
+
+
 def run_single(sc, prec, steps, warmup, profile):
     from paper_2306_04467_amd import Mesh, State
 
     mesh = Mesh.from_scenario(sc)
     st = State.from_scenario(mesh, sc, precision=prec)
+    shapes = tune(st)
     ms = timed_steps(st, steps, warmup)
     value = mesh.n_tri * 2 * steps / (ms / 1e3)
     log(f"{prec}: {steps} steps {ms:.2f} ms, {value / 1e9:.3f} G tri-stage/s")
     kernels, roof = kernel_roofline(st, mesh, steps, prec) if profile else ({}, None)
     if profile:
         log(f"{prec} kernels: {json.dumps(kernels)}")
+    if shapes:
+        kernels["threads_per_block"] = shapes
     return mesh, value, ms / steps, kernels, roof
 
 
@@ -188,12 +205,13 @@ def run_ensemble(n_scen, steps, warmup, with_error):
         m.close()
     log(f"ensemble mesh setup {time.time() - t0:.1f}s")
     st = State.from_scenarios(bm, scs, precision="fp32")
+    shapes = tune(st)
     ms = timed_steps(st, steps, warmup, graph=True)
     value = T * 2 * steps / (ms / 1e3)
     log(f"ensemble fp32 graph: {steps} steps {ms:.2f} ms, {value / 1e9:.3f} G tri-stage/s")
     out = {"value": round(value, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5),
            "steps": steps, "n_scenarios": n_scen, "n_tri": T, "precision": "fp32-mixed",
-           "launch": "one HIP graph replay per step (all scenarios, both stages)"}
+           "launch": "one HIP graph replay per step (all scenarios, both stages)", "threads_per_block": shapes}
     if with_error:
         # error of the first three scenarios after one step, against the oracle
         import oracle
@@ -272,6 +290,7 @@ def run_indicator(n, steps, warmup, err_n, with_error):
         st = State.from_scenario(mesh, sc, precision="fp32")
         if name == "indicator":
             st.indicator(P, thr)
+        tune(st)
         ms = timed_steps(st, steps, warmup, graph=True)
         value = sc.n_tri * 2 * steps / (ms / 1e3)
         rec = {"value": round(value, 1), "ms_per_step": round(ms / steps, 5)}
@@ -329,10 +348,13 @@ def main():
     ap.add_argument("--indicator-n", type=int, default=1000,
                     help="lattice size of the learned-indicator gain case (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
+    global AUTOTUNE
+    AUTOTUNE = not args.no_autotune
     if args.copy_calibration:
         import torch
 

@@ -239,6 +239,14 @@ gks_status gks_trainer_logits(gks_trainer *tr, float *logits);
  * max_false_skip * n samples of label 0 would be skipped, with the inference arithmetic. */
 gks_status gks_trainer_threshold(gks_trainer *tr, double max_false_skip, float *threshold);
 
+/* Launch-shape autotuner (for batches and single meshes alike): for the ghost, force-model, flux
+ * and update kernels it times `reps` full steps of this state with 64, 128 and 256 threads per
+ * block, one kernel class after the other, and keeps the fastest; the state's values, time and
+ * step size are restored afterwards (results are independent of the launch shape).  chosen (may be
+ * NULL): host [GKS_KERNEL_COUNT] threads per block of each kernel class after tuning.  A captured
+ * graph is discarded.  Synchronising; allocates a copy of the state while it runs. */
+gks_status gks_autotune(gks_state *st, int32_t reps, int32_t *chosen);
+
 const char *gks_last_error(void);
 
 #ifdef __cplusplus

@@ -54,6 +54,8 @@ hipError_t upload_f32(const std::vector<double> &h, const void **d, std::vector<
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+constexpr int64_t DT_CHUNK = 4096;  // cells per block of the batched time step
+
 // bytes of the head and of the tail of one Gauss-point record
 size_t head_bytes(int prec) { return prec == GKS_FP64 ? sizeof(gks::GpHead<double>) : sizeof(gks::GpHead<float>); }
 size_t rec_bytes(int prec)
@@ -93,6 +95,8 @@ struct gks_state {
     double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
     uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
     uint8_t *need = nullptr;    // cells whose plane gradient of the force model is used
+    // threads per block of the edge and cell kernels (per kernel class), chosen by gks_autotune
+    int bs[GKS_KERNEL_COUNT] = {256, 192, 256, 256, 256, 256, 256, 256};
     int nparts = 0;
     // learned indicator: parameters, bf16 copies of the weight matrices, threshold
     bool ind_on = false;
@@ -161,7 +165,8 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
     R *Wmout = (R *)s->Wm[out], *gWout = (R *)s->gW[out];
     if (m.NG > 0)
         timed(s, st, GKS_KERNEL_GHOST, [&] {
-            hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, 256)), dim3(256), 0, st, m, Whin, Wmin, gWin);
+            const int b = s->bs[GKS_KERNEL_GHOST];
+            hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, b)), dim3(b), 0, st, m, Whin, Wmin, gWin);
         });
     timed(s, st, GKS_KERNEL_RECON, [&] {
         const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
@@ -174,19 +179,23 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
                                recs_of<R>(s->rec, m.T), (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
-        hipLaunchKernelGGL(gks::k_need<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, (const R *)s->r0, s->need);
-        hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, 256)), dim3(256), 0, st, m, s->p,
+        const int b = s->bs[GKS_KERNEL_HHAT];
+        hipLaunchKernelGGL(gks::k_need<R>, dim3(blocks(m.T, b)), dim3(b), 0, st, m, (const R *)s->r0, s->need);
+        hipLaunchKernelGGL(gks::k_hhat<R>, dim3(blocks(m.E, b)), dim3(b), 0, st, m, s->p,
                            (const gks::GpHead<R> *)s->rec, s->need, s->hmid);
     });
     timed(s, st, GKS_KERNEL_PLANE, [&] {
-        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->need, s->hmid, s->gP1);
+        const int b = s->bs[GKS_KERNEL_PLANE];
+        hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->need, s->hmid, s->gP1);
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
-        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, 256)), dim3(256), 0, st, m, s->p,
+        const int b = s->bs[GKS_KERNEL_FLUX];
+        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
                            recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
-        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, 256)), dim3(256), 0, st, m, s->p, stage,
+        const int b = s->bs[GKS_KERNEL_UPDATE];
+        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, stage,
                            s->eoh, (const R *)s->eom, Whin, Wmin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
     });
 }
@@ -201,8 +210,9 @@ void launch_dt(gks_state *s, hipStream_t st)
                                (const R *)s->Wm[0], s->part);
             hipLaunchKernelGGL(gks::k_dt_final, dim3(1), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->part, s->nparts);
         } else {
-            hipLaunchKernelGGL(gks::k_dt_batch<R>, dim3(m.S), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->Wh[0],
-                               (const R *)s->Wm[0]);
+            hipLaunchKernelGGL(gks::k_dt_chunk<R>, dim3(m.NCH), dim3(gks::DT_BLOCK), 0, st, m, s->p, s->Wh[0],
+                               (const R *)s->Wm[0], s->part);
+            hipLaunchKernelGGL(gks::k_dt_scenario, dim3(m.S), dim3(64), 0, st, m, s->p, s->part);
         }
     });
 }
@@ -272,8 +282,22 @@ gks_status upload_mesh(gks_mesh *m)
     if (h.S > 1) {
         up(h.cscen, &d.cscen);
         up(h.escen, &d.escen);
+        // time-step chunks: at most DT_CHUNK cells, never across a scenario boundary
+        std::vector<int64_t> cb{0};
+        std::vector<int32_t> sc0{0};
+        for (int32_t sn = 0; sn < h.S; sn++) {
+            for (int64_t c = h.scell[sn] + DT_CHUNK; c < h.scell[sn + 1]; c += DT_CHUNK) cb.push_back(c);
+            cb.push_back(h.scell[sn + 1]);
+            sc0.push_back((int32_t)cb.size() - 1);
+        }
+        d.NCH = (int32_t)cb.size() - 1;
+        up(cb, &d.cb);
+        up(sc0, &d.sc0);
     } else {
         d.cscen = d.escen = nullptr;
+        d.cb = nullptr;
+        d.sc0 = nullptr;
+        d.NCH = 0;
     }
     if (e != hipSuccess) return fail(GKS_ENOMEM, std::string("mesh upload: ") + hipGetErrorString(e));
     m->d32 = d;
@@ -456,7 +480,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                 {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
                 {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
                 {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
-                {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max(s->nparts, 1024) * 8},
+                {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
                 {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
     for (auto &b : bufs) {
         hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
@@ -1185,3 +1209,78 @@ gks_status gks_trainer_threshold(gks_trainer *t, double max_false_skip, float *t
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// launch-shape autotuner
+
+extern "C" gks_status gks_autotune(gks_state *s, int32_t reps, int32_t *chosen)
+{
+    if (!s || reps < 1) return fail(GKS_EINVAL, "bad autotune arguments");
+    if (s->half) return fail(GKS_EINVAL, "autotune cannot start between stage 0 and stage 1");
+    const gks::HostMesh &h = s->mesh->host;
+    const int64_t TG = h.nt + h.ng;
+    const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
+    const size_t nb[4] = {2 * (size_t)TG * 8, 4 * (size_t)TG * rs, 12 * (size_t)TG * rs, 2 * (size_t)h.S * 8};
+    void *src[4] = {s->Wh[0], s->Wm[0], s->gW[0], s->scal};
+    void *save[4] = {nullptr, nullptr, nullptr, nullptr};
+    gks_status r = GKS_OK;
+    HIP_OK(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < 4 && r == GKS_OK; i++)
+        if (hipMalloc(&save[i], nb[i]) != hipSuccess) r = fail(GKS_ENOMEM, "autotune state copy");
+    auto copy = [&](bool restore) {
+        for (int i = 0; i < 4; i++)
+            (void)hipMemcpyAsync(restore ? src[i] : save[i], restore ? save[i] : src[i], nb[i], hipMemcpyDeviceToDevice,
+                                 s->stream);
+    };
+    const bool prof_was = s->prof_on;
+    if (r == GKS_OK) {
+        copy(false);
+        drop_graph(s);
+        const int tuned[5] = {GKS_KERNEL_GHOST, GKS_KERNEL_HHAT, GKS_KERNEL_PLANE, GKS_KERNEL_FLUX, GKS_KERNEL_UPDATE};
+        const int cand[3] = {64, 128, 256};
+        for (int k : tuned) {
+            if (k == GKS_KERNEL_GHOST && h.ng == 0) continue;
+            double best = 1e300;
+            int pick = s->bs[k];
+            for (int b : cand) {
+                s->bs[k] = b;
+                copy(true);
+                s->prof.clear();
+                s->ev_used = 0;
+                s->prof_on = true;
+                for (int i = 0; i < reps; i++) {
+                    dt_any(s, s->stream);
+                    stage_any(s, 0, s->stream);
+                    stage_any(s, 1, s->stream);
+                }
+                if (hipStreamSynchronize(s->stream) != hipSuccess) {
+                    r = fail(GKS_EDEVICE, "autotune run failed");
+                    break;
+                }
+                double tot = 0;
+                for (const auto &rec : s->prof)
+                    if (rec.kernel == k) {
+                        float ms = 0;
+                        (void)hipEventElapsedTime(&ms, rec.a, rec.b);
+                        tot += ms;
+                    }
+                if (tot < best) {
+                    best = tot;
+                    pick = b;
+                }
+            }
+            s->bs[k] = pick;
+            if (r != GKS_OK) break;
+        }
+        copy(true);
+        (void)hipStreamSynchronize(s->stream);
+    }
+    s->prof.clear();
+    s->ev_used = 0;
+    s->prof_on = prof_was;
+    for (void *p : save)
+        if (p) (void)hipFree(p);
+    if (r == GKS_OK && chosen)
+        for (int k = 0; k < GKS_KERNEL_COUNT; k++) chosen[k] = s->bs[k];
+    return r;
+}

@@ -35,6 +35,11 @@ struct MeshDev {
     const float *igeo;              // [6][T] indicator geometry
     const int32_t *cedge, *sten, *eL, *eR, *eslot, *gsrc;
     const int32_t *cscen, *escen;   // scenario of each cell / edge, nullptr when S == 1
+    // batches: the cells cut into chunks that never straddle two scenarios, chunk c covering
+    // [cb[c], cb[c + 1]); scenario s owns chunks [sc0[s], sc0[s + 1])
+    const int64_t *cb;
+    const int32_t *sc0;
+    int32_t NCH;
     const int64_t *scell;           // [S + 1] first cell of each scenario
 };
 
@@ -1143,18 +1148,29 @@ __global__ void __launch_bounds__(DT_BLOCK) k_dt_final(MeshDev m, Phys p, const 
     if (threadIdx.x == 0) set_step(m, p, 0, v);
 }
 
-// one block per scenario of a batch
+// batches: one block per chunk of cells (the chunk's largest wave speed), then one block per
+// scenario over its chunks
 template <typename R>
-__global__ void __launch_bounds__(DT_BLOCK) k_dt_batch(MeshDev m, Phys p, const double *__restrict__ Wh,
-                                                        const R *__restrict__ Wm)
+__global__ void __launch_bounds__(DT_BLOCK) k_dt_chunk(MeshDev m, Phys p, const double *__restrict__ Wh,
+                                                        const R *__restrict__ Wm, double *__restrict__ part)
 {
     __shared__ double sh[DT_BLOCK / 64];
-    const int s = blockIdx.x;
+    const int ch = blockIdx.x;
     double smax = 0;
-    for (int64_t c = m.scell[s] + threadIdx.x; c < m.scell[s + 1]; c += blockDim.x)
+    for (int64_t c = m.cb[ch] + threadIdx.x; c < m.cb[ch + 1]; c += blockDim.x)
         smax = fmax(smax, wave_speed(m, p, Wh, Wm, c));
     smax = block_max(smax, sh);
-    if (threadIdx.x == 0) set_step(m, p, s, smax);
+    if (threadIdx.x == 0) part[ch] = smax;
+}
+
+__global__ void __launch_bounds__(64) k_dt_scenario(MeshDev m, Phys p, const double *__restrict__ part)
+{
+    const int s = blockIdx.x;
+    double v = 0;
+    for (int i = m.sc0[s] + threadIdx.x; i < m.sc0[s + 1]; i += 64) v = fmax(v, part[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if (threadIdx.x == 0) set_step(m, p, s, v);
 }
 
 __global__ void k_set_dt(Phys p, double dt)

@@ -34,7 +34,7 @@ SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_in
            "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
            "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
            "gks_trainer_info", "gks_trainer_grad", "gks_trainer_fit", "gks_trainer_params", "gks_trainer_logits",
-           "gks_trainer_threshold", "gks_last_error")
+           "gks_trainer_threshold", "gks_autotune", "gks_last_error")
 _VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
 MLP_PARAMS, MLP_FEATURES = 7105, 44
 BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 4, True),
@@ -100,6 +100,7 @@ def load():
     lib.gks_trainer_params.argtypes = [_vp, _fp]
     lib.gks_trainer_logits.argtypes = [_vp, _fp]
     lib.gks_trainer_threshold.argtypes = [_vp, ctypes.c_double, _fp]
+    lib.gks_autotune.argtypes = [_vp, ctypes.c_int32, _i32p]
     for name in SYMBOLS:
         if name not in _VOID:
             getattr(lib, name).restype = ctypes.c_int
@@ -269,6 +270,13 @@ class State:
         out = np.zeros((rows, n), dtype=dt)
         _check(load().gks_state_buffer(self._h, which, out.ctypes.data_as(_vp), out.nbytes))
         return out
+
+    def autotune(self, reps=3):
+        """Pick the threads per block of the edge and cell kernels by timing; returns
+        {kernel class: threads per block}.  The state's values are restored."""
+        out = (ctypes.c_int32 * len(KERNELS))()
+        _check(load().gks_autotune(self._h, int(reps), out))
+        return dict(zip(KERNELS, list(out)))
 
     def profile(self, enable=True):
         _check(load().gks_profile(self._h, int(bool(enable))))

@@ -132,6 +132,30 @@ def test_batch_graph_replay_matches_eager_steps(gks):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def test_autotune_restores_the_state_and_changes_no_result(gks):
+    """The autotuner times several launch shapes on the state itself; afterwards the state is the
+    one it was given, and the chosen shapes give the same results bit for bit (graph replay)."""
+    scs = _small_ensemble()
+    bm = gks.Mesh.batch([gks.Mesh.from_scenario(sc) for sc in scs])
+    ref = gks.State.from_scenarios(bm, scs, precision="fp32")
+    tuned = gks.State.from_scenarios(bm, scs, precision="fp32")
+    tuned.step(2)
+    ref.step(2)
+    W0, gW0, _ = tuned.read()
+    t0 = [tuned.time(i) for i in range(len(scs))]
+    chosen = tuned.autotune(reps=2)
+    W1, gW1, _ = tuned.read()
+    assert np.array_equal(W0, W1) and np.array_equal(gW0, gW1)
+    assert [tuned.time(i) for i in range(len(scs))] == t0
+    for k in ("ghost", "hhat", "plane", "flux", "update"):
+        assert chosen[k] in (64, 128, 256), chosen
+    tuned.batch_step(4)
+    ref.batch_step(4)
+    Wa, gWa, _ = tuned.read()
+    Wr, gWr, _ = ref.read()
+    assert np.array_equal(Wa, Wr) and np.array_equal(gWa, gWr)
+
+
 def test_batch_scenario_against_oracle(gks):
     scs = _small_ensemble()
     bm = gks.Mesh.batch([gks.Mesh.from_scenario(sc) for sc in scs])

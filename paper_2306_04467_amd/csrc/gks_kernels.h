@@ -722,19 +722,22 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     const R thL = R(0.5) * G * sl.h, thR = R(0.5) * G * sr.h;
     const R spi = R(1.7724538509055160273);  // sqrt(pi)
     R ML[6], MR[6], eL, eR;
+    // half-space masses from one error function per Gaussian: 1/2 erfc(-x) = 1/2 (1 + erf(x))
+    // (exactly 1/2 at rest; where erf(x) is close to -1 the lost relative digits of the tiny mass
+    // are below the absolute rounding of the moments it enters)
     {
         const R sq = sqrt_(lamL);
-        const R m0 = R(0.5) * erfc_(-sq * sl.U);
+        eL = erf_(sq * sl.U);  // 2 (M0 - 1/2)
+        const R m0 = R(0.5) + R(0.5) * eL;
         const R ex = exp_(-lamL * sl.U * sl.U) / (2 * spi * sq);
         u_moments(sl.U, thL, m0, sl.U * m0 + ex, ML);
-        eL = erf_(sq * sl.U);  // 2 (M0 - 1/2)
     }
     {
         const R sq = sqrt_(lamR);
-        const R m0 = R(0.5) * erfc_(sq * sr.U);
+        eR = -erf_(sq * sr.U);
+        const R m0 = R(0.5) + R(0.5) * eR;  // 1/2 erfc(x)
         const R ex = exp_(-lamR * sr.U * sr.U) / (2 * spi * sq);
         u_moments(sr.U, thR, m0, sr.U * m0 - ex, MR);
-        eR = -erf_(sq * sr.U);
     }
     // interface equilibrium state: thickness as an FP64 base plus a deviation that is 0 at rest
     const R hdev = R(0.5) * (sl.h * eL + sr.h * eR);
@@ -746,7 +749,8 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     R Mp[6], Mm[6];
     {
         const R sq = sqrt_(lamb);
-        const R m0p = R(0.5) * erfc_(-sq * Ub), m0m = R(0.5) * erfc_(sq * Ub);
+        const R eb = erf_(sq * Ub);
+        const R m0p = R(0.5) + R(0.5) * eb, m0m = R(0.5) - R(0.5) * eb;
         const R ex = exp_(-lamb * Ub * Ub) / (2 * spi * sq);
         u_moments(Ub, thb, m0p, Ub * m0p + ex, Mp);
         u_moments(Ub, thb, m0m, Ub * m0m - ex, Mm);

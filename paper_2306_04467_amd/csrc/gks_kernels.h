@@ -192,14 +192,15 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
 // reconstruction of variable v of cell c: P^3 coefficients from its right-hand side (Ms points
 // at the cell's least-squares operator in LDS, entry j at Ms[32 j]), then the weights and the
 // Gauss-point values
-template <typename R>
+// coefficients k0 <= k < k1 of the P^3 fit; Ms holds the operator rows from row 17 k0 on
+template <int k0, int k1, typename R>
 __device__ inline void recon_coeffs(const ReconRhs<R> &q, const R *Ms, R a[9])
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = k0; k < k1; k++) {
         R s = 0;
 #pragma unroll
-        for (int r = 0; r < 17; r++) s = fma(Ms[(k * 17 + r) * RECON_CELLS], q.rhs[r], s);
+        for (int r = 0; r < 17; r++) s = fma(Ms[((k - k0) * 17 + r) * RECON_CELLS], q.rhs[r], s);
         a[k] = s;
     }
 }
@@ -371,7 +372,10 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     // features and hidden activations (with IND); then the block's 32 x 6 Gauss-point records
     // (heads, then tails), each array written out as one contiguous span
     constexpr int NR = RECON_CELLS * 6;
-    constexpr int MBYTES = 153 * RECON_CELLS * (int)sizeof(R);
+    // the operator is staged in two parts (rows of coefficients 0..4, then 5..8), both loaded at
+    // once into registers, so that the LDS holds only the larger part
+    constexpr int ROWS1 = 5 * 17, ROWS2 = 153 - ROWS1;
+    constexpr int MBYTES = ROWS1 * RECON_CELLS * (int)sizeof(R);
     constexpr int OBYTES = NR * (int)(sizeof(GpHead<R>) + sizeof(GpTail<R>));
     constexpr int IBYTES = IND ? RECON_CELLS * (FB + HB) * 2 + 4 * RECON_CELLS * 8 + RECON_CELLS : 0;
     constexpr int B1 = MBYTES > OBYTES ? MBYTES : OBYTES, LBYTES = B1 > IBYTES ? B1 : IBYTES;
@@ -389,9 +393,10 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     // the cell's own gathers are issued first, so that they overlap the operator staging
     ReconRhs<R> q;
     if (valid) recon_rhs<R>(m, Wh, Wm, gW, v, thick, c, q);
+    R a[9];
     {
         // every load of the staging is issued before the first LDS write
-        constexpr int NM = 153 * RECON_CELLS, IT = (NM + 191) / 192;
+        constexpr int NM = 153 * RECON_CELLS, NM1 = ROWS1 * RECON_CELLS, IT = (NM + 191) / 192;
         const R *M = tab<R>(m.M);
         R buf[IT];
 #pragma unroll
@@ -402,12 +407,19 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
 #pragma unroll
         for (int it = 0; it < IT; it++) {
             const int i = (int)threadIdx.x + 192 * it;
-            if (i < NM) Ms[i] = buf[it];
+            if (i < NM1) Ms[i] = buf[it];
         }
+        __syncthreads();
+        if (valid) recon_coeffs<0, 5, R>(q, Ms + lane, a);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < IT; it++) {
+            const int i = (int)threadIdx.x + 192 * it;
+            if (i >= NM1 && i < NM) Ms[i - NM1] = buf[it];
+        }
+        __syncthreads();
+        if (valid) recon_coeffs<5, 9, R>(q, Ms + lane, a);
     }
-    __syncthreads();
-    R a[9];
-    if (valid) recon_coeffs<R>(q, Ms + lane, a);
     bool lin = false;
     if constexpr (IND) {
         __syncthreads();  // the operators are no longer needed: the space holds the network's data

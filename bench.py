@@ -161,6 +161,28 @@ def tune(st):
     return out
 
 
+def copy_bandwidth():
+    """Read + write bandwidth of a plain 1 GiB device-to-device copy on this GPU (the practical
+    HBM ceiling next to the nominal 8 TB/s)."""
+    import torch
+
+    x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * x.numel() * 8 / (e0.elapsed_time(e1) / 20 / 1e3) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def run_single(sc, prec, steps, warmup, profile):
     from paper_2306_04467_amd import Mesh, State
 
@@ -363,7 +385,15 @@ def main():
         for _ in range(5):
             y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read_per_launch": x.numel() * 8, "copy_bytes_written_per_launch": x.numel() * 8}))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            y.copy_(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        print(json.dumps({"copy_bytes_read_per_launch": x.numel() * 8, "copy_bytes_written_per_launch": x.numel() * 8,
+                          "copy_ms": round(ms, 4), "copy_GBs_read_plus_written": round(2 * x.numel() * 8 / (ms / 1e3) / 1e9, 1)}))
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -384,6 +414,15 @@ def main():
         res[prec] = run_single(sc, prec, args.steps, args.warmup, not args.no_profile)
     head = precs[0]
     mesh, value, ms_step, kernels, roof = res[head]
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.1f} GB/s read + written")
+    for prec in precs:
+        r = res[prec][4]
+        if r:
+            r["copy_GBs"] = round(copy_gbs, 1)
+            r["frac_of_copy"] = round(r["achieved"] / copy_gbs, 4)
+            if r.get("traffic_GBs"):
+                r["traffic_frac_of_copy"] = round(r["traffic_GBs"] / copy_gbs, 4)
 
     cpu, errs = None, {}
     if not args.no_cpu_baseline:

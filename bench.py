@@ -210,7 +210,7 @@ def one_step_error(mesh, sc, prec, Wr, dt):
     return rel_l1(W, Wr, sc_area(sc), sc.G)
 
 
-def run_ensemble(n_scen, steps, warmup, with_error):
+def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
     import numpy as np
 
     import workloads
@@ -234,22 +234,46 @@ def run_ensemble(n_scen, steps, warmup, with_error):
     out = {"value": round(value, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5),
            "steps": steps, "n_scenarios": n_scen, "n_tri": T, "precision": "fp32-mixed",
            "launch": "one HIP graph replay per step (all scenarios, both stages)", "threads_per_block": shapes}
+    st.close()
+    if indicator is not None:
+        # the same batch with the learned indicator fused into the reconstruction
+        P, thr = indicator
+        sti = State.from_scenarios(bm, scs, precision="fp32")
+        sti.indicator(P, thr)
+        tune(sti)
+        msi = timed_steps(sti, steps, warmup, graph=True)
+        vi = T * 2 * steps / (msi / 1e3)
+        _, _, k = sti.indicator_eval()
+        log(f"ensemble fp32 + indicator graph: {steps} steps {msi:.2f} ms, {vi / 1e9:.3f} G tri-stage/s, "
+            f"skipped {k / T:.3f}")
+        out["with_indicator"] = {"value": round(vi, 1), "ms_per_step": round(msi / steps, 5),
+                                 "skipped_fraction_end": round(k / T, 4)}
+        sti.close()
     if with_error:
         # error of the first three scenarios after one step, against the oracle
         import oracle
 
-        st2 = State.from_scenarios(bm, scs, precision="fp32")
-        st2.step(1)
-        W, _, _ = st2.read()
-        errs = []
+        refs = []
         for i in range(3):
             sc = scs[i]
             om = oracle.Mesh.from_scenario(sc)
             p = oracle.params_of(sc)
             Wr, _ = oracle.step(om, p, oracle.dt(om, p, sc.W0), sc.W0, sc.gradW0)
-            c0, n = bm.scenario_range(i)
-            errs.append(rel_l1(W[:, c0:c0 + n], Wr, sc_area(sc), sc.G))
-        out["rel_l1_vs_oracle_1step_first3"] = float(np.max(errs))
+            refs.append(Wr)
+        for key, ind in (("rel_l1_vs_oracle_1step_first3", None), ("rel_l1_vs_oracle_1step_first3_indicator", indicator)):
+            if key.endswith("indicator") and ind is None:
+                continue
+            st2 = State.from_scenarios(bm, scs, precision="fp32")
+            if ind is not None:
+                st2.indicator(*ind)
+            st2.step(1)
+            W, _, _ = st2.read()
+            errs = []
+            for i in range(3):
+                c0, n = bm.scenario_range(i)
+                errs.append(rel_l1(W[:, c0:c0 + n], refs[i], sc_area(scs[i]), scs[i].G))
+            out[key] = float(np.max(errs))
+            st2.close()
     return out
 
 
@@ -292,7 +316,7 @@ def train_indicator(label_tol=1e-7, snapshots=6, every=10, epochs=8, batch=2048,
     return tr.params(), thr, info
 
 
-def run_indicator(n, steps, warmup, err_n, with_error):
+def run_indicator(n, steps, warmup, err_n, with_error, trained=None):
     """Gain case: dam break plus bump on a 2 n^2-triangle mesh, FP32 mixed, with and without the
     learned indicator; rel-L1 error of both against the FP64 oracle after 20 steps on a smaller
     mesh of the same shape."""
@@ -301,7 +325,7 @@ def run_indicator(n, steps, warmup, err_n, with_error):
     import workloads
     from paper_2306_04467_amd import Mesh, State
 
-    P, thr, info = train_indicator()
+    P, thr, info = trained if trained is not None else train_indicator()
     t0 = time.time()
     sc = workloads.dam_break(n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
     mesh = Mesh.from_scenario(sc)
@@ -447,10 +471,13 @@ def main():
         extra["fp32_mixed"] = {"value": round(v32, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms32, 5),
                                "speedup_vs_fp64": round(v32 / value, 3), "rel_l1_vs_oracle_1step": errs.get("fp32"),
                                "roofline": r32, "kernels": k32}
+    trained = train_indicator() if (args.ensemble > 0 or args.indicator_n > 0) else None
     if args.ensemble > 0:
-        extra["ensemble"] = run_ensemble(args.ensemble, 50, 5, not args.no_cpu_baseline)
+        extra["ensemble"] = run_ensemble(args.ensemble, 50, 5, not args.no_cpu_baseline,
+                                         indicator=(trained[0], trained[1]))
     if args.indicator_n > 0:
-        extra["fp32_learned_indicator"] = run_indicator(args.indicator_n, 50, 5, 160, not args.no_cpu_baseline)
+        extra["fp32_learned_indicator"] = run_indicator(args.indicator_n, 50, 5, 160, not args.no_cpu_baseline,
+                                                        trained=trained)
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "triangle-stage/s", "n_gpus": 1,

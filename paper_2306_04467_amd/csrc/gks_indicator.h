@@ -7,7 +7,7 @@
 //             neighbours, s = max_l |Q_l - Q_0| + 1e-12 |Q_0|; the size of the variation,
 //             log10(s / h)/4, and of the layer's momentum variation against h sqrt(G h); then the
 //             face neighbours' area ratios and the cell's edge lengths over hs (static, from the mesh)
-//   inference BF16 MFMA (v_mfma_f32_32x32x8_bf16), FP32 accumulation, one wave per 32 cells; the
+//   inference BF16 MFMA (v_mfma_f32_32x32x16_bf16), FP32 accumulation, 32 cells per wave; the
 //             44 inputs are padded with zeros to 48 (six K-steps of 8)
 //   training  FP32: per-sample forward and backward deltas, deterministic weight-gradient sums
 //             (one thread per parameter, fixed order over the batch), Adam

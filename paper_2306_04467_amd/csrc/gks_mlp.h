@@ -13,7 +13,8 @@ constexpr int OFF_B1 = MLP_IN * MLP_H, OFF_W2 = OFF_B1 + MLP_H, OFF_B2 = OFF_W2 
               OFF_W3 = OFF_B2 + MLP_H, OFF_B3 = OFF_W3 + MLP_H;
 
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ inline short to_bf16(float x)
@@ -25,15 +26,21 @@ __device__ inline short to_bf16(float x)
 
 constexpr int IND_WAVES = 4;
 
-// LDS row strides (in bf16 elements) of the feature and hidden-activation tiles: multiples of 4
-// (8-byte aligned operand reads), not of 64 (bank spread)
-constexpr int FB = MLP_K + 4, HB = MLP_H + 4;
+// LDS row strides (in bf16 elements) of the feature and hidden-activation tiles: multiples of 8
+// (16-byte aligned operand reads), not of 64 (bank spread)
+constexpr int FB = MLP_K + 8, HB = MLP_H + 8;
+
+// eight bf16 operands (stored as their bit patterns) for the matrix core
+__device__ inline bf16x8 bf16_operand(const short *p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8 *>(p));
+}
 
 // The network on 32 rows held in LDS as bf16: featb[32][FB] (features, zero padded to 48),
 // hidb[32][HB] (first hidden layer), one wave per block of 32 hidden units.  The matrix products use
-// v_mfma_f32_32x32x8_bf16: lane l supplies row l%32 of A and column l%32 of B for
-// k = 4 (l/32) + 0..3; accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4, column
-// l%32.  The weights come pre-arranged in that operand order (k_weights_bf16), four bf16 per lane
+// v_mfma_f32_32x32x16_bf16: lane l supplies row l%32 of A and column l%32 of B for
+// k = 8 (l/32) + 0..7; accumulator register r of lane l holds row 8 (r/4) + 4 (l/32) + r%4, column
+// l%32.  The weights come pre-arranged in that operand order (k_weights_bf16), eight bf16 per lane
 // and step.  The caller synchronises between the two halves.
 __device__ inline void mlp_layer1(const short (*featb)[FB], short (*hidb)[HB], int lane, int nbk,
                                   const short *__restrict__ W1r, const float *__restrict__ P)
@@ -42,10 +49,10 @@ __device__ inline void mlp_layer1(const short (*featb)[FB], short (*hidb)[HB], i
     const int row = lane & 31, half = lane >> 5;
     f32x16 acc = f32x16{0};
 #pragma unroll
-    for (int s = 0; s < MLP_K / 8; s++) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&featb[row][8 * s + 4 * half]);
-        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W1r + ((nbk * (MLP_K / 8) + s) * 64 + lane) * 4);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int s = 0; s < MLP_K / 16; s++) {
+        const bf16x8 a = bf16_operand(&featb[row][16 * s + 8 * half]);
+        const bf16x8 b = bf16_operand(W1r + ((nbk * (MLP_K / 16) + s) * 64 + lane) * 8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     const float bias = P[OFF_B1 + 32 * nbk + row];
 #pragma unroll
@@ -62,10 +69,10 @@ __device__ inline void mlp_layer2(const short (*hidb)[HB], int lane, int nbk, co
     const int row = lane & 31, half = lane >> 5;
     f32x16 acc = f32x16{0};
 #pragma unroll
-    for (int s = 0; s < MLP_H / 8; s++) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&hidb[row][8 * s + 4 * half]);
-        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(W2r + ((nbk * (MLP_H / 8) + s) * 64 + lane) * 4);
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+    for (int s = 0; s < MLP_H / 16; s++) {
+        const bf16x8 a = bf16_operand(&hidb[row][16 * s + 8 * half]);
+        const bf16x8 b = bf16_operand(W2r + ((nbk * (MLP_H / 16) + s) * 64 + lane) * 8);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     // column j lives in lane j of each half: reduce over the half's 32 lanes
     const float b2 = P[OFF_B2 + 32 * nbk + row], w3 = P[OFF_W3 + 32 * nbk + row];
@@ -90,20 +97,20 @@ __device__ inline void mlp_layer2_out(const short (*hidb)[HB], int lane, const s
     for (int r = 0; r < 16; r++) z[r] = z[r] + z1[r] + b3;
 }
 
-// The weight matrices in the operand order of mlp_layer1 / mlp_layer2_out, bf16 (round to nearest
-// even): element ((nbk * steps + s) * 64 + l) * 4 + i holds W[k][col] with k = 8 s + 4 (l / 32) + i,
+// The weight matrices in the operand order of mlp_layer1 / mlp_layer2, bf16 (round to nearest
+// even): element ((nbk * steps + s) * 64 + l) * 8 + i holds W[k][col] with k = 16 s + 8 (l / 32) + i,
 // col = 32 nbk + l % 32; W1 rows 44..47 (input padding) are zero.  W1r [3072], W2r [4096].
 __global__ void k_weights_bf16(const float *__restrict__ P, short *__restrict__ W1r, short *__restrict__ W2r)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ii = i & 3, l = (i >> 2) & 63, blk = i >> 8;
-    const int k0 = 4 * (l >> 5) + ii, col = (l & 31);
+    const int ii = i & 7, l = (i >> 3) & 63, blk = i >> 9;
+    const int k0 = 8 * (l >> 5) + ii, col = (l & 31);
     if (i < MLP_K * MLP_H) {
-        const int nbk = blk / (MLP_K / 8), s = blk % (MLP_K / 8), k = 8 * s + k0;
+        const int nbk = blk / (MLP_K / 16), s = blk % (MLP_K / 16), k = 16 * s + k0;
         W1r[i] = k < MLP_IN ? to_bf16(P[k * MLP_H + 32 * nbk + col]) : (short)0;
     }
     if (i < MLP_H * MLP_H) {
-        const int nbk = blk / (MLP_H / 8), s = blk % (MLP_H / 8), k = 8 * s + k0;
+        const int nbk = blk / (MLP_H / 16), s = blk % (MLP_H / 16), k = 16 * s + k0;
         W2r[i] = to_bf16(P[OFF_W2 + k * MLP_H + 32 * nbk + col]);
     }
 }

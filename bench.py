@@ -420,8 +420,8 @@ def main():
                           "copy_ms": round(ms, 4), "copy_GBs_read_plus_written": round(2 * x.numel() * 8 / (ms / 1e3) / 1e9, 1)}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py: this implementation runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the decomposition over several GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
 
     import torch

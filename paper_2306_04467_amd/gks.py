@@ -59,7 +59,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run python paper_2306_04467_amd/build.py)")
     # stream handles come from torch: load torch's HIP runtime first so that the library binds to
     # the same one
     import torch  # noqa: F401

@@ -108,8 +108,9 @@ void gks_state_destroy(gks_state *st);
  * (the step size is reused). */
 gks_status gks_stage(gks_state *st, int32_t stage, const double *dt);
 /* n_steps full steps, every scenario with its own CFL time step computed on the device (no host
- * synchronisation).  If dt_last is not NULL the call synchronises and returns the last step size
- * of scenario 0.  GKS_EINVAL if called between stage 0 and stage 1. */
+ * synchronisation).  A scenario that has reached its t_end is left unchanged by later steps.  If
+ * dt_last is not NULL the call synchronises and returns the last step size of scenario 0.
+ * GKS_EINVAL if called between stage 0 and stage 1. */
 gks_status gks_step(gks_state *st, int32_t n_steps, double *dt_last);
 /* The same n_steps steps replayed from a HIP graph that holds one captured step (time step and
  * both stages of every scenario); the graph is captured on the first call on a private stream

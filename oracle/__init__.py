@@ -48,7 +48,8 @@ def load():
     lib.om_mesh_n_edges.restype = ctypes.c_int
     lib.om_stencil.argtypes = [ctypes.c_void_p, ctypes.c_int, _ip, _dp]
     lib.om_lsq_matrix.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp]
-    lib.om_reconstruct_cell.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp, _dp, _dp]
+    lib.om_reconstruct_cell.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.c_int, ctypes.c_double,
+                                        _dp, _dp, _dp]
     lib.om_gks_point.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, _dp, _dp, _dp, _dp]
     lib.om_gks_point_integrated.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
@@ -156,12 +157,12 @@ class Mesh:
         load().om_lsq_matrix(self._h, c, _d(M))
         return M
 
-    def reconstruct(self, c, W, gW, linear=False):
+    def reconstruct(self, c, W, gW, linear=False, G=9.81):
         W, gW = _f64(W), _f64(gW)
         val = np.zeros((6, 6))
         grad = np.zeros((6, 6, 2))
         r0 = np.zeros(6)
-        load().om_reconstruct_cell(self._h, c, _d(W), _d(gW), int(linear), _d(val), _d(grad), _d(r0))
+        load().om_reconstruct_cell(self._h, c, _d(W), _d(gW), int(linear), float(G), _d(val), _d(grad), _d(r0))
         return val, grad, r0
 
 

@@ -639,7 +639,7 @@ static double beta_cubic(const double *a, const double v0[3][2], const double *x
     return area * s1 + area * area * s2 + area * area * area * s3;
 }
 
-void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear,
+void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                          double *val, double *grad, double *r0)
 {
     const double d0 = 0.8, dm = 0.05; /* reading: linear weights of the WENO-AO combination */
@@ -702,7 +702,15 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
                 tauz += fabs(beta0 - betam[s]);
             }
             tauz *= 0.25;
-            double eps = 1e-10 * fmax(Q0 * Q0, 1e-20);
+            /* reading: the floor of the smoothness indicators carries the variable's scale, the
+             * level itself for a thickness and h sqrt(G h) of the layer for a momentum, so that
+             * round-off about a state at rest stays under the linear weights */
+            double S2 = 1e-20;
+            if (v != 0 && v != 3) {
+                double hl = W[(v < 3 ? 0 : 3) * m->nt + c];
+                S2 = G * hl * hl * hl;
+            }
+            double eps = 1e-10 * fmax(Q0 * Q0, S2);
             double wt0 = d0 * (1 + tauz / (beta0 + eps)), wts[4], sum = wt0;
             for (int s = 0; s < 4; s++) {
                 wts[s] = dm * (1 + tauz / (betam[s] + eps));
@@ -993,7 +1001,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     double *grd = (double *)malloc(sizeof(double) * (size_t)T * 72);
     double *r0 = (double *)malloc(sizeof(double) * (size_t)T * 6);
     for (int c = 0; c < T; c++)
-        om_reconstruct_cell(m, c, W, gW, p->linear, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6);
+        om_reconstruct_cell(m, c, W, gW, p->linear, p->G, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6);
 
     /* side records of edge e, Gauss point g (edge orientation), side s: pointers or mirrors */
 #define REC_VAL(c, k, g) (val + (size_t)(c) * 36 + (2 * (k) + (g)) * 6)

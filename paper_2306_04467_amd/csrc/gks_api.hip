@@ -196,7 +196,7 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
         const int b = s->bs[GKS_KERNEL_UPDATE];
         hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, stage,
-                           s->eoh, (const R *)s->eom, Whin, Wmin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+                           s->eoh, (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
     });
 }
 

@@ -150,6 +150,7 @@ struct ReconRhs {
     R rhs[17];  // average differences, then scaled gradients of the cell and its face neighbours
     R hs, Q0;
     double Q0h;  // cell average of a thickness in double
+    double hl;   // momenta: thickness of the variable's layer (scale of the smoothness floor)
 };
 
 template <typename R>
@@ -176,6 +177,7 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
         Q0 = Q[c];
 #pragma unroll
         for (int s = 0; s < 9; s++) rhs[s] = Q[nb[s]] - Q0;
+        q.hl = v < 3 ? Wh[c] : Wh[TG + c] - m.Bbar[c];
     }
     rhs[9] = hs * gW[(2 * v) * TG + c];
     rhs[10] = hs * gW[(2 * v + 1) * TG + c];
@@ -294,7 +296,10 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
             tz += fabs(beta0 - bm[s]);
         }
         tz *= R(0.25);
-        const R epsw = R(1e-10) * fmax(Q0 * Q0, R(1e-20));
+        // floor of the smoothness indicators with the variable's scale: the level of a thickness,
+        // h sqrt(G h) of the layer for a momentum (round-off about rest stays under linear weights)
+        const R S2 = thick ? R(1e-20) : (R)(p.G * q.hl * q.hl * q.hl);
+        const R epsw = R(1e-10) * fmax(Q0 * Q0, S2);
         const R t0 = d0 * (1 + tz / (beta0 + epsw));
         R sum = t0, tm[4];
 #pragma unroll
@@ -862,6 +867,9 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     const int64_t T = m.T, E = m.E;
     const int sc = m.escen ? m.escen[e] : 0;
     const R dt = (R)p.scal[2 * sc];
+    // a scenario that has reached its end time takes zero-length steps: nothing to evolve (both
+    // lanes of a Gauss-point pair belong to the same edge and leave together)
+    if (p.scal[2 * sc] == 0.0) return;
     const R chi = (R)p.chi[sc], G = (R)p.G;
     const int32_t L = m.eL[e], Rc = m.eR[e], sl = m.eslot[e];
     const int kL = sl & 3, kR = sl >> 2;
@@ -997,15 +1005,36 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 template <typename R>
 __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, int stage, const double *__restrict__ eoh,
                                                 const R *__restrict__ eom, const double *__restrict__ Whin,
-                                                const R *__restrict__ Wmin, double *__restrict__ Whout,
-                                                R *__restrict__ Wmout, R *__restrict__ gWout,
-                                                double *__restrict__ Wc, R *__restrict__ Gc)
+                                                const R *__restrict__ Wmin, const R *__restrict__ gWin,
+                                                double *__restrict__ Whout, R *__restrict__ Wmout,
+                                                R *__restrict__ gWout, double *__restrict__ Wc, R *__restrict__ Gc)
 {
     int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T, E = m.E, TG = m.T + m.NG;
     const int sc = m.cscen ? m.cscen[c] : 0;
     const double dt = p.scal[2 * sc], G = p.G, chi = p.chi[sc];
+    if (dt == 0.0) {
+        // the scenario has reached its end time: the state stays as it is (the stage's output is
+        // its input; stage 0 also leaves the carry equal to it for stage 1)
+#pragma unroll
+        for (int v = 0; v < 6; v++) {
+            const double w = stage == 0 ? ((v == 0) ? Whin[c] : (v == 3) ? Whin[TG + c] : (double)Wmin[mom_slot(v) * TG + c])
+                                        : Wc[v * T + c];
+            if (v == 0 || v == 3)
+                Whout[(v == 3 ? TG : 0) + c] = w;
+            else
+                Wmout[mom_slot(v) * TG + c] = (R)w;
+            if (stage == 0) Wc[v * T + c] = w;
+#pragma unroll
+            for (int d = 0; d < 2; d++) {
+                const R g = stage == 0 ? gWin[(2 * v + d) * TG + c] : Gc[(2 * v + d) * T + c];
+                gWout[(2 * v + d) * TG + c] = g;
+                if (stage == 0) Gc[(2 * v + d) * T + c] = g;
+            }
+        }
+        return;
+    }
     double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}}, hs[2] = {0, 0}, hts[2] = {0, 0};
 #pragma unroll
     for (int k = 0; k < 3; k++) {

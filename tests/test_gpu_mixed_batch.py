@@ -132,6 +132,34 @@ def test_batch_graph_replay_matches_eager_steps(gks):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+def test_scenarios_stop_at_their_end_times(gks):
+    """A scenario that reaches its t_end stays unchanged by later steps while the others go on:
+    the finished one equals its own single run stopped at t_end, bit for bit."""
+    scs = _small_ensemble()
+    t_ends = [0.004, 0.0, 0.011]              # 0: no end time
+    for sc, te in zip(scs, t_ends):
+        sc.t_end = te if te > 0 else 1e300
+    singles = []
+    for sc, te in zip(scs, t_ends):
+        st = gks.State.from_scenario(gks.Mesh.from_scenario(sc), sc, t_end=te)
+        st.step(30)
+        singles.append(st.read())
+    bm = gks.Mesh.batch([gks.Mesh.from_scenario(sc) for sc in scs])
+    bs = gks.State.from_scenarios(bm, scs)
+    bs.batch_step(30)
+    Wb, gWb, _ = bs.read()
+    for i, (sc, te) in enumerate(zip(scs, t_ends)):
+        c0, n = bm.scenario_range(i)
+        W, gW, t = singles[i]
+        assert np.isfinite(Wb).all()
+        assert np.array_equal(Wb[:, c0:c0 + n], W) and np.array_equal(gWb[:, :, c0:c0 + n], gW), i
+        tb, _ = bs.time(i)
+        if te > 0:
+            assert tb == te and t == te, (i, tb, t)
+        else:
+            assert tb > 0.011
+
+
 def test_autotune_restores_the_state_and_changes_no_result(gks):
     """The autotuner times several launch shapes on the state itself; afterwards the state is the
     one it was given, and the chosen shapes give the same results bit for bit (graph replay)."""

@@ -166,9 +166,13 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
     int32_t nb[9];
 #pragma unroll
     for (int s = 0; s < 9; s++) nb[s] = m.sten[s * T + c];
+    // the level of the variable's layer (h2, or eta1 for the lower layer), loaded outside the
+    // branch so that a wave holding a thickness and a momentum issues it once: a thickness
+    // differences it, a momentum takes its layer's thickness from it
+    const double hq = Wh[(v < 3 ? 0 : TG) + c], bq = m.Bbar[c];
     if (thick) {
         const double *Q = Wh + (v == 3 ? TG : 0);
-        Q0h = Q[c];
+        Q0h = hq;
         Q0 = (R)Q0h;
 #pragma unroll
         for (int s = 0; s < 9; s++) rhs[s] = (R)(Q[nb[s]] - Q0h);
@@ -177,8 +181,8 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
         Q0 = Q[c];
 #pragma unroll
         for (int s = 0; s < 9; s++) rhs[s] = Q[nb[s]] - Q0;
-        q.hl = v < 3 ? Wh[c] : Wh[TG + c] - m.Bbar[c];
     }
+    q.hl = v < 3 ? hq : hq - bq;
     rhs[9] = hs * gW[(2 * v) * TG + c];
     rhs[10] = hs * gW[(2 * v + 1) * TG + c];
 #pragma unroll

@@ -703,12 +703,12 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             }
             tauz *= 0.25;
             /* reading: the floor of the smoothness indicators carries the variable's scale, the
-             * level itself for a thickness and h sqrt(G h) of the layer for a momentum, so that
-             * round-off about a state at rest stays under the linear weights */
+             * level itself for a thickness and 1e-5 h sqrt(G h) of the layer for a momentum, so
+             * that round-off about a state at rest stays under the linear weights */
             double S2 = 1e-20;
             if (v != 0 && v != 3) {
                 double hl = W[(v < 3 ? 0 : 3) * m->nt + c];
-                S2 = G * hl * hl * hl;
+                S2 = 1e-10 * G * hl * hl * hl;
             }
             double eps = 1e-10 * fmax(Q0 * Q0, S2);
             double wt0 = d0 * (1 + tauz / (beta0 + eps)), wts[4], sum = wt0;

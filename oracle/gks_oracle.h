@@ -47,7 +47,7 @@ void om_lsq_matrix(const om_mesh *m, int c, double *M);
  * six Gauss points (local edge k, point g -> index 2k+g):
  *   val[6 gp][6 comp], grad[6 gp][6 comp][2], r0[6 comp] = omega_0 / d_0.
  * linear != 0 returns the linear P^3 reconstruction (all weights at their linear values).  G enters
- * the floor of the smoothness indicators of the momenta (scale h sqrt(G h)). */
+ * the floor of the smoothness indicators of the momenta (scale 1e-5 h sqrt(G h)). */
 void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                          double *val, double *grad, double *r0);
 

@@ -301,8 +301,9 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         }
         tz *= R(0.25);
         // floor of the smoothness indicators with the variable's scale: the level of a thickness,
-        // h sqrt(G h) of the layer for a momentum (round-off about rest stays under linear weights)
-        const R S2 = thick ? R(1e-20) : (R)(p.G * q.hl * q.hl * q.hl);
+        // 1e-5 h sqrt(G h) of the layer for a momentum (round-off about rest stays under the
+        // linear weights)
+        const R S2 = thick ? R(1e-20) : (R)(1e-10 * p.G * q.hl * q.hl * q.hl);
         const R epsw = R(1e-10) * fmax(Q0 * Q0, S2);
         const R t0 = d0 * (1 + tz / (beta0 + epsw));
         R sum = t0, tm[4];

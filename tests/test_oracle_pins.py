@@ -273,7 +273,7 @@ def test_reconstruction_nonoscillatory_at_a_jump():
 
 def test_smoothness_floor_carries_the_variable_scale():
     """Reading of the nonlinear weights' floor: epsilon = 1e-10 max(Q0^2, S^2) with S the level of a
-    thickness and h sqrt(G h) of the layer for a momentum.  Round-off noise on a momentum at rest
+    thickness and 1e-5 h sqrt(G h) of the layer for a momentum.  Round-off noise on a momentum at rest
     keeps the linear weights (omega_0 / d_0 = 1), while a momentum jump of a tenth of
     h sqrt(G h) still switches them (the oracle divides by the rounded sum of the weights, hence
     the 1e-12)."""

@@ -24,7 +24,8 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
-                ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int)]
+                ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int),
+                ("per_side_gb", ctypes.c_int)]
 
 
 def build() -> str:
@@ -62,6 +63,8 @@ def load():
     lib.om_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, ctypes.c_int,
                             _dp, _dp, _dp, _dp]
     lib.om_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
+    lib.om_s2o4_stage.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.om_s2o4_final.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
     lib.om_cell_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
     lib.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp, _dp]
     lib.om_mlp_forward.argtypes = [_dp, _dp, ctypes.c_int, _dp]
@@ -99,7 +102,7 @@ def mlp_forward_bf16(P, X):
 
 
 def mlp_grad(P, X, y):
-    """(mean logistic loss, gradient [6849]) of the MLP on the batch (X, y)."""
+    """(mean logistic loss, gradient [MLP_PARAMS]) of the MLP on the batch (X, y)."""
     X = _f64(X)
     g = np.zeros(MLP_PARAMS)
     loss = load().om_mlp_grad(_d(_f64(P)), _d(X), _d(_f64(y)), X.shape[0], _d(g))
@@ -166,8 +169,8 @@ class Mesh:
         return val, grad, r0
 
 
-def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False) -> Params:
-    return Params(G, chi, cfl, eps, eps_num, int(linear))
+def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False) -> Params:
+    return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb))
 
 
 def params_of(sc, linear=False) -> Params:
@@ -204,6 +207,22 @@ def run(mesh: Mesh, p: Params, W, gW, t_end: float, max_steps: int = 10 ** 9):
         t += d
         n += 1
     return W, gW, t, n
+
+
+def s2o4_stage(dt_: float, W, L, Lt):
+    """First S2O4 stage on flat arrays: W + dt/2 L + dt^2/8 Lt."""
+    W, L, Lt = (_f64(np.ravel(a)) for a in (W, L, Lt))
+    out = np.zeros_like(W)
+    load().om_s2o4_stage(W.size, float(dt_), _d(W), _d(L), _d(Lt), _d(out))
+    return out
+
+
+def s2o4_final(dt_: float, W, L, Lt, Lt2):
+    """Second S2O4 stage on flat arrays: W + dt L + dt^2/6 Lt + dt^2/3 Lt2."""
+    W, L, Lt, Lt2 = (_f64(np.ravel(a)) for a in (W, L, Lt, Lt2))
+    out = np.zeros_like(W)
+    load().om_s2o4_final(W.size, float(dt_), _d(W), _d(L), _d(Lt), _d(Lt2), _d(out))
+    return out
 
 
 def mass(mesh: Mesh, W):

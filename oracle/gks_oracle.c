@@ -1078,8 +1078,14 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
             rR[0] = rL[0];
             rR[1] = rL[1];
         }
-        /* reading: single-valued bottom slope at the interface */
+        /* reading: single-valued bottom slope at the interface (the test-only switch gives each
+         * side its own cell's slope instead) */
         double gB[2] = {0.5 * (gBL[0] + gBR[0]), 0.5 * (gBL[1] + gBR[1])};
+        double gBs[2][2];
+        for (int d = 0; d < 2; d++) {
+            gBs[0][d] = p->per_side_gb ? gBL[d] : gB[d];
+            gBs[1][d] = p->per_side_gb ? gBR[d] : gB[d];
+        }
         /* reading: nonlinear weight of the force model from the cells' high-order weights */
         double wf[2];
         for (int f = 0; f < 2; f++) wf[f] = fmin(1.0, fmin(rL[f], rR[f]));
@@ -1107,14 +1113,14 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
                  * the upper layer's thickness, upper layer the interface level */
                 double phi1[2], phi2[2];
                 for (int d = 0; d < 2; d++) {
-                    phi1[d] = -G * gB[d] - chi * G * dh2[d];
+                    phi1[d] = -G * gBs[s][d] - chi * G * dh2[d];
                     phi2[d] = -G * deta[d];
                 }
                 for (int layer = 0; layer < 2; layer++) {
                     int o = layer == 0 ? 3 : 0;
                     double h = layer == 0 ? vs[s][3] - Bg : vs[s][0];
                     double dh[2];
-                    for (int d = 0; d < 2; d++) dh[d] = layer == 0 ? gs[s][2 * 3 + d] - gB[d] : gs[s][d];
+                    for (int d = 0; d < 2; d++) dh[d] = layer == 0 ? gs[s][2 * 3 + d] - gBs[s][d] : gs[s][d];
                     const double *dm1 = gs[s] + 2 * (o + 1), *dm2 = gs[s] + 2 * (o + 2);
                     const double *phi = layer == 0 ? phi1 : phi2;
                     double mx = vs[s][o + 1], my = vs[s][o + 2];
@@ -1228,6 +1234,17 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
 /* ----------------------------------------------------------------------------------------- */
 /* S2O4 step (Sec. 3.3)                                                                       */
 
+void om_s2o4_stage(int n, double dt, const double *W, const double *L, const double *Lt, double *out)
+{
+    for (int i = 0; i < n; i++) out[i] = W[i] + 0.5 * dt * L[i] + 0.125 * dt * dt * Lt[i];
+}
+
+void om_s2o4_final(int n, double dt, const double *W, const double *L, const double *Lt, const double *Lt2,
+                   double *out)
+{
+    for (int i = 0; i < n; i++) out[i] = W[i] + dt * L[i] + dt * dt / 6.0 * Lt[i] + dt * dt / 3.0 * Lt2[i];
+}
+
 int om_step(const om_mesh *m, const om_params *p, double dt, int nstages, const double *W,
             const double *gW, double *Wout, double *gWout)
 {
@@ -1236,17 +1253,16 @@ int om_step(const om_mesh *m, const om_params *p, double dt, int nstages, const 
     double *G = (double *)malloc(sizeof(double) * 12 * T), *Gt = (double *)malloc(sizeof(double) * 12 * T);
     om_operator(m, p, dt, W, gW, L, Lt, G, Gt);
     if (nstages == 1) {
-        for (size_t i = 0; i < 6 * T; i++) Wout[i] = W[i] + 0.5 * dt * L[i] + 0.125 * dt * dt * Lt[i];
+        om_s2o4_stage((int)(6 * T), dt, W, L, Lt, Wout);
         for (size_t i = 0; i < 12 * T; i++) gWout[i] = G[i] + 0.5 * dt * Gt[i];
     } else {
         double *Ws = (double *)malloc(sizeof(double) * 6 * T), *gWs = (double *)malloc(sizeof(double) * 12 * T);
-        for (size_t i = 0; i < 6 * T; i++) Ws[i] = W[i] + 0.5 * dt * L[i] + 0.125 * dt * dt * Lt[i];
+        om_s2o4_stage((int)(6 * T), dt, W, L, Lt, Ws);
         for (size_t i = 0; i < 12 * T; i++) gWs[i] = G[i] + 0.5 * dt * Gt[i];
         double *L2 = (double *)malloc(sizeof(double) * 6 * T), *Lt2 = (double *)malloc(sizeof(double) * 6 * T);
         double *G2 = (double *)malloc(sizeof(double) * 12 * T), *Gt2 = (double *)malloc(sizeof(double) * 12 * T);
         om_operator(m, p, dt, Ws, gWs, L2, Lt2, G2, Gt2);
-        for (size_t i = 0; i < 6 * T; i++)
-            Wout[i] = W[i] + dt * L[i] + dt * dt / 6.0 * Lt[i] + dt * dt / 3.0 * Lt2[i];
+        om_s2o4_final((int)(6 * T), dt, W, L, Lt, Lt2, Wout);
         for (size_t i = 0; i < 12 * T; i++) gWout[i] = G[i] + dt * Gt2[i];
         free(Ws); free(gWs); free(L2); free(Lt2); free(G2); free(Gt2);
     }

@@ -29,7 +29,17 @@ typedef struct {
     double eps_num;  /* pressure-jump constant of the collision time (Sec. 4), 5 */
     int linear;      /* 1: linear P^3 reconstruction everywhere (all weights at their linear
                         values), 0: the nonlinear compact reconstruction */
+    int per_side_gb; /* test only: 1 gives each side of an interface its own cell's bottom slope
+                        in the evolution instead of the single-valued mean (shows what the
+                        single-valued slope is for); 0 in every real use */
 } om_params;
+
+/* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
+ * stage  out = W + dt/2 L + dt^2/8 Lt               (the state at t + dt/2)
+ * final  out = W + dt L + dt^2/6 Lt + dt^2/3 Lt2     (Lt2 = time derivative at the stage state) */
+void om_s2o4_stage(int n, double dt, const double *W, const double *L, const double *Lt, double *out);
+void om_s2o4_final(int n, double dt, const double *W, const double *L, const double *Lt, const double *Lt2,
+                   double *out);
 
 /* Mesh: node coordinates [nn][2], counter-clockwise triangles [nt][3], bottom at the nodes
  * (piecewise linear), periodic != 0 pairs the boundary edges of [0,Lx]x[0,Ly] by translation,

@@ -409,3 +409,112 @@ def test_accuracy_table_magnitude_and_order():
             assert ref / 5 < e[v] < 5 * ref, (key, row, e[v], ref)
         # mean order over h_re = 1/8 .. 1/32
         assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.8
+
+
+# ------------------------------------------------------------------------------------------
+# time stepping, gradient update, single-valued bottom slope, self-convergence
+
+@pytest.mark.parametrize("rhs", ["decay", "blowup"])
+def test_s2o4_is_fourth_order(rhs):
+    """The two-stage step (Sec. 3.3, Eq. SWE-fully-discrete) with exact time derivatives is fourth
+    order: y' = -y to t = 1 and y' = y^2 from y = 1 to t = 1/2 (solution 1/(1 - t)).  The global
+    error falls by ~16 per halving of the step."""
+    def f(y):
+        return (-y, y) if rhs == "decay" else (y * y, 2 * y ** 3)      # L and dL/dt = L'(y) L
+    t_end = 1.0 if rhs == "decay" else 0.5
+    exact = math.exp(-1.0) if rhs == "decay" else 2.0
+    errs = []
+    for n in (10, 20, 40):
+        dt, y = t_end / n, np.array([1.0])
+        for _ in range(n):
+            L, Lt = f(y)
+            ys = o.s2o4_stage(dt, y, L, Lt)
+            _, Lt2 = f(ys)
+            y = o.s2o4_final(dt, y, L, Lt, Lt2)
+        errs.append(abs(y[0] - exact))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert min(orders) > 3.8, (errs, orders)
+
+
+def test_green_gauss_update_is_exact_for_cubic_interface_data():
+    """Gradient update (Sec. 3.3, Eq. slope-1): with cubic thickness fields at rest (flat bottom)
+    the linear reconstruction is exact at the Gauss points, the interface state equals it, and the
+    Green-Gauss sum with two Gauss points per edge returns each cell's exact average gradient; the
+    momentum gradients stay zero."""
+    sc = w.lake_at_rest(12, seed=5, bump_amp=0.0)
+    rng = np.random.default_rng(3)
+    polys = []
+    for v in range(6):
+        if v in (0, 3):
+            P = {(p, q): 0.1 * rng.uniform(-1, 1) for p in range(4) for q in range(4 - p)}
+            P[(0, 0)] = 1.0
+        else:
+            P = {(0, 0): 0.0}
+        polys.append(P)
+    W, gW = _poly_cell_data(sc, polys)
+    mesh = o.Mesh.from_scenario(sc)
+    p = o.params(G=sc.G, chi=sc.chi, linear=True)
+    _, _, GW, _ = o.operator(mesh, p, 1e-3, W, gW)
+    far = [c for c in range(sc.n_tri) if np.all(sc.node_xy[sc.tri[c]] > 0.3) and np.all(sc.node_xy[sc.tri[c]] < 0.7)]
+    assert len(far) > 10
+    for v in (0, 3):
+        assert np.abs(GW[v][:, far] - gW[v][:, far]).max() < 1e-8, v
+    assert np.abs(GW[[1, 2, 4, 5]][:, :, far]).max() < 1e-10
+
+
+def test_single_valued_bottom_slope_keeps_the_lake_at_rest():
+    """Reading R17: the evolution takes one bottom slope per interface, the mean of the two cells'
+    constant slopes.  Over a piecewise-linear bottom (slope jumps at every edge) that keeps the lake
+    at rest to round-off; giving each side its own cell's slope (a test-only switch of the oracle)
+    breaks the balance at once."""
+    sc = w.lake_at_rest(8, chi=0.98)
+    mesh = o.Mesh.from_scenario(sc)
+    drift = []
+    for per_side in (False, True):
+        p = o.params(G=sc.G, chi=sc.chi, cfl=sc.cfl, per_side_gb=per_side)
+        W, gW = sc.W0.copy(), sc.gradW0.copy()
+        for _ in range(10):
+            W, gW = o.step(mesh, p, o.dt(mesh, p, W), W, gW)
+        drift.append(np.abs(W[[1, 2, 4, 5]]).max())
+    assert drift[0] < 1e-13 and drift[1] > 1e-6, drift
+
+
+def _restrict(fine, coarse, Wf):
+    """Average fine-cell values onto the coarse triangles that contain their centroids (nested
+    periodic meshes: each coarse triangle is the union of four fine ones of equal area)."""
+    cf = fine.node_xy[fine.tri].mean(axis=1)
+    P = coarse.node_xy[coarse.tri]
+    out = np.zeros((Wf.shape[0], coarse.n_tri))
+    cnt = np.zeros(coarse.n_tri)
+    for i, x in enumerate(cf):
+        a, b, c = P[:, 0], P[:, 1], P[:, 2]
+        det = (b[:, 0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (c[:, 0] - a[:, 0])
+        l1 = ((x[0] - a[:, 0]) * (c[:, 1] - a[:, 1]) - (x[1] - a[:, 1]) * (c[:, 0] - a[:, 0])) / det
+        l2 = ((b[:, 0] - a[:, 0]) * (x[1] - a[:, 1]) - (b[:, 1] - a[:, 1]) * (x[0] - a[:, 0])) / det
+        k = np.where((l1 > -1e-12) & (l2 > -1e-12) & (l1 + l2 < 1 + 1e-12))[0]
+        assert k.size == 1
+        out[:, k[0]] += Wf[:, i]
+        cnt[k[0]] += 1
+    assert np.all(cnt == 4)
+    return out / 4
+
+
+def test_smooth_periodic_self_convergence():
+    """C1-type smooth two-layer flow on nested periodic meshes (16, 32, 64 squares a side) to
+    t = 0.05 with the linear reconstruction: the differences to the restricted finer solution fall
+    at second order in every component (the layer-coupling source is second order, Sec. 3.2, which
+    bounds the two-layer scheme; measured 1.8-2.1)."""
+    sols = {}
+    for n in (16, 32, 64):
+        sc = w.smooth_periodic(n, t_end=0.05)
+        mesh = o.Mesh.from_scenario(sc)
+        W, _, t, _ = o.run(mesh, o.params_of(sc, linear=True), sc.W0, sc.gradW0, sc.t_end)
+        assert abs(t - sc.t_end) < 1e-12
+        sols[n] = (sc, W)
+    e = []
+    for n in (16, 32):
+        sc, W = sols[n]
+        scf, Wf = sols[2 * n]
+        e.append(np.abs(W - _restrict(scf, sc, Wf)).mean(axis=1))
+    order = np.log2(e[0] / e[1])
+    assert order.min() >= 1.75, (e, order)

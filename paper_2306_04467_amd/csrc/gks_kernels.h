@@ -139,8 +139,9 @@ constexpr int RECON_CELLS = 32;
 // values of one variable at a cell's six Gauss points and its gradient there
 template <typename R>
 struct ReconOut {
-    double h[6];  // thicknesses (h2, eta1) in double
-    R val[6];     // momenta
+    // Gauss-point values: a thickness (h2, eta1) in double, a momentum in the bulk precision widened
+    // to double (exact); one array for both keeps every access at a constant index (registers)
+    double v[6];
     R gx[6], gy[6];
 };
 
@@ -336,7 +337,6 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     }
     const R ihs = R(1) / hs;
     const R gs[2] = {R(0.5 - 0.28867513459481288225), R(0.5 + 0.28867513459481288225)};
-    const int gbase = 4 + 2 * v;
 #pragma unroll
     for (int k = 0; k < 3; k++)
 #pragma unroll
@@ -351,10 +351,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
             // all candidates share the cell average Q0 (ratio + sum cm = 1)
             const R dev = ratio * P + sbx * x + sby * y;
             const int slot = 2 * k + g;
-            if (thick)
-                out.h[slot] = Q0h + (double)dev;
-            else
-                out.val[slot] = Q0 + dev;
+            out.v[slot] = thick ? Q0h + (double)dev : (double)(Q0 + dev);
             out.gx[slot] = (ratio * Px + sbx) * ihs;
             out.gy[slot] = (ratio * Py + sby) * ihs;
         }
@@ -505,9 +502,9 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         for (int slot = 0; slot < 6; slot++) {
             const int i = 6 * lane + slot;
             if (thick)
-                th[i].h[v == 3] = out.h[slot];
+                th[i].h[v == 3] = out.v[slot];
             else
-                th[i].q[mom_slot(v)] = out.val[slot];
+                th[i].q[mom_slot(v)] = (R)out.v[slot];
             tt[i].g[2 * v] = out.gx[slot];
             tt[i].g[2 * v + 1] = out.gy[slot];
         }

@@ -641,11 +641,11 @@ struct Slope {
     R an, bn, gn, at, bt, gt;
 };
 
+// ih = 1/h of the Maxwellian the slopes belong to
 template <typename R>
-__host__ __device__ inline Slope<R> slope_of(const SideL<R> &s, R h, R U, R V, R lam)
+__host__ __device__ inline Slope<R> slope_of(const SideL<R> &s, R ih, R U, R V, R lam)
 {
     Slope<R> r;
-    const R ih = R(1) / h;
     r.an = lam * s.en * ih;
     r.bn = 2 * lam * (s.mnn - U * s.hn) * ih;
     r.gn = 2 * lam * (s.mtn - V * s.hn) * ih;
@@ -737,9 +737,11 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
                                  R eps_num, R dt, R *F0, R *Ft, R *Wb, R *Wbt)
 {
     const bool bottom = (gBn != R(0)) || (gBt != R(0));
-    const R lamL = R(1) / (G * sl.h), lamR = R(1) / (G * sr.h);
+    // reciprocals formed once (lam = 1/(G h)); 1/(2 sqrt(pi lam)) = sqrt(lam) th / sqrt(pi)
+    const R iG = R(1) / G, ihL = R(1) / sl.h, ihR = R(1) / sr.h;
+    const R lamL = iG * ihL, lamR = iG * ihR;
     const R thL = R(0.5) * G * sl.h, thR = R(0.5) * G * sr.h;
-    const R spi = R(1.7724538509055160273);  // sqrt(pi)
+    const R ispi = R(0.56418958354775628695);  // 1/sqrt(pi)
     R ML[6], MR[6], eL, eR;
     // half-space masses from one error function per Gaussian: 1/2 erfc(-x) = 1/2 (1 + erf(x))
     // (exactly 1/2 at rest; where erf(x) is close to -1 the lost relative digits of the tiny mass
@@ -748,14 +750,14 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
         const R sq = sqrt_(lamL);
         eL = erf_(sq * sl.U);  // 2 (M0 - 1/2)
         const R m0 = R(0.5) + R(0.5) * eL;
-        const R ex = exp_(-lamL * sl.U * sl.U) / (2 * spi * sq);
+        const R ex = exp_(-lamL * sl.U * sl.U) * sq * thL * ispi;
         u_moments(sl.U, thL, m0, sl.U * m0 + ex, ML);
     }
     {
         const R sq = sqrt_(lamR);
         eR = -erf_(sq * sr.U);
         const R m0 = R(0.5) + R(0.5) * eR;  // 1/2 erfc(x)
-        const R ex = exp_(-lamR * sr.U * sr.U) / (2 * spi * sq);
+        const R ex = exp_(-lamR * sr.U * sr.U) * sq * thR * ispi;
         u_moments(sr.U, thR, m0, sr.U * m0 - ex, MR);
     }
     // interface equilibrium state: thickness as an FP64 base plus a deviation that is 0 at rest
@@ -763,20 +765,44 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     const R hb = (R)(hbase + (double)hdev);
     const R wb1 = sum_products(sl.h, ML[1], sr.h, MR[1]);
     const R wb2 = sum_products(sl.h * ML[0], sl.V, sr.h * MR[0], sr.V);
-    const R Ub = wb1 / hb, Vb = wb2 / hb;
-    const R lamb = R(1) / (G * hb), thb = R(0.5) * G * hb;
+    // brackets of the initial (side) distributions first, so that the sides' moments are dead
+    // before the interface equilibrium's are formed.  B4 = (.., D4 + P + B4p, ..)
+    R B4[3], B5[3], t1[3], t2[3];
+    B4[0] = wb1;
+    // normal momentum: h U M1 parts plus the pressure-like part's excess over 1/2 G hb^2
+    // (h^2 M0 summed over the sides minus hb^2: exactly zero at rest)
+    {
+        const R sq2 = sum_products(sl.h * sl.h, ML[0], sr.h * sr.h, MR[0]);
+        const R hb2 = sum_products(hb, hb, R(0), R(0));
+        B4[1] = sum_products(sl.h * sl.U, ML[1], sr.h * sr.U, MR[1]) + R(0.5) * G * (sq2 - hb2);
+    }
+    B4[2] = sum_products(sl.h * ML[1], sl.V, sr.h * MR[1], sr.V);
+    {
+        const Slope<R> aL = slope_of(sl, ihL, sl.U, sl.V, lamL), aR = slope_of(sr, ihR, sr.U, sr.V, lamR);
+        poly_moments(aL, sl.pn, sl.pt, sl.h, sl.U, sl.V, lamL, thL, ML, 1, t1);
+        poly_moments(aR, sr.pn, sr.pt, sr.h, sr.U, sr.V, lamR, thR, MR, 1, t2);
+        if (bottom) {
+            bottom_moments(gBn, gBt, sl.U, sl.V, lamL, thL, ML, 1, t1);
+            bottom_moments(gBn, gBt, sr.U, sr.V, lamR, thR, MR, 1, t2);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; i++) B5[i] = t1[i] + t2[i];
+    }
+    const R ihb = R(1) / hb;
+    const R Ub = wb1 * ihb, Vb = wb2 * ihb;
+    const R lamb = iG * ihb, thb = R(0.5) * G * hb;
     R Mp[6], Mm[6];
     {
         const R sq = sqrt_(lamb);
         const R eb = erf_(sq * Ub);
         const R m0p = R(0.5) + R(0.5) * eb, m0m = R(0.5) - R(0.5) * eb;
-        const R ex = exp_(-lamb * Ub * Ub) / (2 * spi * sq);
+        const R ex = exp_(-lamb * Ub * Ub) * sq * thb * ispi;
         u_moments(Ub, thb, m0p, Ub * m0p + ex, Mp);
         u_moments(Ub, thb, m0m, Ub * m0m - ex, Mm);
     }
-    const Slope<R> bL = slope_of(sl, hb, Ub, Vb, lamb), bR = slope_of(sr, hb, Ub, Vb, lamb);
+    const Slope<R> bL = slope_of(sl, ihb, Ub, Vb, lamb), bR = slope_of(sr, ihb, Ub, Vb, lamb);
     // time slope of the interface equilibrium from compatibility
-    R t1[3], t2[3], wt[3];
+    R wt[3];
     poly_moments(bL, sl.pn, sl.pt, hb, Ub, Vb, lamb, thb, Mp, 0, t1);
     poly_moments(bR, sr.pn, sr.pt, hb, Ub, Vb, lamb, thb, Mm, 0, t2);
     if (bottom) {
@@ -786,8 +812,8 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 #pragma unroll
     for (int i = 0; i < 3; i++) wt[i] = -(t1[i] + t2[i]);
     // brackets multiplying the five time coefficients; B1 and B4 split into a hydrostatic part
-    // and the rest.  B1 = (hb Ub, hb Ub^2 + P, hb Ub Vb), B4 = (.., D4 + P + B4p, ..)
-    R B1[3], B2[3], B3[3], B4[3], B5[3];
+    // and the rest.  B1 = (hb Ub, hb Ub^2 + P, hb Ub Vb)
+    R B1[3], B2[3], B3[3];
     B1[0] = hb * Ub;
     B1[1] = hb * Ub * Ub;  // pressure removed
     B1[2] = hb * Ub * Vb;
@@ -800,34 +826,13 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 #pragma unroll
     for (int i = 0; i < 3; i++) B2[i] = t1[i] + t2[i];
     {
-        const R ih = R(1) / hb;
-        const R aA = lamb * wt[0] * ih;
-        const R bA = 2 * lamb * (wt[1] - Ub * wt[0]) * ih;
-        const R gA = 2 * lamb * (wt[2] - Vb * wt[0]) * ih;
+        const R aA = lamb * wt[0] * ihb;
+        const R bA = 2 * lamb * (wt[1] - Ub * wt[0]) * ihb;
+        const R gA = 2 * lamb * (wt[2] - Vb * wt[0]) * ihb;
         const R mA = 2 * aA * thb;  // <A>
         B3[0] = hb * (Ub * mA + bA * thb);
         B3[1] = hb * (Ub * Ub * mA + 2 * Ub * bA * thb + 4 * aA * thb * thb);
         B3[2] = hb * (Ub * Vb * mA + Ub * gA * thb + Vb * bA * thb);
-    }
-    B4[0] = wb1;
-    // normal momentum: h U M1 parts plus the pressure-like part's excess over 1/2 G hb^2
-    // (h^2 M0 summed over the sides minus hb^2: exactly zero at rest)
-    {
-        const R sq2 = sum_products(sl.h * sl.h, ML[0], sr.h * sr.h, MR[0]);
-        const R hb2 = sum_products(hb, hb, R(0), R(0));
-        B4[1] = sum_products(sl.h * sl.U, ML[1], sr.h * sr.U, MR[1]) + R(0.5) * G * (sq2 - hb2);
-    }
-    B4[2] = sum_products(sl.h * ML[1], sl.V, sr.h * MR[1], sr.V);
-    {
-        const Slope<R> aL = slope_of(sl, sl.h, sl.U, sl.V, lamL), aR = slope_of(sr, sr.h, sr.U, sr.V, lamR);
-        poly_moments(aL, sl.pn, sl.pt, sl.h, sl.U, sl.V, lamL, thL, ML, 1, t1);
-        poly_moments(aR, sr.pn, sr.pt, sr.h, sr.U, sr.V, lamR, thR, MR, 1, t2);
-        if (bottom) {
-            bottom_moments(gBn, gBt, sl.U, sl.V, lamL, thL, ML, 1, t1);
-            bottom_moments(gBn, gBt, sr.U, sr.V, lamR, thR, MR, 1, t2);
-        }
-#pragma unroll
-        for (int i = 0; i < 3; i++) B5[i] = t1[i] + t2[i];
     }
     // collision time (Sec. 4) in units of dt, and the weights of F(dt), F(dt/2) giving the flux and
     // its time derivative; c01 + c04 = 1 and ct1 + ct4 = 0 exactly (the hydrostatic part of B1 and B4

@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # keep packed FP32 instructions out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary vector registers: the fused indicator then adds no
+    # accumulation registers to the reconstruction's budget (7 instead of 5 waves per SIMD in FP32)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

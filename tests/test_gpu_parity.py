@@ -173,3 +173,50 @@ def test_full_size_step_parity(gks):
     e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
     print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
     assert e.max() < TOL_FP64 and g.max() < TOL_FP64, (e, g)
+
+
+_DAM_BREAK_REF = {}
+
+
+def _dam_break_reference():
+    """The 1M-triangle dam break and the oracle's first step on it (computed once per session)."""
+    if not _DAM_BREAK_REF:
+        sc = w.dam_break(707, seed=20230605)
+        om = o.Mesh.from_scenario(sc)
+        p = o.params_of(sc)
+        dref = o.dt(om, p, sc.W0)
+        Wr, gWr = o.step(om, p, dref, sc.W0, sc.gradW0)
+        a, _, _ = om.geometry()
+        _DAM_BREAK_REF.update(sc=sc, dt=dref, W=Wr, gW=gWr, area=a)
+    return _DAM_BREAK_REF
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_dam_break_step_parity(gks, precision):
+    """The 999,698-triangle two-layer dam break over a sinusoidal bottom (density ratio 0.95) at
+    full size: one S2O4 step with the CFL step, every cell against the oracle's step.  Here the
+    nonlinear weights, the force model's plane gradients and the collision time's jump term are
+    all active.  FP64 to the per-step bound; the mixed path to its relative L1 bound."""
+    print(f"[parity] dam break {precision}, 999,698 triangles (oracle step computed once)", flush=True)
+    ref = _dam_break_reference()
+    sc, dref, Wr, gWr = ref["sc"], ref["dt"], ref["W"], ref["gW"]
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, precision=precision)
+    st.stage(0, dref)
+    st.stage(1)
+    W, gW, _ = st.read()
+    if precision == "fp64":
+        e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
+        print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
+        assert e.max() < TOL_FP64 and g.max() < TOL_FP64, (e, g)
+    else:
+        a = ref["area"]
+        err = []
+        for q in (0, 3):
+            h = Wr[q]
+            err.append((a * np.abs(W[q] - h)).sum() / (a * np.abs(h)).sum())
+            den = (a * h * np.sqrt(sc.G * h)).sum()
+            for v in (q + 1, q + 2):
+                err.append((a * np.abs(W[v] - Wr[v])).sum() / den)
+        print(f"   rel-L1 {max(err):.2e}", flush=True)
+        assert max(err) <= 1e-5, err

@@ -47,9 +47,10 @@ def algorithmic_bytes(T, E, NG, prec):
         "flux": T * (12 * d + 96 * r + 2 * r + 4 * d) + E * (4 * 3 + 2 * r + 2 * d + 2 * r + 4 * d + 22 * r),
         "hhat": T * (12 * d + 24 * r) + E * (4 * 3 + 2 * r + 2 * d + 2 * d),
         "plane": T * (4 * 3 + 6 * d + 4 * d) + E * 2 * d,
-        # geometry, edge outputs once, state / carry (average of the two stages)
-        "update": T * (4 * 3 + 12 * d) + E * (4 * d + 22 * r) + T * ((2 * d + 4 * r) * 2 + 12 * r + 6 * d + 12 * r
-                                                                     + (6 * d + 12 * r)) // 2,
+        # geometry, edge outputs once (the second stage reads only the interface thicknesses, the
+        # thickness fluxes and the time derivatives), state / carry (average of the two stages)
+        "update": T * (4 * 3 + 12 * d) + E * ((4 * d + 22 * r) + (2 * d + 14 * r)) // 2
+                  + T * ((2 * d + 4 * r) * 2 + 12 * r + 6 * d + 12 * r + (6 * d + 12 * r)) // 2,
         "ghost": NG * (2 * 2 * d + 2 * 16 * r + 4 * d + 4),
         "dt": T * (2 * d + 4 * r + d),
     }

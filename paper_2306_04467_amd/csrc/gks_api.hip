@@ -195,8 +195,12 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
         const int b = s->bs[GKS_KERNEL_UPDATE];
-        hipLaunchKernelGGL(gks::k_update<R>, dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, stage,
-                           s->eoh, (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+        if (stage == 0)
+            hipLaunchKernelGGL((gks::k_update<R, 0>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                               (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+        else
+            hipLaunchKernelGGL((gks::k_update<R, 1>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                               (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
     });
 }
 

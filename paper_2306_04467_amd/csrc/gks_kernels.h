@@ -1009,13 +1009,17 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 
 // stage 0: Ws = W + dt/2 L + dt^2/8 Lt, gWs = G + dt/2 Gt; carry Wc = W + dt L + dt^2/6 Lt, Gc = G
 // stage 1: W = Wc + dt^2/3 Lt, gW = Gc + dt Gt
-template <typename R>
-__global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, int stage, const double *__restrict__ eoh,
+// STAGE is a template argument: the second stage needs only the time derivatives, the thickness
+// fluxes and the interface thicknesses, so it neither loads nor sums the momentum fluxes, the
+// hydrostatic terms and the interface momenta
+template <typename R, int STAGE>
+__global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double *__restrict__ eoh,
                                                 const R *__restrict__ eom, const double *__restrict__ Whin,
                                                 const R *__restrict__ Wmin, const R *__restrict__ gWin,
                                                 double *__restrict__ Whout, R *__restrict__ Wmout,
                                                 R *__restrict__ gWout, double *__restrict__ Wc, R *__restrict__ Gc)
 {
+    constexpr int stage = STAGE;
     int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T, E = m.E, TG = m.T + m.NG;
@@ -1048,30 +1052,38 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, int stage, co
         const int32_t code = m.cedge[k * T + c];
         const int64_t e = code >= 0 ? code : ~code;
         const double f = m.fl[k * T + c], gx = m.gg[(2 * k) * T + c], gy = m.gg[(2 * k + 1) * T + c];
-        const double Pu = eoh[e], Pl = eoh[E + e], Hu = eoh[2 * E + e], Hl = eoh[3 * E + e];
+        const double Hu = eoh[2 * E + e], Hl = eoh[3 * E + e];
         double Wb[6];
         Wb[0] = Hu;
-        Wb[1] = eom[12 * E + e];
-        Wb[2] = eom[13 * E + e];
         Wb[3] = Hl;
-        Wb[4] = eom[14 * E + e];
-        Wb[5] = eom[15 * E + e];
+        if constexpr (stage == 0) {
+            Wb[1] = eom[12 * E + e];
+            Wb[2] = eom[13 * E + e];
+            Wb[4] = eom[14 * E + e];
+            Wb[5] = eom[15 * E + e];
+        }
 #pragma unroll
         for (int v = 0; v < 6; v++) {
-            const double F0 = eom[(int64_t)v * E + e], Ft = eom[(int64_t)(6 + v) * E + e];
+            const bool mass = v == 0 || v == 3;
+            if (stage == 0 || mass) {
+                LF[v] -= f * (double)eom[(int64_t)v * E + e];
+                GG[v][0] += gx * Wb[v];
+                GG[v][1] += gy * Wb[v];
+            }
+            const double Ft = eom[(int64_t)(6 + v) * E + e];
             const double Wbt = eom[(int64_t)(16 + v) * E + e];
-            LF[v] -= f * F0;
             LFt[v] -= f * Ft;
-            GG[v][0] += gx * Wb[v];
-            GG[v][1] += gy * Wb[v];
             GGt[v][0] += gx * Wbt;
             GGt[v][1] += gy * Wbt;
         }
-        // hydrostatic part of the normal momentum flux, along the outward normal
-        LF[1] -= gx * Pu;
-        LF[2] -= gy * Pu;
-        LF[4] -= gx * Pl;
-        LF[5] -= gy * Pl;
+        if constexpr (stage == 0) {
+            // hydrostatic part of the normal momentum flux, along the outward normal
+            const double Pu = eoh[e], Pl = eoh[E + e];
+            LF[1] -= gx * Pu;
+            LF[2] -= gy * Pu;
+            LF[4] -= gx * Pl;
+            LF[5] -= gy * Pl;
+        }
         hs[1] += Hu;
         hs[0] += Hl;
         hts[1] += eom[16 * E + e];
@@ -1092,7 +1104,7 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, int stage, co
     Lt[5] += -chi * G * (hts[0] * GG[0][1] + hs[0] * GGt[0][1]);
     Lt[1] += -G * (hts[1] * GG[3][0] + hs[1] * GGt[3][0]);
     Lt[2] += -G * (hts[1] * GG[3][1] + hs[1] * GGt[3][1]);
-    if (stage == 0) {
+    if constexpr (stage == 0) {
         double L[6];
 #pragma unroll
         for (int v = 0; v < 6; v++) L[v] = LF[v];

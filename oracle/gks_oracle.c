@@ -744,6 +744,25 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             grad[(p * NV + v) * 2] = Rx;
             grad[(p * NV + v) * 2 + 1] = Ry;
         }
+        /* positivity safeguard (not in the paper): where a layer thickness at a Gauss point would
+         * fall below a tenth of the cell's average, the reconstruction's deviation from the
+         * average is scaled down (Zhang-Shu scaling) until it does not; the lower layer's
+         * thickness is eta1 minus the piecewise-linear bottom.  At rest and in ordinary flows the
+         * factor is 1 and nothing changes. */
+        if (v == 0 || v == 3) {
+            double hbar = v == 0 ? Q0 : Q0 - m->Bbar[c], floor_h = 0.1 * hbar, theta = 1.0;
+            for (int p = 0; p < 6; p++) {
+                double dev = val[p * NV + v] - Q0;
+                double bdev = v == 3 ? m->Bx[c] * (gp[p][0] - x0[0]) + m->By[c] * (gp[p][1] - x0[1]) : 0.0;
+                if (dev < 0) theta = fmin(theta, fmax(0.0, (hbar - bdev - floor_h) / -dev));
+            }
+            if (theta < 1.0)
+                for (int p = 0; p < 6; p++) {
+                    val[p * NV + v] = Q0 + theta * (val[p * NV + v] - Q0);
+                    grad[(p * NV + v) * 2] *= theta;
+                    grad[(p * NV + v) * 2 + 1] *= theta;
+                }
+        }
     }
 }
 

@@ -337,6 +337,14 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     }
     const R ihs = R(1) / hs;
     const R gs[2] = {R(0.5 - 0.28867513459481288225), R(0.5 + 0.28867513459481288225)};
+    // positivity safeguard (not in the paper): where a layer thickness at a Gauss point would fall
+    // below a tenth of the cell's average, the deviation from the average is scaled down
+    // (Zhang-Shu scaling) until it does not; the lower layer's thickness is eta1 minus the
+    // piecewise-linear bottom.  The factor is 1 at rest and in ordinary flows; it is formed in the
+    // bulk precision (it only decides how far to pull the values back).
+    const R hbar = (R)(v == 0 ? Q0h : Q0h - m.Bbar[c]), floor_h = R(0.1) * hbar;
+    const R gBx = v == 3 ? (R)m.gB[c] : R(0), gBy = v == 3 ? (R)m.gB[T + c] : R(0);
+    R theta = 1;
 #pragma unroll
     for (int k = 0; k < 3; k++)
 #pragma unroll
@@ -354,7 +362,19 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
             out.v[slot] = thick ? Q0h + (double)dev : (double)(Q0 + dev);
             out.gx[slot] = (ratio * Px + sbx) * ihs;
             out.gy[slot] = (ratio * Py + sby) * ihs;
+            if (thick && dev < 0) {
+                const R bdev = hs * (gBx * x + gBy * y);
+                theta = fmin(theta, fmax(R(0), (hbar - bdev - floor_h) / -dev));
+            }
         }
+    if (theta < R(1)) {
+#pragma unroll
+        for (int slot = 0; slot < 6; slot++) {
+            out.v[slot] = Q0h + (double)theta * (out.v[slot] - Q0h);
+            out.gx[slot] *= theta;
+            out.gy[slot] *= theta;
+        }
+    }
 }
 
 // the learned indicator inside the reconstruction: bf16 weight matrices, FP32 parameters, logit

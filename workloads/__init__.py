@@ -5,7 +5,7 @@ problems (meshes, bottom topography at nodes, cell averages and cell-averaged gr
 initial state).  It holds none of the scheme's arithmetic: no reconstruction, flux, source or
 time-stepping code lives here, only geometry generation and quadrature of analytic initial data.
 """
-from .meshes import periodic_square, jittered_square  # noqa: F401
+from .meshes import periodic_square, jittered_square, jittered_rect  # noqa: F401
 from .scenarios import (  # noqa: F401
     Scenario,
     smooth_periodic,
@@ -13,5 +13,8 @@ from .scenarios import (  # noqa: F401
     lake_at_rest,
     dam_break,
     ensemble,
+    riemann_exchange,
+    riemann_interface,
+    circular_interface,
     COMPONENTS,
 )

@@ -85,6 +85,30 @@ def jittered_square(n: int, seed: int, jitter: float = 0.3):
     return xy, tri[order].astype(np.int32)
 
 
+def jittered_rect(nx: int, ny: int, lx: float, ly: float, seed: int, jitter: float = 0.3):
+    """Jittered-lattice Delaunay mesh of [0, lx] x [0, ly] with 2 nx ny triangles: the
+    (nx+1) x (ny+1) lattice with interior nodes moved by uniform offsets within jitter times the
+    local spacing (boundary nodes along the boundary only), Morton-ordered."""
+    from scipy.spatial import Delaunay
+
+    hx, hy = lx / nx, ly / ny
+    rng = np.random.default_rng(seed)
+    ii, jj = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    x = ii * hx + rng.uniform(-jitter * hx, jitter * hx, size=ii.shape)
+    y = jj * hy + rng.uniform(-jitter * hy, jitter * hy, size=ii.shape)
+    x[(ii == 0) | (ii == nx)] = (ii[(ii == 0) | (ii == nx)] * hx)
+    y[(jj == 0) | (jj == ny)] = (jj[(jj == 0) | (jj == ny)] * hy)
+    x[ii == nx] = lx
+    y[jj == ny] = ly
+    xy = np.stack([x, y], axis=1).astype(np.float64)
+    tri = _orient_ccw(xy, Delaunay(xy).simplices.astype(np.int64))
+    if tri.shape[0] != 2 * nx * ny:
+        raise RuntimeError(f"Delaunay gave {tri.shape[0]} triangles, expected {2 * nx * ny}")
+    order = _morton_order(xy[tri].mean(axis=1))
+    return xy, tri[order].astype(np.int32)
+
+
 def _morton_order(c: np.ndarray) -> np.ndarray:
     """Permutation sorting points along a Z-order curve (spatial locality of cell numbering)."""
     lo = c.min(axis=0)

@@ -15,7 +15,7 @@ from typing import Callable, Optional
 
 import numpy as np
 
-from .meshes import jittered_square, periodic_square
+from .meshes import jittered_rect, jittered_square, periodic_square
 
 COMPONENTS = ("h2", "h2U2", "h2V2", "h1", "h1U1", "h1V1")
 
@@ -216,6 +216,55 @@ def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, dis
     if (W0[3] <= 0).any() or (W0[0] <= 0).any():
         raise ValueError("non-positive layer thickness in initial data")
     return Scenario(name, xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0)
+
+
+def riemann_exchange(n: int = 100, chi: float = 0.98, cfl: float = 0.3, t_end: float = 0.1,
+                     G: float = 10.0) -> Scenario:
+    """Two-layer exchange flow with a small interface jump (Sec. 4, first Riemann problem): lower /
+    upper thicknesses (0.5, 0.5) for x < 0.3 and (0.55, 0.45) beyond, both layers moving with
+    U = 2.5, flat bottom, G = 10.  On the periodic right-triangle lattice of [0, 1]^2 (the wrap at
+    x = 0 adds a second jump), so the data are invariant under the lattice's y translations."""
+    xy, tri, L = periodic_square(n, 1.0)
+    c = xy[tri].mean(axis=1)
+    left = c[:, 0] < 0.3
+    T = tri.shape[0]
+    W0 = np.zeros((6, T))
+    W0[3] = np.where(left, 0.5, 0.55)      # lower layer h1
+    W0[0] = np.where(left, 0.5, 0.45)      # upper layer h2
+    W0[4] = 2.5 * W0[3]
+    W0[1] = 2.5 * W0[0]
+    return Scenario(f"riemann_exchange_n{n}", xy, tri, np.zeros(xy.shape[0]), "periodic", L, G, chi,
+                    cfl, t_end, W0, np.zeros((6, 2, T)))
+
+
+def riemann_interface(nx: int = 400, ny: int = 40, seed: int = 20230611, chi: float = 0.98,
+                      cfl: float = 0.3, t_end: float = 1.0, G: float = 9.81) -> Scenario:
+    """Two-layer Riemann problem with a large interface jump (Sec. 4, second Riemann problem):
+    thicknesses (0.2, 1.8) for x < 5 and (1.8, 0.2) beyond, at rest, flat bottom, on a jittered
+    Delaunay mesh of [0, 10] x [0, 1] (cell size 1/40) with walls."""
+    xy, tri = jittered_rect(nx, ny, 10.0, 1.0, seed)
+
+    def levels(cx, cy):
+        left = cx < 5.0
+        return np.where(left, 0.2, 1.8), np.where(left, 1.8, 0.2)
+
+    return _level_state(f"riemann_interface_{nx}x{ny}", xy, tri, np.zeros(xy.shape[0]), chi, cfl, t_end, G,
+                        levels, 0.0, None)
+
+
+def circular_interface(n: int = 100, seed: int = 20230612, chi: float = 0.98, cfl: float = 0.3,
+                       t_end: float = 4.0, G: float = 9.81) -> Scenario:
+    """Circular interface propagation (Sec. 4): thicknesses (1.8, 0.2) inside the circle of radius 2
+    about (5, 5) and (0.2, 1.8) outside, at rest, flat bottom, on a jittered Delaunay mesh of
+    [0, 10]^2 (cell size 10/n) with walls."""
+    xy, tri = jittered_rect(n, n, 10.0, 10.0, seed)
+
+    def levels(cx, cy):
+        inside = (cx - 5.0) ** 2 + (cy - 5.0) ** 2 < 4.0
+        return np.where(inside, 1.8, 0.2), np.where(inside, 0.2, 1.8)
+
+    return _level_state(f"circular_interface_n{n}", xy, tri, np.zeros(xy.shape[0]), chi, cfl, t_end, G,
+                        levels, 0.0, None)
 
 
 def _ensemble_member(args):

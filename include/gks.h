@@ -8,7 +8,10 @@
  * W = (h2, h2U2, h2V2, h1, h1U1, h1V1), layer 1 the lower (density rho1), layer 2 the upper,
  * chi = rho2 / rho1, bottom B.  The solver advances cell averages and cell-averaged gradients with
  * the two-stage fourth-order (S2O4) time stepping of Sec. 3.3, each stage running the compact
- * reconstruction (Sec. 3.4), the interface force modelling (Sec. 2.3), the time-accurate
+ * reconstruction (Sec. 3.4; where a layer thickness at a Gauss point would fall below a tenth of
+ * its cell's average, the reconstruction's deviation from the average is scaled down, a
+ * positivity safeguard the paper does not state), the interface force modelling (Sec. 2.3), the
+ * time-accurate
  * gas-kinetic evolution at two Gauss points per edge (Sec. 2.2, Eq. SWE-2nd-order) and the
  * well-balanced finite-volume update with bottom and layer-coupling sources (Sec. 3.1-3.2).
  *

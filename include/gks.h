@@ -11,9 +11,9 @@
  * reconstruction (Sec. 3.4; where a layer thickness at a Gauss point would fall below a tenth of
  * its cell's average, the reconstruction's deviation from the average is scaled down, a
  * positivity safeguard the paper does not state), the interface force modelling (Sec. 2.3), the
- * time-accurate
- * gas-kinetic evolution at two Gauss points per edge (Sec. 2.2, Eq. SWE-2nd-order) and the
- * well-balanced finite-volume update with bottom and layer-coupling sources (Sec. 3.1-3.2).
+ * time-accurate gas-kinetic evolution at two Gauss points per edge (Sec. 2.2, Eq. SWE-2nd-order)
+ * and the well-balanced finite-volume update with bottom and layer-coupling sources
+ * (Sec. 3.1-3.2).
  *
  * Conventions
  *  - All pointers to user arrays are HOST pointers; the library copies them (the caller keeps

@@ -6,6 +6,8 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -22,6 +24,20 @@ gks_status fail(gks_status s, const std::string &msg)
 {
     g_err = msg;
     return s;
+}
+
+// the body of an entry point: C++ exceptions (a failed host allocation) become status codes and
+// never cross the C boundary
+template <typename F>
+gks_status guarded(F &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(GKS_ENOMEM, "host allocation failed");
+    } catch (const std::exception &x) {
+        return fail(GKS_EDEVICE, std::string("internal error: ") + x.what());
+    }
 }
 
 #define HIP_OK(expr)                                                                                      \
@@ -351,55 +367,59 @@ const char *gks_last_error(void) { return g_err.c_str(); }
 gks_status gks_mesh_create(const double *node_xy, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
                            const double *node_B, int32_t bc, const double *periodic_L, gks_mesh **out)
 {
-    if (!out || !node_xy || !tri || n_nodes <= 0 || n_tri <= 0) return fail(GKS_EINVAL, "bad mesh arguments");
-    if (bc != GKS_BC_WALL && bc != GKS_BC_PERIODIC) return fail(GKS_EINVAL, "unknown boundary kind");
-    if (n_tri > (int64_t)1 << 29) return fail(GKS_EINVAL, "mesh too large for 32-bit cell indices");
-    *out = nullptr;
-    gks_mesh *m = new gks_mesh();
-    std::string err;
-    if (gks::build_host_mesh(node_xy, n_nodes, tri, n_tri, node_B, bc, periodic_L, m->host, err) != 0) {
-        delete m;
-        return fail(GKS_EMESH, err);
-    }
-    if (hipGetDevice(&m->device) != hipSuccess) {
-        delete m;
-        return fail(GKS_EDEVICE, "no HIP device");
-    }
-    gks_status r = upload_mesh(m);
-    if (r != GKS_OK) {
-        gks_mesh_destroy(m);
-        return r;
-    }
-    *out = m;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!out || !node_xy || !tri || n_nodes <= 0 || n_tri <= 0) return fail(GKS_EINVAL, "bad mesh arguments");
+        if (bc != GKS_BC_WALL && bc != GKS_BC_PERIODIC) return fail(GKS_EINVAL, "unknown boundary kind");
+        if (n_tri > (int64_t)1 << 29) return fail(GKS_EINVAL, "mesh too large for 32-bit cell indices");
+        *out = nullptr;
+        gks_mesh *m = new gks_mesh();
+        std::string err;
+        if (gks::build_host_mesh(node_xy, n_nodes, tri, n_tri, node_B, bc, periodic_L, m->host, err) != 0) {
+            delete m;
+            return fail(GKS_EMESH, err);
+        }
+        if (hipGetDevice(&m->device) != hipSuccess) {
+            delete m;
+            return fail(GKS_EDEVICE, "no HIP device");
+        }
+        gks_status r = upload_mesh(m);
+        if (r != GKS_OK) {
+            gks_mesh_destroy(m);
+            return r;
+        }
+        *out = m;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_mesh_batch(const gks_mesh *const *meshes, int32_t n, gks_mesh **out)
 {
-    if (!meshes || n <= 0 || !out) return fail(GKS_EINVAL, "bad batch arguments");
-    *out = nullptr;
-    std::vector<const gks::HostMesh *> parts;
-    int64_t T = 0;
-    for (int32_t i = 0; i < n; i++) {
-        if (!meshes[i]) return fail(GKS_EINVAL, "null mesh in batch");
-        if (meshes[i]->host.S != 1) return fail(GKS_EINVAL, "batches cannot be nested");
-        parts.push_back(&meshes[i]->host);
-        T += meshes[i]->host.nt + meshes[i]->host.ng;
-    }
-    if (T > (int64_t)1 << 30) return fail(GKS_EINVAL, "batch too large for 32-bit cell indices");
-    gks_mesh *m = new gks_mesh();
-    m->host = gks::concat_host_meshes(parts);
-    if (hipGetDevice(&m->device) != hipSuccess) {
-        delete m;
-        return fail(GKS_EDEVICE, "no HIP device");
-    }
-    gks_status r = upload_mesh(m);
-    if (r != GKS_OK) {
-        gks_mesh_destroy(m);
-        return r;
-    }
-    *out = m;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!meshes || n <= 0 || !out) return fail(GKS_EINVAL, "bad batch arguments");
+        *out = nullptr;
+        std::vector<const gks::HostMesh *> parts;
+        int64_t T = 0;
+        for (int32_t i = 0; i < n; i++) {
+            if (!meshes[i]) return fail(GKS_EINVAL, "null mesh in batch");
+            if (meshes[i]->host.S != 1) return fail(GKS_EINVAL, "batches cannot be nested");
+            parts.push_back(&meshes[i]->host);
+            T += meshes[i]->host.nt + meshes[i]->host.ng;
+        }
+        if (T > (int64_t)1 << 30) return fail(GKS_EINVAL, "batch too large for 32-bit cell indices");
+        gks_mesh *m = new gks_mesh();
+        m->host = gks::concat_host_meshes(parts);
+        if (hipGetDevice(&m->device) != hipSuccess) {
+            delete m;
+            return fail(GKS_EDEVICE, "no HIP device");
+        }
+        gks_status r = upload_mesh(m);
+        if (r != GKS_OK) {
+            gks_mesh_destroy(m);
+            return r;
+        }
+        *out = m;
+        return GKS_OK;
+    });
 }
 
 void gks_mesh_destroy(gks_mesh *m)
@@ -411,121 +431,135 @@ void gks_mesh_destroy(gks_mesh *m)
 
 gks_status gks_mesh_info(const gks_mesh *m, int64_t *n_tri, int64_t *n_edges, int64_t *n_ghost, int32_t *n_scen)
 {
-    if (!m) return fail(GKS_EINVAL, "null mesh");
-    if (n_tri) *n_tri = m->host.nt;
-    if (n_edges) *n_edges = m->host.ne;
-    if (n_ghost) *n_ghost = m->host.ng;
-    if (n_scen) *n_scen = m->host.S;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!m) return fail(GKS_EINVAL, "null mesh");
+        if (n_tri) *n_tri = m->host.nt;
+        if (n_edges) *n_edges = m->host.ne;
+        if (n_ghost) *n_ghost = m->host.ng;
+        if (n_scen) *n_scen = m->host.S;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_mesh_scenario(const gks_mesh *m, int32_t s, int64_t *first_cell, int64_t *n_cells)
 {
-    if (!m || s < 0 || s >= m->host.S) return fail(GKS_EINVAL, "bad scenario index");
-    if (first_cell) *first_cell = m->host.scell[s];
-    if (n_cells) *n_cells = m->host.scell[s + 1] - m->host.scell[s];
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!m || s < 0 || s >= m->host.S) return fail(GKS_EINVAL, "bad scenario index");
+        if (first_cell) *first_cell = m->host.scell[s];
+        if (n_cells) *n_cells = m->host.scell[s + 1] - m->host.scell[s];
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const double *W0, const double *gradW0,
                           void *stream, gks_state **out)
 {
-    if (!mesh_c || !prm || !W0 || !gradW0 || !out) return fail(GKS_EINVAL, "null argument");
-    gks_mesh *mesh = const_cast<gks_mesh *>(mesh_c);
-    const gks::HostMesh &h = mesh->host;
-    const int32_t S = h.S;
-    for (int32_t s = 0; s < S; s++) {
-        const gks_params &q = prm[s];
-        if (q.precision != GKS_FP64 && q.precision != GKS_FP32_MIXED)
-            return fail(GKS_EUNSUPPORTED, "unknown precision");
-        if (!(q.G > 0) || !(q.cfl > 0) || !(q.chi > 0) || !(q.eps > 0) || !(q.eps_num >= 0))
-            return fail(GKS_EINVAL, "bad physical parameters");
-        if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
-            q.precision != prm[0].precision || q.linear != prm[0].linear)
-            return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision and linear");
-    }
-    *out = nullptr;
-    const int prec = prm[0].precision;
-    if (prec == GKS_FP32_MIXED) {
-        gks_status r = ensure_f32(mesh);
-        if (r != GKS_OK) return r;
-    }
-    const int64_t T = h.nt, TG = T + h.ng, E = h.ne;
-    // host conversion: the device state carries eta1 = h1 + B and grad(eta1)
-    std::vector<double> wh(2 * TG, 0.0), wm(4 * TG, 0.0), g(12 * TG, 0.0);
-    for (int v = 0; v < 6; v++)
-        for (int64_t c = 0; c < T; c++) {
-            double x = W0[v * T + c];
-            if (!std::isfinite(x) || ((v == 0 || v == 3) && !(x > 0)))
-                return fail(GKS_ENONFINITE, "bad initial value at component " + std::to_string(v) + ", cell " +
-                                                std::to_string(c));
-            if (v == 0) wh[c] = x;
-            else if (v == 3) wh[TG + c] = x + h.Bbar[c];
-            else wm[(v < 3 ? v - 1 : v - 2) * TG + c] = x;
-            for (int d = 0; d < 2; d++) {
-                double y = gradW0[(2 * v + d) * T + c];
-                if (!std::isfinite(y)) return fail(GKS_ENONFINITE, "non-finite initial gradient");
-                g[(2 * v + d) * TG + c] = v == 3 ? y + h.gB[d * T + c] : y;
+    return guarded([&]() -> gks_status {
+        if (!mesh_c || !prm || !W0 || !gradW0 || !out) return fail(GKS_EINVAL, "null argument");
+        gks_mesh *mesh = const_cast<gks_mesh *>(mesh_c);
+        const gks::HostMesh &h = mesh->host;
+        const int32_t S = h.S;
+        for (int32_t s = 0; s < S; s++) {
+            const gks_params &q = prm[s];
+            if (q.precision != GKS_FP64 && q.precision != GKS_FP32_MIXED)
+                return fail(GKS_EUNSUPPORTED, "unknown precision");
+            if (!(q.G > 0) || !(q.cfl > 0) || !(q.chi > 0) || !(q.eps > 0) || !(q.eps_num >= 0))
+                return fail(GKS_EINVAL, "bad physical parameters");
+            if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
+                q.precision != prm[0].precision || q.linear != prm[0].linear)
+                return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision and linear");
+        }
+        *out = nullptr;
+        const int prec = prm[0].precision;
+        if (prec == GKS_FP32_MIXED) {
+            gks_status r = ensure_f32(mesh);
+            if (r != GKS_OK) return r;
+        }
+        const int64_t T = h.nt, TG = T + h.ng, E = h.ne;
+        // host conversion: the device state carries eta1 = h1 + B and grad(eta1)
+        std::vector<double> wh(2 * TG, 0.0), wm(4 * TG, 0.0), g(12 * TG, 0.0);
+        for (int v = 0; v < 6; v++)
+            for (int64_t c = 0; c < T; c++) {
+                double x = W0[v * T + c];
+                if (!std::isfinite(x) || ((v == 0 || v == 3) && !(x > 0)))
+                    return fail(GKS_ENONFINITE, "bad initial value at component " + std::to_string(v) + ", cell " +
+                                                    std::to_string(c));
+                if (v == 0) wh[c] = x;
+                else if (v == 3) wh[TG + c] = x + h.Bbar[c];
+                else wm[(v < 3 ? v - 1 : v - 2) * TG + c] = x;
+                for (int d = 0; d < 2; d++) {
+                    double y = gradW0[(2 * v + d) * T + c];
+                    if (!std::isfinite(y)) return fail(GKS_ENONFINITE, "non-finite initial gradient");
+                    g[(2 * v + d) * TG + c] = v == 3 ? y + h.gB[d * T + c] : y;
+                }
             }
+        gks_state *s = new gks_state();
+        s->mesh = mesh;
+        s->prec = prec;
+        s->md = prec == GKS_FP64 ? mesh->d64 : mesh->d32;
+        s->stream = (hipStream_t)stream;
+        s->nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (T + gks::DT_BLOCK - 1) / gks::DT_BLOCK));
+        const size_t rs = prec == GKS_FP64 ? sizeof(double) : sizeof(float);
+        const size_t uT = (size_t)T, uTG = (size_t)TG, uE = (size_t)E, uS = (size_t)S;
+        struct Buf {
+            void **p;
+            size_t bytes;
+        } bufs[] = {{(void **)&s->Wh[0], 2 * uTG * 8}, {(void **)&s->Wh[1], 2 * uTG * 8}, {&s->Wm[0], 4 * uTG * rs},
+                    {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
+                    {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
+                    {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
+                    {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
+                    {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
+                    {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
+        for (auto &b : bufs) {
+            hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
+            if (e != hipSuccess) {
+                gks_state_destroy(s);
+                return fail(GKS_ENOMEM, std::string("state allocation: ") + hipGetErrorString(e));
+            }
+            s->owned.push_back(*b.p);
         }
-    gks_state *s = new gks_state();
-    s->mesh = mesh;
-    s->prec = prec;
-    s->md = prec == GKS_FP64 ? mesh->d64 : mesh->d32;
-    s->stream = (hipStream_t)stream;
-    s->nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (T + gks::DT_BLOCK - 1) / gks::DT_BLOCK));
-    const size_t rs = prec == GKS_FP64 ? sizeof(double) : sizeof(float);
-    const size_t uT = (size_t)T, uTG = (size_t)TG, uE = (size_t)E, uS = (size_t)S;
-    struct Buf {
-        void **p;
-        size_t bytes;
-    } bufs[] = {{(void **)&s->Wh[0], 2 * uTG * 8}, {(void **)&s->Wh[1], 2 * uTG * 8}, {&s->Wm[0], 4 * uTG * rs},
-                {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
-                {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
-                {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
-                {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
-                {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
-                {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
-    for (auto &b : bufs) {
-        hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
-        if (e != hipSuccess) {
+        std::vector<double> chi(S), tend(S), scal(2 * S, 0.0);
+        for (int32_t i = 0; i < S; i++) {
+            chi[i] = prm[i].chi;
+            tend[i] = prm[i].t_end > 0 ? prm[i].t_end : 1e300;
+        }
+        s->p.G = prm[0].G;
+        s->p.eps = prm[0].eps;
+        s->p.eps_num = prm[0].eps_num;
+        s->p.cfl = prm[0].cfl;
+        s->p.linear = prm[0].linear;
+        s->p.chi = s->chi;
+        s->p.t_end = s->tend;
+        s->p.scal = s->scal;
+        std::vector<unsigned char> bm, bg;
+        if (prec == GKS_FP64) {
+            to_real<double>(wm, bm);
+            to_real<double>(g, bg);
+        } else {
+            to_real<float>(wm, bm);
+            to_real<float>(g, bg);
+        }
+        // a failed copy releases the partly built state
+        const gks_status r = [&]() -> gks_status {
+            HIP_OK(hipMemcpy(s->Wh[0], wh.data(), wh.size() * 8, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(s->Wm[0], bm.data(), bm.size(), hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(s->gW[0], bg.data(), bg.size(), hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(s->chi, chi.data(), S * 8, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(s->tend, tend.data(), S * 8, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(s->scal, scal.data(), 2 * S * 8, hipMemcpyHostToDevice));
+            HIP_OK(hipMemset(s->Wh[1], 0, 2 * TG * 8));
+            HIP_OK(hipMemset(s->Wm[1], 0, 4 * TG * rs));
+            HIP_OK(hipMemset(s->gW[1], 0, 12 * TG * rs));
+            return GKS_OK;
+        }();
+        if (r != GKS_OK) {
             gks_state_destroy(s);
-            return fail(GKS_ENOMEM, std::string("state allocation: ") + hipGetErrorString(e));
+            return r;
         }
-        s->owned.push_back(*b.p);
-    }
-    std::vector<double> chi(S), tend(S), scal(2 * S, 0.0);
-    for (int32_t i = 0; i < S; i++) {
-        chi[i] = prm[i].chi;
-        tend[i] = prm[i].t_end > 0 ? prm[i].t_end : 1e300;
-    }
-    s->p.G = prm[0].G;
-    s->p.eps = prm[0].eps;
-    s->p.eps_num = prm[0].eps_num;
-    s->p.cfl = prm[0].cfl;
-    s->p.linear = prm[0].linear;
-    s->p.chi = s->chi;
-    s->p.t_end = s->tend;
-    s->p.scal = s->scal;
-    std::vector<unsigned char> bm, bg;
-    if (prec == GKS_FP64) {
-        to_real<double>(wm, bm);
-        to_real<double>(g, bg);
-    } else {
-        to_real<float>(wm, bm);
-        to_real<float>(g, bg);
-    }
-    HIP_OK(hipMemcpy(s->Wh[0], wh.data(), wh.size() * 8, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->Wm[0], bm.data(), bm.size(), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->gW[0], bg.data(), bg.size(), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->chi, chi.data(), S * 8, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->tend, tend.data(), S * 8, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(s->scal, scal.data(), 2 * S * 8, hipMemcpyHostToDevice));
-    HIP_OK(hipMemset(s->Wh[1], 0, 2 * TG * 8));
-    HIP_OK(hipMemset(s->Wm[1], 0, 4 * TG * rs));
-    HIP_OK(hipMemset(s->gW[1], 0, 12 * TG * rs));
-    *out = s;
-    return GKS_OK;
+        *out = s;
+        return GKS_OK;
+    });
 }
 
 void gks_state_destroy(gks_state *s)
@@ -545,168 +579,184 @@ void gks_state_destroy(gks_state *s)
 
 gks_status gks_profile(gks_state *s, int32_t enable)
 {
-    if (!s) return fail(GKS_EINVAL, "null state");
-    HIP_OK(hipStreamSynchronize(s->stream));
-    s->prof.clear();
-    s->ev_used = 0;
-    s->prof_on = enable != 0;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s) return fail(GKS_EINVAL, "null state");
+        HIP_OK(hipStreamSynchronize(s->stream));
+        s->prof.clear();
+        s->ev_used = 0;
+        s->prof_on = enable != 0;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_profile_read(gks_state *s, int32_t kernel, double *total_ms, int64_t *launches)
 {
-    if (!s || kernel < 0 || kernel >= GKS_KERNEL_COUNT) return fail(GKS_EINVAL, "bad profile query");
-    HIP_OK(hipStreamSynchronize(s->stream));
-    double tot = 0;
-    int64_t n = 0;
-    for (const auto &r : s->prof)
-        if (r.kernel == kernel) {
-            float ms = 0;
-            HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
-            tot += ms;
-            n++;
-        }
-    if (total_ms) *total_ms = tot;
-    if (launches) *launches = n;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || kernel < 0 || kernel >= GKS_KERNEL_COUNT) return fail(GKS_EINVAL, "bad profile query");
+        HIP_OK(hipStreamSynchronize(s->stream));
+        double tot = 0;
+        int64_t n = 0;
+        for (const auto &r : s->prof)
+            if (r.kernel == kernel) {
+                float ms = 0;
+                HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+                tot += ms;
+                n++;
+            }
+        if (total_ms) *total_ms = tot;
+        if (launches) *launches = n;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_stage(gks_state *s, int32_t stage, const double *dt)
 {
-    if (!s || (stage != 0 && stage != 1)) return fail(GKS_EINVAL, "bad stage arguments");
-    if (stage == 1 && !s->half) return fail(GKS_EINVAL, "stage 1 must follow stage 0");
-    if (stage == 0 && s->half) return fail(GKS_EINVAL, "stage 0 must follow stage 1");
-    if (stage == 0) {
-        if (dt) {
-            if (s->md.S != 1) return fail(GKS_EINVAL, "an explicit dt needs a single-scenario state");
-            if (!(*dt > 0) || !std::isfinite(*dt)) return fail(GKS_EINVAL, "dt must be positive");
-            hipLaunchKernelGGL(gks::k_set_dt, dim3(1), dim3(1), 0, s->stream, s->p, *dt);
-        } else {
-            dt_any(s, s->stream);
+    return guarded([&]() -> gks_status {
+        if (!s || (stage != 0 && stage != 1)) return fail(GKS_EINVAL, "bad stage arguments");
+        if (stage == 1 && !s->half) return fail(GKS_EINVAL, "stage 1 must follow stage 0");
+        if (stage == 0 && s->half) return fail(GKS_EINVAL, "stage 0 must follow stage 1");
+        if (stage == 0) {
+            if (dt) {
+                if (s->md.S != 1) return fail(GKS_EINVAL, "an explicit dt needs a single-scenario state");
+                if (!(*dt > 0) || !std::isfinite(*dt)) return fail(GKS_EINVAL, "dt must be positive");
+                hipLaunchKernelGGL(gks::k_set_dt, dim3(1), dim3(1), 0, s->stream, s->p, *dt);
+            } else {
+                dt_any(s, s->stream);
+            }
+        } else if (dt) {
+            return fail(GKS_EINVAL, "stage 1 reuses the step size of stage 0");
         }
-    } else if (dt) {
-        return fail(GKS_EINVAL, "stage 1 reuses the step size of stage 0");
-    }
-    stage_any(s, stage, s->stream);
-    HIP_OK(hipGetLastError());
-    s->half = stage == 0;
-    return GKS_OK;
+        stage_any(s, stage, s->stream);
+        HIP_OK(hipGetLastError());
+        s->half = stage == 0;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_step(gks_state *s, int32_t n_steps, double *dt_last)
 {
-    if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
-    if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
-    for (int i = 0; i < n_steps; i++) {
-        dt_any(s, s->stream);
-        stage_any(s, 0, s->stream);
-        stage_any(s, 1, s->stream);
-        HIP_OK(hipGetLastError());
-    }
-    if (dt_last) {
-        double sc[2];
-        HIP_OK(hipMemcpyAsync(sc, s->scal, sizeof(sc), hipMemcpyDeviceToHost, s->stream));
-        HIP_OK(hipStreamSynchronize(s->stream));
-        *dt_last = sc[0];
-    }
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
+        if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
+        for (int i = 0; i < n_steps; i++) {
+            dt_any(s, s->stream);
+            stage_any(s, 0, s->stream);
+            stage_any(s, 1, s->stream);
+            HIP_OK(hipGetLastError());
+        }
+        if (dt_last) {
+            double sc[2];
+            HIP_OK(hipMemcpyAsync(sc, s->scal, sizeof(sc), hipMemcpyDeviceToHost, s->stream));
+            HIP_OK(hipStreamSynchronize(s->stream));
+            *dt_last = sc[0];
+        }
+        return GKS_OK;
+    });
 }
 
 gks_status gks_batch_step(gks_state *s, int32_t n_steps)
 {
-    if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
-    if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
-    if (!s->gexec) {
-        // capture one full step (every scenario's dt, both stages) on a private stream
-        HIP_OK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
-        HIP_OK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
-        HIP_OK(hipEventCreateWithFlags(&s->gev[1], hipEventDisableTiming));
-        s->capturing = true;
-        HIP_OK(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
-        dt_any(s, s->gstream);
-        stage_any(s, 0, s->gstream);
-        stage_any(s, 1, s->gstream);
-        hipError_t e = hipStreamEndCapture(s->gstream, &s->graph);
-        s->capturing = false;
-        HIP_OK(e);
-        HIP_OK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
-    }
-    // order the graph replays after the work already queued on the state's stream, and later
-    // work on that stream after them
-    HIP_OK(hipEventRecord(s->gev[0], s->stream));
-    HIP_OK(hipStreamWaitEvent(s->gstream, s->gev[0], 0));
-    for (int i = 0; i < n_steps; i++) HIP_OK(hipGraphLaunch(s->gexec, s->gstream));
-    HIP_OK(hipEventRecord(s->gev[1], s->gstream));
-    HIP_OK(hipStreamWaitEvent(s->stream, s->gev[1], 0));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || n_steps < 0) return fail(GKS_EINVAL, "bad step arguments");
+        if (s->half) return fail(GKS_EINVAL, "a step cannot start between stage 0 and stage 1");
+        if (!s->gexec) {
+            // capture one full step (every scenario's dt, both stages) on a private stream
+            HIP_OK(hipStreamCreateWithFlags(&s->gstream, hipStreamNonBlocking));
+            HIP_OK(hipEventCreateWithFlags(&s->gev[0], hipEventDisableTiming));
+            HIP_OK(hipEventCreateWithFlags(&s->gev[1], hipEventDisableTiming));
+            s->capturing = true;
+            HIP_OK(hipStreamBeginCapture(s->gstream, hipStreamCaptureModeThreadLocal));
+            dt_any(s, s->gstream);
+            stage_any(s, 0, s->gstream);
+            stage_any(s, 1, s->gstream);
+            hipError_t e = hipStreamEndCapture(s->gstream, &s->graph);
+            s->capturing = false;
+            HIP_OK(e);
+            HIP_OK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+        }
+        // order the graph replays after the work already queued on the state's stream, and later
+        // work on that stream after them
+        HIP_OK(hipEventRecord(s->gev[0], s->stream));
+        HIP_OK(hipStreamWaitEvent(s->gstream, s->gev[0], 0));
+        for (int i = 0; i < n_steps; i++) HIP_OK(hipGraphLaunch(s->gexec, s->gstream));
+        HIP_OK(hipEventRecord(s->gev[1], s->gstream));
+        HIP_OK(hipStreamWaitEvent(s->stream, s->gev[1], 0));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_read(const gks_state *s, double *W, double *gradW, double *t)
 {
-    if (!s) return fail(GKS_EINVAL, "null state");
-    const gks::HostMesh &h = s->mesh->host;
-    const int64_t T = h.nt, TG = T + h.ng;
-    const int b = s->half ? 1 : 0;
-    const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
-    HIP_OK(hipStreamSynchronize(s->stream));
-    if (W) {
-        std::vector<double> wh(2 * TG), wm;
-        std::vector<unsigned char> raw(4 * TG * rs);
-        HIP_OK(hipMemcpy(wh.data(), s->Wh[b], wh.size() * 8, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(raw.data(), s->Wm[b], raw.size(), hipMemcpyDeviceToHost));
-        if (s->prec == GKS_FP64) from_real<double>(raw, wm); else from_real<float>(raw, wm);
-        for (int64_t c = 0; c < T; c++) {
-            W[c] = wh[c];
-            W[3 * T + c] = wh[TG + c] - h.Bbar[c];
-            W[T + c] = wm[c];
-            W[2 * T + c] = wm[TG + c];
-            W[4 * T + c] = wm[2 * TG + c];
-            W[5 * T + c] = wm[3 * TG + c];
+    return guarded([&]() -> gks_status {
+        if (!s) return fail(GKS_EINVAL, "null state");
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t T = h.nt, TG = T + h.ng;
+        const int b = s->half ? 1 : 0;
+        const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
+        HIP_OK(hipStreamSynchronize(s->stream));
+        if (W) {
+            std::vector<double> wh(2 * TG), wm;
+            std::vector<unsigned char> raw(4 * TG * rs);
+            HIP_OK(hipMemcpy(wh.data(), s->Wh[b], wh.size() * 8, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(raw.data(), s->Wm[b], raw.size(), hipMemcpyDeviceToHost));
+            if (s->prec == GKS_FP64) from_real<double>(raw, wm); else from_real<float>(raw, wm);
+            for (int64_t c = 0; c < T; c++) {
+                W[c] = wh[c];
+                W[3 * T + c] = wh[TG + c] - h.Bbar[c];
+                W[T + c] = wm[c];
+                W[2 * T + c] = wm[TG + c];
+                W[4 * T + c] = wm[2 * TG + c];
+                W[5 * T + c] = wm[3 * TG + c];
+            }
         }
-    }
-    if (gradW) {
-        std::vector<double> g;
-        std::vector<unsigned char> raw(12 * TG * rs);
-        HIP_OK(hipMemcpy(raw.data(), s->gW[b], raw.size(), hipMemcpyDeviceToHost));
-        if (s->prec == GKS_FP64) from_real<double>(raw, g); else from_real<float>(raw, g);
-        for (int v = 0; v < 6; v++)
-            for (int d = 0; d < 2; d++)
-                for (int64_t c = 0; c < T; c++)
-                    gradW[(2 * v + d) * T + c] = v == 3 ? g[(2 * v + d) * TG + c] - h.gB[d * T + c] : g[(2 * v + d) * TG + c];
-    }
-    if (t) return gks_state_time(s, 0, t, nullptr);
-    return GKS_OK;
+        if (gradW) {
+            std::vector<double> g;
+            std::vector<unsigned char> raw(12 * TG * rs);
+            HIP_OK(hipMemcpy(raw.data(), s->gW[b], raw.size(), hipMemcpyDeviceToHost));
+            if (s->prec == GKS_FP64) from_real<double>(raw, g); else from_real<float>(raw, g);
+            for (int v = 0; v < 6; v++)
+                for (int d = 0; d < 2; d++)
+                    for (int64_t c = 0; c < T; c++)
+                        gradW[(2 * v + d) * T + c] = v == 3 ? g[(2 * v + d) * TG + c] - h.gB[d * T + c] : g[(2 * v + d) * TG + c];
+        }
+        if (t) return gks_state_time(s, 0, t, nullptr);
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_time(const gks_state *s, int32_t scen, double *t, double *dt)
 {
-    if (!s || scen < 0 || scen >= s->md.S) return fail(GKS_EINVAL, "bad scenario index");
-    double sc[2];
-    HIP_OK(hipStreamSynchronize(s->stream));
-    HIP_OK(hipMemcpy(sc, s->scal + 2 * scen, sizeof(sc), hipMemcpyDeviceToHost));
-    if (t) *t = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
-    if (dt) *dt = sc[0];
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || scen < 0 || scen >= s->md.S) return fail(GKS_EINVAL, "bad scenario index");
+        double sc[2];
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(sc, s->scal + 2 * scen, sizeof(sc), hipMemcpyDeviceToHost));
+        if (t) *t = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
+        if (dt) *dt = sc[0];
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_mass(const gks_state *s, int32_t scen, double mass[2])
 {
-    if (!s || !mass || scen < -1 || scen >= s->md.S) return fail(GKS_EINVAL, "bad mass query");
-    const gks::HostMesh &h = s->mesh->host;
-    const int64_t c0 = scen < 0 ? 0 : h.scell[scen], c1 = scen < 0 ? h.nt : h.scell[scen + 1];
-    const int nb = 256;
-    hipLaunchKernelGGL(gks::k_mass_partial, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[s->half ? 1 : 0], c0, c1,
-                       s->part);
-    HIP_OK(hipGetLastError());
-    std::vector<double> part(2 * nb);
-    HIP_OK(hipMemcpyAsync(part.data(), s->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIP_OK(hipStreamSynchronize(s->stream));
-    mass[0] = mass[1] = 0;
-    for (int b = 0; b < nb; b++) {
-        mass[0] += part[2 * b];
-        mass[1] += part[2 * b + 1];
-    }
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || !mass || scen < -1 || scen >= s->md.S) return fail(GKS_EINVAL, "bad mass query");
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t c0 = scen < 0 ? 0 : h.scell[scen], c1 = scen < 0 ? h.nt : h.scell[scen + 1];
+        const int nb = 256;
+        hipLaunchKernelGGL(gks::k_mass_partial, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[s->half ? 1 : 0], c0, c1,
+                           s->part);
+        HIP_OK(hipGetLastError());
+        std::vector<double> part(2 * nb);
+        HIP_OK(hipMemcpyAsync(part.data(), s->part, part.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+        mass[0] = mass[1] = 0;
+        for (int b = 0; b < nb; b++) {
+            mass[0] += part[2 * b];
+            mass[1] += part[2 * b + 1];
+        }
+        return GKS_OK;
+    });
 }
 
 }  // extern "C"
@@ -754,26 +804,28 @@ gks_status read_buffer(const gks_state *s, int32_t which, void *dst)
 
 extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *dst, int64_t bytes)
 {
-    if (!s || !dst || which < 0 || which >= GKS_BUF_COUNT) return fail(GKS_EINVAL, "bad buffer query");
-    const int64_t T = s->md.T, E = s->md.E;
-    const int64_t rs = s->prec == GKS_FP64 ? 8 : 4;
-    int64_t need = 0;
-    switch (which) {
-    case GKS_BUF_RECH: need = 12 * T * 8; break;
-    case GKS_BUF_RECM: need = 96 * T * rs; break;
-    case GKS_BUF_R0: need = 2 * T * rs; break;
-    case GKS_BUF_EOH: need = 4 * E * 8; break;
-    case GKS_BUF_SKIP: need = T; break;
-    default: need = 22 * E * rs; break;
-    }
-    if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
-    HIP_OK(hipStreamSynchronize(s->stream));
-    if (which == GKS_BUF_SKIP) {
-        if (!s->smooth) return fail(GKS_EINVAL, "the indicator has never been switched on");
-        HIP_OK(hipMemcpy(dst, s->smooth, (size_t)T, hipMemcpyDeviceToHost));
-        return GKS_OK;
-    }
-    return s->prec == GKS_FP64 ? read_buffer<double>(s, which, dst) : read_buffer<float>(s, which, dst);
+    return guarded([&]() -> gks_status {
+        if (!s || !dst || which < 0 || which >= GKS_BUF_COUNT) return fail(GKS_EINVAL, "bad buffer query");
+        const int64_t T = s->md.T, E = s->md.E;
+        const int64_t rs = s->prec == GKS_FP64 ? 8 : 4;
+        int64_t need = 0;
+        switch (which) {
+        case GKS_BUF_RECH: need = 12 * T * 8; break;
+        case GKS_BUF_RECM: need = 96 * T * rs; break;
+        case GKS_BUF_R0: need = 2 * T * rs; break;
+        case GKS_BUF_EOH: need = 4 * E * 8; break;
+        case GKS_BUF_SKIP: need = T; break;
+        default: need = 22 * E * rs; break;
+        }
+        if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
+        HIP_OK(hipStreamSynchronize(s->stream));
+        if (which == GKS_BUF_SKIP) {
+            if (!s->smooth) return fail(GKS_EINVAL, "the indicator has never been switched on");
+            HIP_OK(hipMemcpy(dst, s->smooth, (size_t)T, hipMemcpyDeviceToHost));
+            return GKS_OK;
+        }
+        return s->prec == GKS_FP64 ? read_buffer<double>(s, which, dst) : read_buffer<float>(s, which, dst);
+    });
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -910,143 +962,153 @@ extern "C" {
 
 gks_status gks_indicator_set(gks_state *s, const float *params, float threshold)
 {
-    if (!s) return fail(GKS_EINVAL, "null state");
-    if (!params) {
-        if (s->ind_on) drop_graph(s);
-        s->ind_on = false;
+    return guarded([&]() -> gks_status {
+        if (!s) return fail(GKS_EINVAL, "null state");
+        if (!params) {
+            if (s->ind_on) drop_graph(s);
+            s->ind_on = false;
+            return GKS_OK;
+        }
+        if (!std::isfinite(threshold)) return fail(GKS_EINVAL, "threshold must be finite");
+        for (int i = 0; i < gks::MLP_NP; i++)
+            if (!std::isfinite(params[i])) return fail(GKS_ENONFINITE, "non-finite indicator parameter");
+        const size_t T = (size_t)s->md.T;
+        gks_status r = state_alloc(s, (void **)&s->ind_P, gks::MLP_NP * sizeof(float));
+        if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W1b, gks::MLP_K * gks::MLP_H * sizeof(short));
+        if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W2b, gks::MLP_H * gks::MLP_H * sizeof(short));
+        if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_logit, T * sizeof(float));
+        if (r == GKS_OK) r = state_alloc(s, (void **)&s->smooth, T);
+        if (r != GKS_OK) return r;
+        // the captured graph (if any) holds the launches without the indicator
+        drop_graph(s);
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(s->ind_P, params, gks::MLP_NP * sizeof(float), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(gks::k_weights_bf16, dim3(blocks(gks::MLP_H * gks::MLP_H, 256)), dim3(256), 0, s->stream,
+                           s->ind_P, s->ind_W1b, s->ind_W2b);
+        HIP_OK(hipGetLastError());
+        s->ind_thr = threshold;
+        s->ind_on = true;
         return GKS_OK;
-    }
-    if (!std::isfinite(threshold)) return fail(GKS_EINVAL, "threshold must be finite");
-    for (int i = 0; i < gks::MLP_NP; i++)
-        if (!std::isfinite(params[i])) return fail(GKS_ENONFINITE, "non-finite indicator parameter");
-    const size_t T = (size_t)s->md.T;
-    gks_status r = state_alloc(s, (void **)&s->ind_P, gks::MLP_NP * sizeof(float));
-    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W1b, gks::MLP_K * gks::MLP_H * sizeof(short));
-    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_W2b, gks::MLP_H * gks::MLP_H * sizeof(short));
-    if (r == GKS_OK) r = state_alloc(s, (void **)&s->ind_logit, T * sizeof(float));
-    if (r == GKS_OK) r = state_alloc(s, (void **)&s->smooth, T);
-    if (r != GKS_OK) return r;
-    // the captured graph (if any) holds the launches without the indicator
-    drop_graph(s);
-    HIP_OK(hipStreamSynchronize(s->stream));
-    HIP_OK(hipMemcpy(s->ind_P, params, gks::MLP_NP * sizeof(float), hipMemcpyHostToDevice));
-    hipLaunchKernelGGL(gks::k_weights_bf16, dim3(blocks(gks::MLP_H * gks::MLP_H, 256)), dim3(256), 0, s->stream,
-                       s->ind_P, s->ind_W1b, s->ind_W2b);
-    HIP_OK(hipGetLastError());
-    s->ind_thr = threshold;
-    s->ind_on = true;
-    return GKS_OK;
+    });
 }
 
 gks_status gks_indicator_eval(gks_state *s, float *logits, uint8_t *mask, int64_t *n_skip)
 {
-    if (!s) return fail(GKS_EINVAL, "null state");
-    if (!s->ind_on) return fail(GKS_EINVAL, "the indicator is off");
-    const gks::MeshDev &m = s->md;
-    const int b = s->half ? 1 : 0;
-    if (s->prec == GKS_FP64) {
-        ghost_latest<double>(s, b);
-        hipLaunchKernelGGL(gks::k_indicator<double>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
-                           dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const double *)s->Wm[b],
-                           (const double *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
-                           s->ind_logit);
-    } else {
-        ghost_latest<float>(s, b);
-        hipLaunchKernelGGL(gks::k_indicator<float>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
-                           dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const float *)s->Wm[b],
-                           (const float *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
-                           s->ind_logit);
-    }
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(s->stream));
-    const size_t T = (size_t)m.T;
-    if (logits) HIP_OK(hipMemcpy(logits, s->ind_logit, T * sizeof(float), hipMemcpyDeviceToHost));
-    if (mask || n_skip) {
-        std::vector<uint8_t> mk(T);
-        HIP_OK(hipMemcpy(mk.data(), s->smooth, T, hipMemcpyDeviceToHost));
-        if (mask) std::memcpy(mask, mk.data(), T);
-        if (n_skip) {
-            int64_t k = 0;
-            for (uint8_t v : mk) k += v;
-            *n_skip = k;
+    return guarded([&]() -> gks_status {
+        if (!s) return fail(GKS_EINVAL, "null state");
+        if (!s->ind_on) return fail(GKS_EINVAL, "the indicator is off");
+        const gks::MeshDev &m = s->md;
+        const int b = s->half ? 1 : 0;
+        if (s->prec == GKS_FP64) {
+            ghost_latest<double>(s, b);
+            hipLaunchKernelGGL(gks::k_indicator<double>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
+                               dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const double *)s->Wm[b],
+                               (const double *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
+                               s->ind_logit);
+        } else {
+            ghost_latest<float>(s, b);
+            hipLaunchKernelGGL(gks::k_indicator<float>, dim3(blocks(m.T, 32 * gks::IND_WAVES)),
+                               dim3(64 * gks::IND_WAVES), 0, s->stream, m, s->p.G, s->Wh[b], (const float *)s->Wm[b],
+                               (const float *)s->gW[b], s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth,
+                               s->ind_logit);
         }
-    }
-    return GKS_OK;
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(s->stream));
+        const size_t T = (size_t)m.T;
+        if (logits) HIP_OK(hipMemcpy(logits, s->ind_logit, T * sizeof(float), hipMemcpyDeviceToHost));
+        if (mask || n_skip) {
+            std::vector<uint8_t> mk(T);
+            HIP_OK(hipMemcpy(mk.data(), s->smooth, T, hipMemcpyDeviceToHost));
+            if (mask) std::memcpy(mask, mk.data(), T);
+            if (n_skip) {
+                int64_t k = 0;
+                for (uint8_t v : mk) k += v;
+                *n_skip = k;
+            }
+        }
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_features(gks_state *s, float *X)
 {
-    if (!s || !X) return fail(GKS_EINVAL, "null argument");
-    const size_t T = (size_t)s->md.T;
-    float *d = nullptr;
-    HIP_OK(hipMalloc((void **)&d, T * gks::MLP_IN * sizeof(float)));
-    if (s->prec == GKS_FP64)
-        launch_features<double>(s, d);
-    else
-        launch_features<float>(s, d);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (e == hipSuccess) e = hipMemcpy(X, d, T * gks::MLP_IN * sizeof(float), hipMemcpyDeviceToHost);
-    (void)hipFree(d);
-    if (e != hipSuccess) return fail(GKS_EDEVICE, std::string("features: ") + hipGetErrorString(e));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || !X) return fail(GKS_EINVAL, "null argument");
+        const size_t T = (size_t)s->md.T;
+        float *d = nullptr;
+        HIP_OK(hipMalloc((void **)&d, T * gks::MLP_IN * sizeof(float)));
+        if (s->prec == GKS_FP64)
+            launch_features<double>(s, d);
+        else
+            launch_features<float>(s, d);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e == hipSuccess) e = hipMemcpy(X, d, T * gks::MLP_IN * sizeof(float), hipMemcpyDeviceToHost);
+        (void)hipFree(d);
+        if (e != hipSuccess) return fail(GKS_EDEVICE, std::string("features: ") + hipGetErrorString(e));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_state_labels(gks_state *s, double tol, uint8_t *y)
 {
-    if (!s || !y) return fail(GKS_EINVAL, "null argument");
-    gks_status r = labels_any(s, tol);
-    if (r != GKS_OK) return r;
-    HIP_OK(hipStreamSynchronize(s->stream));
-    HIP_OK(hipMemcpy(y, s->lab_y, (size_t)s->md.T, hipMemcpyDeviceToHost));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!s || !y) return fail(GKS_EINVAL, "null argument");
+        gks_status r = labels_any(s, tol);
+        if (r != GKS_OK) return r;
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(y, s->lab_y, (size_t)s->md.T, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_create(int64_t capacity, int32_t max_batch, const float *params0, void *stream,
                               gks_trainer **out)
 {
-    if (!out || !params0 || capacity <= 0 || max_batch <= 0 || capacity > ((int64_t)1 << 31) - 1)
-        return fail(GKS_EINVAL, "bad trainer arguments");
-    *out = nullptr;
-    for (int i = 0; i < gks::MLP_NP; i++)
-        if (!std::isfinite(params0[i])) return fail(GKS_ENONFINITE, "non-finite initial parameter");
-    gks_trainer *t = new gks_trainer();
-    t->stream = (hipStream_t)stream;
-    t->cap = capacity;
-    t->maxB = max_batch;
-    if (hipGetDevice(&t->device) != hipSuccess) {
-        delete t;
-        return fail(GKS_EDEVICE, "no HIP device");
-    }
-    const size_t C = (size_t)capacity, B = (size_t)max_batch, NP = gks::MLP_NP;
-    struct Buf {
-        void **p;
-        size_t bytes;
-    } bufs[] = {{(void **)&t->X, C * gks::MLP_IN * 4}, {(void **)&t->Y, C * 4}, {(void **)&t->logit, C * 4},
-                {(void **)&t->perm, C * 4}, {(void **)&t->P, NP * 4}, {(void **)&t->g, NP * 4},
-                {(void **)&t->mo, NP * 4}, {(void **)&t->ve, NP * 4}, {(void **)&t->H1, B * gks::MLP_H * 4},
-                {(void **)&t->H2, B * 64 * 4}, {(void **)&t->D1, B * 64 * 4}, {(void **)&t->D2, B * 64 * 4},
-                {(void **)&t->DZ, B * 4}, {(void **)&t->L, B * 4}, {(void **)&t->loss, (C / 1 + 1) * 4},
-                {(void **)&t->W1b, (size_t)gks::MLP_K * gks::MLP_H * 2},
-                {(void **)&t->W2b, (size_t)gks::MLP_H * gks::MLP_H * 2}};
-    for (auto &b : bufs) {
-        hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
+    return guarded([&]() -> gks_status {
+        if (!out || !params0 || capacity <= 0 || max_batch <= 0 || capacity > ((int64_t)1 << 31) - 1)
+            return fail(GKS_EINVAL, "bad trainer arguments");
+        *out = nullptr;
+        for (int i = 0; i < gks::MLP_NP; i++)
+            if (!std::isfinite(params0[i])) return fail(GKS_ENONFINITE, "non-finite initial parameter");
+        gks_trainer *t = new gks_trainer();
+        t->stream = (hipStream_t)stream;
+        t->cap = capacity;
+        t->maxB = max_batch;
+        if (hipGetDevice(&t->device) != hipSuccess) {
+            delete t;
+            return fail(GKS_EDEVICE, "no HIP device");
+        }
+        const size_t C = (size_t)capacity, B = (size_t)max_batch, NP = gks::MLP_NP;
+        struct Buf {
+            void **p;
+            size_t bytes;
+        } bufs[] = {{(void **)&t->X, C * gks::MLP_IN * 4}, {(void **)&t->Y, C * 4}, {(void **)&t->logit, C * 4},
+                    {(void **)&t->perm, C * 4}, {(void **)&t->P, NP * 4}, {(void **)&t->g, NP * 4},
+                    {(void **)&t->mo, NP * 4}, {(void **)&t->ve, NP * 4}, {(void **)&t->H1, B * gks::MLP_H * 4},
+                    {(void **)&t->H2, B * 64 * 4}, {(void **)&t->D1, B * 64 * 4}, {(void **)&t->D2, B * 64 * 4},
+                    {(void **)&t->DZ, B * 4}, {(void **)&t->L, B * 4}, {(void **)&t->loss, (C / 1 + 1) * 4},
+                    {(void **)&t->W1b, (size_t)gks::MLP_K * gks::MLP_H * 2},
+                    {(void **)&t->W2b, (size_t)gks::MLP_H * gks::MLP_H * 2}};
+        for (auto &b : bufs) {
+            hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
+            if (e != hipSuccess) {
+                gks_trainer_destroy(t);
+                return fail(GKS_ENOMEM, std::string("trainer allocation: ") + hipGetErrorString(e));
+            }
+            t->owned.push_back(*b.p);
+        }
+        std::vector<float> zero(NP, 0.f);
+        hipError_t e = hipMemcpy(t->P, params0, NP * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(t->mo, zero.data(), NP * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(t->ve, zero.data(), NP * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             gks_trainer_destroy(t);
-            return fail(GKS_ENOMEM, std::string("trainer allocation: ") + hipGetErrorString(e));
+            return fail(GKS_EDEVICE, std::string("trainer upload: ") + hipGetErrorString(e));
         }
-        t->owned.push_back(*b.p);
-    }
-    std::vector<float> zero(NP, 0.f);
-    hipError_t e = hipMemcpy(t->P, params0, NP * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t->mo, zero.data(), NP * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t->ve, zero.data(), NP * 4, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        gks_trainer_destroy(t);
-        return fail(GKS_EDEVICE, std::string("trainer upload: ") + hipGetErrorString(e));
-    }
-    *out = t;
-    return GKS_OK;
+        *out = t;
+        return GKS_OK;
+    });
 }
 
 void gks_trainer_destroy(gks_trainer *t)
@@ -1059,157 +1121,173 @@ void gks_trainer_destroy(gks_trainer *t)
 
 gks_status gks_trainer_add(gks_trainer *t, const float *X, const uint8_t *y, int64_t n)
 {
-    if (!t || n < 0 || (n > 0 && (!X || !y))) return fail(GKS_EINVAL, "bad sample arguments");
-    if (t->n + n > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
-    std::vector<float> yf((size_t)n);
-    int64_t pos = 0;
-    for (int64_t i = 0; i < n; i++) {
-        if (y[i] > 1) return fail(GKS_EINVAL, "labels must be 0 or 1");
-        yf[i] = (float)y[i];
-        pos += y[i];
-    }
-    for (int64_t i = 0; i < n * gks::MLP_IN; i++)
-        if (!std::isfinite(X[i])) return fail(GKS_ENONFINITE, "non-finite feature");
-    HIP_OK(hipStreamSynchronize(t->stream));
-    HIP_OK(hipMemcpy(t->X + t->n * gks::MLP_IN, X, (size_t)n * gks::MLP_IN * 4, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(t->Y + t->n, yf.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-    t->n += n;
-    t->npos += pos;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t || n < 0 || (n > 0 && (!X || !y))) return fail(GKS_EINVAL, "bad sample arguments");
+        if (t->n + n > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
+        std::vector<float> yf((size_t)n);
+        int64_t pos = 0;
+        for (int64_t i = 0; i < n; i++) {
+            if (y[i] > 1) return fail(GKS_EINVAL, "labels must be 0 or 1");
+            yf[i] = (float)y[i];
+            pos += y[i];
+        }
+        for (int64_t i = 0; i < n * gks::MLP_IN; i++)
+            if (!std::isfinite(X[i])) return fail(GKS_ENONFINITE, "non-finite feature");
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(t->X + t->n * gks::MLP_IN, X, (size_t)n * gks::MLP_IN * 4, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(t->Y + t->n, yf.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        t->n += n;
+        t->npos += pos;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_add_state(gks_trainer *t, gks_state *s, double tol, int64_t *n_added)
 {
-    if (!t || !s) return fail(GKS_EINVAL, "null argument");
-    if (s->mesh->device != t->device) return fail(GKS_EINVAL, "state and trainer live on different devices");
-    const int64_t T = s->md.T;
-    if (t->n + T > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
-    HIP_OK(hipStreamSynchronize(t->stream));
-    if (s->prec == GKS_FP64)
-        launch_features<double>(s, t->X + t->n * gks::MLP_IN);
-    else
-        launch_features<float>(s, t->X + t->n * gks::MLP_IN);
-    gks_status r = labels_any(s, tol);
-    if (r != GKS_OK) return r;
-    hipLaunchKernelGGL(gks::k_u8_to_f32, dim3(blocks(T, 256)), dim3(256), 0, s->stream, s->lab_y, T, t->Y + t->n);
-    HIP_OK(hipGetLastError());
-    std::vector<uint8_t> y((size_t)T);
-    HIP_OK(hipStreamSynchronize(s->stream));
-    HIP_OK(hipMemcpy(y.data(), s->lab_y, (size_t)T, hipMemcpyDeviceToHost));
-    int64_t pos = 0;
-    for (uint8_t v : y) pos += v;
-    t->n += T;
-    t->npos += pos;
-    if (n_added) *n_added = T;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t || !s) return fail(GKS_EINVAL, "null argument");
+        if (s->mesh->device != t->device) return fail(GKS_EINVAL, "state and trainer live on different devices");
+        const int64_t T = s->md.T;
+        if (t->n + T > t->cap) return fail(GKS_EINVAL, "trainer capacity exceeded");
+        HIP_OK(hipStreamSynchronize(t->stream));
+        if (s->prec == GKS_FP64)
+            launch_features<double>(s, t->X + t->n * gks::MLP_IN);
+        else
+            launch_features<float>(s, t->X + t->n * gks::MLP_IN);
+        gks_status r = labels_any(s, tol);
+        if (r != GKS_OK) return r;
+        hipLaunchKernelGGL(gks::k_u8_to_f32, dim3(blocks(T, 256)), dim3(256), 0, s->stream, s->lab_y, T, t->Y + t->n);
+        HIP_OK(hipGetLastError());
+        std::vector<uint8_t> y((size_t)T);
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(y.data(), s->lab_y, (size_t)T, hipMemcpyDeviceToHost));
+        int64_t pos = 0;
+        for (uint8_t v : y) pos += v;
+        t->n += T;
+        t->npos += pos;
+        if (n_added) *n_added = T;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_info(const gks_trainer *t, int64_t *n_samples, int64_t *n_positive)
 {
-    if (!t) return fail(GKS_EINVAL, "null trainer");
-    if (n_samples) *n_samples = t->n;
-    if (n_positive) *n_positive = t->npos;
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t) return fail(GKS_EINVAL, "null trainer");
+        if (n_samples) *n_samples = t->n;
+        if (n_positive) *n_positive = t->npos;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_grad(gks_trainer *t, const int32_t *idx, int32_t B, float *loss, float *grad)
 {
-    if (!t || !idx || B < 1 || B > t->maxB) return fail(GKS_EINVAL, "bad gradient arguments");
-    for (int32_t i = 0; i < B; i++)
-        if (idx[i] < 0 || idx[i] >= t->n) return fail(GKS_EINVAL, "sample index out of range");
-    HIP_OK(hipStreamSynchronize(t->stream));
-    HIP_OK(hipMemcpy(t->perm, idx, (size_t)B * 4, hipMemcpyHostToDevice));
-    train_grad(t, 0, B, t->loss);
-    HIP_OK(hipGetLastError());
-    HIP_OK(hipStreamSynchronize(t->stream));
-    if (loss) HIP_OK(hipMemcpy(loss, t->loss, 4, hipMemcpyDeviceToHost));
-    if (grad) HIP_OK(hipMemcpy(grad, t->g, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t || !idx || B < 1 || B > t->maxB) return fail(GKS_EINVAL, "bad gradient arguments");
+        for (int32_t i = 0; i < B; i++)
+            if (idx[i] < 0 || idx[i] >= t->n) return fail(GKS_EINVAL, "sample index out of range");
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(t->perm, idx, (size_t)B * 4, hipMemcpyHostToDevice));
+        train_grad(t, 0, B, t->loss);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(t->stream));
+        if (loss) HIP_OK(hipMemcpy(loss, t->loss, 4, hipMemcpyDeviceToHost));
+        if (grad) HIP_OK(hipMemcpy(grad, t->g, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_fit(gks_trainer *t, int32_t epochs, int32_t batch, float lr, uint64_t seed,
                            float *epoch_loss)
 {
-    if (!t || epochs < 0 || batch < 1 || batch > t->maxB || !(lr > 0) || !std::isfinite(lr))
-        return fail(GKS_EINVAL, "bad training arguments");
-    if (t->n == 0) return fail(GKS_EINVAL, "no samples");
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const int64_t n = t->n, nb = (n + batch - 1) / batch;
-    std::vector<int32_t> perm((size_t)n);
-    std::vector<float> bl((size_t)nb);
-    uint64_t state = seed;
-    for (int32_t ep = 0; ep < epochs; ep++) {
-        for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
-        for (int64_t i = n - 1; i > 0; i--) {
-            const int64_t j = (int64_t)(splitmix64(state) % (uint64_t)(i + 1));
-            std::swap(perm[i], perm[j]);
+    return guarded([&]() -> gks_status {
+        if (!t || epochs < 0 || batch < 1 || batch > t->maxB || !(lr > 0) || !std::isfinite(lr))
+            return fail(GKS_EINVAL, "bad training arguments");
+        if (t->n == 0) return fail(GKS_EINVAL, "no samples");
+        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+        const int64_t n = t->n, nb = (n + batch - 1) / batch;
+        std::vector<int32_t> perm((size_t)n);
+        std::vector<float> bl((size_t)nb);
+        uint64_t state = seed;
+        for (int32_t ep = 0; ep < epochs; ep++) {
+            for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
+            for (int64_t i = n - 1; i > 0; i--) {
+                const int64_t j = (int64_t)(splitmix64(state) % (uint64_t)(i + 1));
+                std::swap(perm[i], perm[j]);
+            }
+            HIP_OK(hipStreamSynchronize(t->stream));
+            HIP_OK(hipMemcpy(t->perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+            for (int64_t k = 0; k < nb; k++) {
+                const int64_t off = k * batch;
+                const int B = (int)std::min<int64_t>(batch, n - off);
+                train_grad(t, off, B, t->loss + k);
+                t->adam_t++;
+                const float c1 = 1.f - std::pow(b1, (float)t->adam_t), c2 = 1.f - std::pow(b2, (float)t->adam_t);
+                hipLaunchKernelGGL(gks::k_adam, dim3(blocks(gks::MLP_NP, 256)), dim3(256), 0, t->stream, t->P, t->g, t->mo,
+                                   t->ve, lr, b1, b2, eps, c1, c2);
+            }
+            HIP_OK(hipGetLastError());
+            if (epoch_loss) {
+                HIP_OK(hipStreamSynchronize(t->stream));
+                HIP_OK(hipMemcpy(bl.data(), t->loss, (size_t)nb * 4, hipMemcpyDeviceToHost));
+                double acc = 0;
+                for (float v : bl) acc += v;
+                epoch_loss[ep] = (float)(acc / (double)nb);
+            }
         }
         HIP_OK(hipStreamSynchronize(t->stream));
-        HIP_OK(hipMemcpy(t->perm, perm.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        for (int64_t k = 0; k < nb; k++) {
-            const int64_t off = k * batch;
-            const int B = (int)std::min<int64_t>(batch, n - off);
-            train_grad(t, off, B, t->loss + k);
-            t->adam_t++;
-            const float c1 = 1.f - std::pow(b1, (float)t->adam_t), c2 = 1.f - std::pow(b2, (float)t->adam_t);
-            hipLaunchKernelGGL(gks::k_adam, dim3(blocks(gks::MLP_NP, 256)), dim3(256), 0, t->stream, t->P, t->g, t->mo,
-                               t->ve, lr, b1, b2, eps, c1, c2);
-        }
-        HIP_OK(hipGetLastError());
-        if (epoch_loss) {
-            HIP_OK(hipStreamSynchronize(t->stream));
-            HIP_OK(hipMemcpy(bl.data(), t->loss, (size_t)nb * 4, hipMemcpyDeviceToHost));
-            double acc = 0;
-            for (float v : bl) acc += v;
-            epoch_loss[ep] = (float)(acc / (double)nb);
-        }
-    }
-    HIP_OK(hipStreamSynchronize(t->stream));
-    return GKS_OK;
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_params(const gks_trainer *t, float *params)
 {
-    if (!t || !params) return fail(GKS_EINVAL, "null argument");
-    HIP_OK(hipStreamSynchronize(t->stream));
-    HIP_OK(hipMemcpy(params, t->P, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t || !params) return fail(GKS_EINVAL, "null argument");
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(params, t->P, gks::MLP_NP * 4, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_logits(gks_trainer *t, float *logits)
 {
-    if (!t || !logits) return fail(GKS_EINVAL, "null argument");
-    gks_status r = trainer_logits(t);
-    if (r != GKS_OK) return r;
-    HIP_OK(hipStreamSynchronize(t->stream));
-    HIP_OK(hipMemcpy(logits, t->logit, (size_t)t->n * 4, hipMemcpyDeviceToHost));
-    return GKS_OK;
+    return guarded([&]() -> gks_status {
+        if (!t || !logits) return fail(GKS_EINVAL, "null argument");
+        gks_status r = trainer_logits(t);
+        if (r != GKS_OK) return r;
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(logits, t->logit, (size_t)t->n * 4, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    });
 }
 
 gks_status gks_trainer_threshold(gks_trainer *t, double max_false_skip, float *threshold)
 {
-    if (!t || !threshold || !(max_false_skip >= 0) || !(max_false_skip <= 1))
-        return fail(GKS_EINVAL, "bad threshold arguments");
-    if (t->n == 0) return fail(GKS_EINVAL, "no samples");
-    gks_status r = trainer_logits(t);
-    if (r != GKS_OK) return r;
-    const size_t n = (size_t)t->n;
-    std::vector<float> z(n), y(n);
-    HIP_OK(hipStreamSynchronize(t->stream));
-    HIP_OK(hipMemcpy(z.data(), t->logit, n * 4, hipMemcpyDeviceToHost));
-    HIP_OK(hipMemcpy(y.data(), t->Y, n * 4, hipMemcpyDeviceToHost));
-    std::vector<float> neg;
-    for (size_t i = 0; i < n; i++)
-        if (y[i] < 0.5f) neg.push_back(z[i]);
-    const size_t allowed = (size_t)std::floor(max_false_skip * (double)n);
-    if (allowed >= neg.size()) {
-        *threshold = -FLT_MAX;
+    return guarded([&]() -> gks_status {
+        if (!t || !threshold || !(max_false_skip >= 0) || !(max_false_skip <= 1))
+            return fail(GKS_EINVAL, "bad threshold arguments");
+        if (t->n == 0) return fail(GKS_EINVAL, "no samples");
+        gks_status r = trainer_logits(t);
+        if (r != GKS_OK) return r;
+        const size_t n = (size_t)t->n;
+        std::vector<float> z(n), y(n);
+        HIP_OK(hipStreamSynchronize(t->stream));
+        HIP_OK(hipMemcpy(z.data(), t->logit, n * 4, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(y.data(), t->Y, n * 4, hipMemcpyDeviceToHost));
+        std::vector<float> neg;
+        for (size_t i = 0; i < n; i++)
+            if (y[i] < 0.5f) neg.push_back(z[i]);
+        const size_t allowed = (size_t)std::floor(max_false_skip * (double)n);
+        if (allowed >= neg.size()) {
+            *threshold = -FLT_MAX;
+            return GKS_OK;
+        }
+        // skip iff z > threshold: at most `allowed` label-0 logits may lie above it
+        std::sort(neg.begin(), neg.end(), [](float a, float b) { return a > b; });
+        *threshold = neg[allowed];
         return GKS_OK;
-    }
-    // skip iff z > threshold: at most `allowed` label-0 logits may lie above it
-    std::sort(neg.begin(), neg.end(), [](float a, float b) { return a > b; });
-    *threshold = neg[allowed];
-    return GKS_OK;
+    });
 }
 
 }  // extern "C"
@@ -1219,72 +1297,74 @@ gks_status gks_trainer_threshold(gks_trainer *t, double max_false_skip, float *t
 
 extern "C" gks_status gks_autotune(gks_state *s, int32_t reps, int32_t *chosen)
 {
-    if (!s || reps < 1) return fail(GKS_EINVAL, "bad autotune arguments");
-    if (s->half) return fail(GKS_EINVAL, "autotune cannot start between stage 0 and stage 1");
-    const gks::HostMesh &h = s->mesh->host;
-    const int64_t TG = h.nt + h.ng;
-    const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
-    const size_t nb[4] = {2 * (size_t)TG * 8, 4 * (size_t)TG * rs, 12 * (size_t)TG * rs, 2 * (size_t)h.S * 8};
-    void *src[4] = {s->Wh[0], s->Wm[0], s->gW[0], s->scal};
-    void *save[4] = {nullptr, nullptr, nullptr, nullptr};
-    gks_status r = GKS_OK;
-    HIP_OK(hipStreamSynchronize(s->stream));
-    for (int i = 0; i < 4 && r == GKS_OK; i++)
-        if (hipMalloc(&save[i], nb[i]) != hipSuccess) r = fail(GKS_ENOMEM, "autotune state copy");
-    auto copy = [&](bool restore) {
-        for (int i = 0; i < 4; i++)
-            (void)hipMemcpyAsync(restore ? src[i] : save[i], restore ? save[i] : src[i], nb[i], hipMemcpyDeviceToDevice,
-                                 s->stream);
-    };
-    const bool prof_was = s->prof_on;
-    if (r == GKS_OK) {
-        copy(false);
-        drop_graph(s);
-        const int tuned[5] = {GKS_KERNEL_GHOST, GKS_KERNEL_HHAT, GKS_KERNEL_PLANE, GKS_KERNEL_FLUX, GKS_KERNEL_UPDATE};
-        const int cand[3] = {64, 128, 256};
-        for (int k : tuned) {
-            if (k == GKS_KERNEL_GHOST && h.ng == 0) continue;
-            double best = 1e300;
-            int pick = s->bs[k];
-            for (int b : cand) {
-                s->bs[k] = b;
-                copy(true);
-                s->prof.clear();
-                s->ev_used = 0;
-                s->prof_on = true;
-                for (int i = 0; i < reps; i++) {
-                    dt_any(s, s->stream);
-                    stage_any(s, 0, s->stream);
-                    stage_any(s, 1, s->stream);
-                }
-                if (hipStreamSynchronize(s->stream) != hipSuccess) {
-                    r = fail(GKS_EDEVICE, "autotune run failed");
-                    break;
-                }
-                double tot = 0;
-                for (const auto &rec : s->prof)
-                    if (rec.kernel == k) {
-                        float ms = 0;
-                        (void)hipEventElapsedTime(&ms, rec.a, rec.b);
-                        tot += ms;
+    return guarded([&]() -> gks_status {
+        if (!s || reps < 1) return fail(GKS_EINVAL, "bad autotune arguments");
+        if (s->half) return fail(GKS_EINVAL, "autotune cannot start between stage 0 and stage 1");
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t TG = h.nt + h.ng;
+        const size_t rs = s->prec == GKS_FP64 ? 8 : 4;
+        const size_t nb[4] = {2 * (size_t)TG * 8, 4 * (size_t)TG * rs, 12 * (size_t)TG * rs, 2 * (size_t)h.S * 8};
+        void *src[4] = {s->Wh[0], s->Wm[0], s->gW[0], s->scal};
+        void *save[4] = {nullptr, nullptr, nullptr, nullptr};
+        gks_status r = GKS_OK;
+        HIP_OK(hipStreamSynchronize(s->stream));
+        for (int i = 0; i < 4 && r == GKS_OK; i++)
+            if (hipMalloc(&save[i], nb[i]) != hipSuccess) r = fail(GKS_ENOMEM, "autotune state copy");
+        auto copy = [&](bool restore) {
+            for (int i = 0; i < 4; i++)
+                (void)hipMemcpyAsync(restore ? src[i] : save[i], restore ? save[i] : src[i], nb[i], hipMemcpyDeviceToDevice,
+                                     s->stream);
+        };
+        const bool prof_was = s->prof_on;
+        if (r == GKS_OK) {
+            copy(false);
+            drop_graph(s);
+            const int tuned[5] = {GKS_KERNEL_GHOST, GKS_KERNEL_HHAT, GKS_KERNEL_PLANE, GKS_KERNEL_FLUX, GKS_KERNEL_UPDATE};
+            const int cand[3] = {64, 128, 256};
+            for (int k : tuned) {
+                if (k == GKS_KERNEL_GHOST && h.ng == 0) continue;
+                double best = 1e300;
+                int pick = s->bs[k];
+                for (int b : cand) {
+                    s->bs[k] = b;
+                    copy(true);
+                    s->prof.clear();
+                    s->ev_used = 0;
+                    s->prof_on = true;
+                    for (int i = 0; i < reps; i++) {
+                        dt_any(s, s->stream);
+                        stage_any(s, 0, s->stream);
+                        stage_any(s, 1, s->stream);
                     }
-                if (tot < best) {
-                    best = tot;
-                    pick = b;
+                    if (hipStreamSynchronize(s->stream) != hipSuccess) {
+                        r = fail(GKS_EDEVICE, "autotune run failed");
+                        break;
+                    }
+                    double tot = 0;
+                    for (const auto &rec : s->prof)
+                        if (rec.kernel == k) {
+                            float ms = 0;
+                            (void)hipEventElapsedTime(&ms, rec.a, rec.b);
+                            tot += ms;
+                        }
+                    if (tot < best) {
+                        best = tot;
+                        pick = b;
+                    }
                 }
+                s->bs[k] = pick;
+                if (r != GKS_OK) break;
             }
-            s->bs[k] = pick;
-            if (r != GKS_OK) break;
+            copy(true);
+            (void)hipStreamSynchronize(s->stream);
         }
-        copy(true);
-        (void)hipStreamSynchronize(s->stream);
-    }
-    s->prof.clear();
-    s->ev_used = 0;
-    s->prof_on = prof_was;
-    for (void *p : save)
-        if (p) (void)hipFree(p);
-    if (r == GKS_OK && chosen)
-        for (int k = 0; k < GKS_KERNEL_COUNT; k++) chosen[k] = s->bs[k];
-    return r;
+        s->prof.clear();
+        s->ev_used = 0;
+        s->prof_on = prof_was;
+        for (void *p : save)
+            if (p) (void)hipFree(p);
+        if (r == GKS_OK && chosen)
+            for (int k = 0; k < GKS_KERNEL_COUNT; k++) chosen[k] = s->bs[k];
+        return r;
+    });
 }

@@ -72,6 +72,12 @@ __device__ inline int64_t xcd_block()
 // the four momentum components in paper order 1, 2, 4, 5 -> slots 0..3 of Wm
 __device__ inline int mom_slot(int v) { return v < 3 ? v - 1 : v - 2; }
 
+// a / b in the bulk precision: in FP32 the product with the hardware reciprocal (one instruction,
+// within about an ulp, where the correctly rounded quotient costs about ten; FP32 results are
+// held to FP32 tolerances), in FP64 the correctly rounded quotient
+__device__ inline float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double div_(double a, double b) { return a / b; }
+
 // Gauss-point records of one cell at one of its six Gauss points (slot = 2 * local edge + point),
 // written by the reconstruction and read by the edge kernels.  Records are stored cell-major,
 // index 6 c + slot, in two arrays: the head (thicknesses and momenta, all that the force model's
@@ -306,11 +312,11 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         // linear weights)
         const R S2 = thick ? R(1e-20) : (R)(1e-10 * p.G * q.hl * q.hl * q.hl);
         const R epsw = R(1e-10) * fmax(Q0 * Q0, S2);
-        const R t0 = d0 * (1 + tz / (beta0 + epsw));
+        const R t0 = d0 * (1 + div_(tz, beta0 + epsw));
         R sum = t0, tm[4];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            tm[s] = dm * (1 + tz / (bm[s] + epsw));
+            tm[s] = dm * (1 + div_(tz, bm[s] + epsw));
             sum += tm[s];
         }
         // where every unnormalised weight equals its linear weight (tau = 0, or tau / (beta + eps)
@@ -319,7 +325,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         bool lin = t0 == d0;
 #pragma unroll
         for (int s = 0; s < 4; s++) lin = lin && tm[s] == dm;
-        const R isum = lin ? R(1) : R(1) / sum;
+        const R isum = lin ? R(1) : div_(R(1), sum);
         w0 = t0 * isum;
 #pragma unroll
         for (int s = 0; s < 4; s++) wm[s] = tm[s] * isum;
@@ -335,7 +341,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         sbx += cm * bx[s];
         sby += cm * by[s];
     }
-    const R ihs = R(1) / hs;
+    const R ihs = div_(R(1), hs);
     const R gs[2] = {R(0.5 - 0.28867513459481288225), R(0.5 + 0.28867513459481288225)};
     // positivity safeguard (not in the paper): where a layer thickness at a Gauss point would fall
     // below a tenth of the cell's average, the deviation from the average is scaled down
@@ -364,7 +370,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
             out.gy[slot] = (ratio * Py + sby) * ihs;
             if (thick && dev < 0) {
                 const R bdev = hs * (gBx * x + gBy * y);
-                theta = fmin(theta, fmax(R(0), (hbar - bdev - floor_h) / -dev));
+                theta = fmin(theta, fmax(R(0), div_(hbar - bdev - floor_h, -dev)));
             }
         }
     if (theta < R(1)) {
@@ -651,6 +657,7 @@ __global__ void k_plane(MeshDev m, const uint8_t *__restrict__ need, const doubl
 template <typename R>
 struct SideL {
     R h, U, V;                    // state
+    R ih;                         // 1/h
     R hn, ht, mnn, mnt, mtn, mtt;  // d/dn, d/dt of h, h U_n, h U_t
     R en, et;                     // d/dn, d/dt of the level whose |c|^2 slope enters P (h, or eta1)
     R pn, pt;                     // acceleration (without the bottom part for the lower layer)
@@ -758,7 +765,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 {
     const bool bottom = (gBn != R(0)) || (gBt != R(0));
     // reciprocals formed once (lam = 1/(G h)); 1/(2 sqrt(pi lam)) = sqrt(lam) th / sqrt(pi)
-    const R iG = R(1) / G, ihL = R(1) / sl.h, ihR = R(1) / sr.h;
+    const R iG = div_(R(1), G), ihL = sl.ih, ihR = sr.ih;
     const R lamL = iG * ihL, lamR = iG * ihR;
     const R thL = R(0.5) * G * sl.h, thR = R(0.5) * G * sr.h;
     const R ispi = R(0.56418958354775628695);  // 1/sqrt(pi)
@@ -808,7 +815,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 #pragma unroll
         for (int i = 0; i < 3; i++) B5[i] = t1[i] + t2[i];
     }
-    const R ihb = R(1) / hb;
+    const R ihb = div_(R(1), hb);
     const R Ub = wb1 * ihb, Vb = wb2 * ihb;
     const R lamb = iG * ihb, thb = R(0.5) * G * hb;
     R Mp[6], Mm[6];
@@ -858,8 +865,8 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     // its time derivative; c01 + c04 = 1 and ct1 + ct4 = 0 exactly (the hydrostatic part of B1 and B4
     // carries weight 1 in F0 and 0 in Ft)
     const R pl = sl.h * sl.h, pr = sr.h * sr.h;
-    const R r = eps + eps_num * fabs((pl - pr) / (pl + pr));
-    const R E2 = exp_(R(-0.5) / r), E1 = E2 * E2, a1 = 1 - E1, a2 = 1 - E2;
+    const R r = eps + eps_num * fabs(div_(pl - pr, pl + pr));
+    const R E2 = exp_(div_(R(-0.5), r)), E1 = E2 * E2, a1 = 1 - E1, a2 = 1 - E2;
     const R c04 = r * (4 * a2 - a1), c01 = 1 - c04;
     const R ct1 = 4 * r * (2 * a2 - a1), ct4 = -ct1;
     const R c02 = -r + r * r * (8 * a2 - 2 * a1) - 2 * r * E2 + r * E1;
@@ -867,7 +874,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     const R c03 = -r + r * r * (4 * a2 - a1), ct3 = 4 * (R(0.25) + r * r * (a1 - 2 * a2));
     const R c05 = r * (2 + 4 * r) * E2 - r * (1 + r) * E1 - 3 * r * r;
     const R ct5 = 4 * (r * (1 + r) * E1 - r * (1 + 2 * r) * E2 + r * r);
-    const R idt = R(1) / dt;
+    const R idt = div_(R(1), dt);
 #pragma unroll
     for (int i = 0; i < 3; i++) {
         F0[i] = c01 * B1[i] + c04 * B4[i] + dt * (c02 * B2[i] + c03 * B3[i] + c05 * B5[i]);
@@ -951,10 +958,11 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
             ay = -G * dfy;
         }
         SideL<R> &q = side[s];
-        const R h = (R)hh;
+        const R h = (R)hh, ih = div_(R(1), h);
         q.h = h;
-        q.U = (mx * nx + my * ny) / h;
-        q.V = (mx * tx + my * ty) / h;
+        q.ih = ih;
+        q.U = (mx * nx + my * ny) * ih;
+        q.V = (mx * tx + my * ty) * ih;
         q.hn = hx * nx + hy * ny;
         q.ht = hx * tx + hy * ty;
         q.en = ex * nx + ey * ny;

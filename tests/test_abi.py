@@ -41,3 +41,18 @@ def test_last_error_is_callable_without_gpu():
     lib = ctypes.CDLL(LIB)
     lib.gks_last_error.restype = ctypes.c_char_p
     assert isinstance(lib.gks_last_error(), bytes)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_null_handles_are_rejected_on_the_host():
+    """Argument checks run before any device call: null handles give GKS_EINVAL and a message."""
+    lib = ctypes.CDLL(LIB)
+    lib.gks_last_error.restype = ctypes.c_char_p
+    vp = ctypes.c_void_p
+    i64 = ctypes.c_int64()
+    assert lib.gks_mesh_info(vp(), ctypes.byref(i64), None, None, None) == 1
+    assert b"null" in lib.gks_last_error()
+    assert lib.gks_state_read(vp(), None, None, None) == 1
+    assert lib.gks_stage(vp(), 0, None) == 1
+    assert lib.gks_mesh_scenario(vp(), 0, None, None) == 1
+    assert lib.gks_trainer_info(vp(), None, None) == 1

@@ -66,6 +66,9 @@ def load():
     lib.om_s2o4_stage.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp]
     lib.om_s2o4_final.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
     lib.om_cell_geometry.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+    lib.om_edge_height.restype = ctypes.c_double
+    lib.om_edge_height.argtypes = [ctypes.c_double] * 7
+    lib.om_plane_gradient.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
     lib.om_features.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp, _dp, _dp]
     lib.om_mlp_forward.argtypes = [_dp, _dp, ctypes.c_int, _dp]
     lib.om_mlp_grad.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
@@ -160,6 +163,13 @@ class Mesh:
         load().om_lsq_matrix(self._h, c, _d(M))
         return M
 
+    def plane_gradient(self, c, hk):
+        """Gradient of the plane through the values hk[3] at the centres of cell c's local edges
+        (edge k joins vertices k and k + 1 of tri[c])."""
+        out = np.zeros(2)
+        load().om_plane_gradient(self._h, int(c), _d(_f64(hk)), _d(out))
+        return out
+
     def reconstruct(self, c, W, gW, linear=False, G=9.81):
         W, gW = _f64(W), _f64(gW)
         val = np.zeros((6, 6))
@@ -241,6 +251,12 @@ def time_integrals(delta, tau):
     out = np.zeros(5)
     load().om_time_integrals(float(delta), float(tau), _d(out))
     return out
+
+
+def edge_height(zl, zr, hl, hr, unl, unr, G):
+    """Interface height of the force model (Sec. 2.3): xi zl + (1 - xi) zr, xi the kinetic fraction
+    of the interface Maxwellian moving from the left side to the right."""
+    return load().om_edge_height(*(float(x) for x in (zl, zr, hl, hr, unl, unr, G)))
 
 
 def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0):

@@ -547,6 +547,33 @@ void om_mesh_free(om_mesh *m)
 
 int om_mesh_n_edges(const om_mesh *m) { return m->ne; }
 
+/* Interface height of the force model (Sec. 2.3): the convex combination of the two sides' heights
+ * whose weight xi is, in this reading, the fraction of the particles of the interface Maxwellian
+ * (mean normal velocity (unl + unr) / 2, lambda = 2 / (G (hl + hr))) that move from the left
+ * side to the right one, 1/2 erfc(-sqrt(lambda) (unl + unr) / 2). */
+double om_edge_height(double zl, double zr, double hl, double hr, double unl, double unr, double G)
+{
+    double lamb = 2 / (G * (hl + hr));
+    double xi = 0.5 * erfc(-sqrt(lamb) * 0.5 * (unl + unr));
+    return xi * zl + (1 - xi) * zr;
+}
+
+/* Gradient of the plane through the values hk[k] at the centres of cell c's local edges k (edge k
+ * joins vertices k and k + 1): the cell average of the gradient by Gauss's theorem, exact for a
+ * plane (Sec. 2.3 extended to two dimensions). */
+void om_plane_gradient(const om_mesh *m, int c, const double *hk, double *out)
+{
+    double s[2] = {0, 0};
+    for (int k = 0; k < 3; k++) {
+        int e = m->c_edge[3 * c + k];
+        double sg = m->c_side[3 * c + k] == 0 ? 1.0 : -1.0;
+        s[0] += sg * m->e_len[e] * m->e_n[2 * e] * hk[k];
+        s[1] += sg * m->e_len[e] * m->e_n[2 * e + 1] * hk[k];
+    }
+    out[0] = s[0] / m->area[c];
+    out[1] = s[1] / m->area[c];
+}
+
 void om_cell_geometry(const om_mesh *m, double *area, double *cx, double *cy)
 {
     for (int c = 0; c < m->nt; c++) {
@@ -1048,10 +1075,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
                 double hl = f == 0 ? vl[3] - Bg : vl[0], hr = f == 0 ? vr[3] - Bg : vr[0];
                 double unl = (vl[o + 1] * n[0] + vl[o + 2] * n[1]) / hl;
                 double unr = (vr[o + 1] * n[0] + vr[o + 2] * n[1]) / hr;
-                double lamb = 2 / (G * (hl + hr));
-                /* reading: kinetic upwind fraction of the convex combination */
-                double xi = 0.5 * erfc(-sqrt(lamb) * 0.5 * (unl + unr));
-                acc[f] += 0.5 * (xi * vl[o] + (1 - xi) * vr[o]);
+                acc[f] += 0.5 * om_edge_height(vl[o], vr[o], hl, hr, unl, unr, G);
             }
         }
         hmid[2 * e] = acc[0];
@@ -1060,16 +1084,11 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     /* gradient of the plane through the three edge-centre values of each cell */
     double *gP1 = (double *)malloc(sizeof(double) * (size_t)T * 4);
     for (int c = 0; c < T; c++) {
-        double s[4] = {0, 0, 0, 0};
-        for (int k = 0; k < 3; k++) {
-            int e = m->c_edge[3 * c + k];
-            double sg = m->c_side[3 * c + k] == 0 ? 1.0 : -1.0;
-            for (int f = 0; f < 2; f++) {
-                s[2 * f] += sg * m->e_len[e] * m->e_n[2 * e] * hmid[2 * e + f];
-                s[2 * f + 1] += sg * m->e_len[e] * m->e_n[2 * e + 1] * hmid[2 * e + f];
-            }
+        for (int f = 0; f < 2; f++) {
+            double hk[3];
+            for (int k = 0; k < 3; k++) hk[k] = hmid[2 * m->c_edge[3 * c + k] + f];
+            om_plane_gradient(m, c, hk, gP1 + 4 * c + 2 * f);
         }
-        for (int i = 0; i < 4; i++) gP1[4 * c + i] = s[i] / m->area[c];
     }
 
     /* 3. gas-kinetic evolution at every Gauss point of every edge, both layers */

@@ -49,6 +49,14 @@ om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, cons
 void om_mesh_free(om_mesh *m);
 int om_mesh_n_edges(const om_mesh *m);
 
+/* Force model pieces (Sec. 2.3).  om_edge_height: interface height xi zl + (1 - xi) zr of the two
+ * sides' heights zl, zr, with xi = 1/2 erfc(-sqrt(lambda) (unl + unr) / 2), lambda = 2 / (G (hl + hr))
+ * from the layer thicknesses hl, hr and normal velocities unl, unr (normal from left to right).
+ * om_plane_gradient: gradient out[2] of the plane through the values hk[3] at the centres of cell c's
+ * local edges (edge k joins vertices k and k + 1 of the triangle as given to om_mesh_new). */
+double om_edge_height(double zl, double zr, double hl, double hr, double unl, double unr, double G);
+void om_plane_gradient(const om_mesh *m, int c, const double *hk, double *out);
+
 /* Stencil of cell c: 10 (cell, map) images; cells[10], maps[10][6] = (R00 R01 R10 R11 t0 t1). */
 void om_stencil(const om_mesh *m, int c, int *cells, double *maps);
 /* Least-squares solution matrix of cell c, [9][17] row-major (Sec. 3.4, Eq. Recons-system). */

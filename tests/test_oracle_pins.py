@@ -294,6 +294,132 @@ def test_smoothness_floor_carries_the_variable_scale():
 
 
 # ------------------------------------------------------------------------------------------
+# force model of the layer coupling (Sec. 2.3): interface heights, plane gradient, weight
+
+@pytest.mark.parametrize("hl,hr,unl,unr", [(1.0, 1.0, 0.3, 0.1), (0.4, 1.6, -0.8, 0.2),
+                                           (2.0, 0.5, 1.5, 2.5), (0.1, 0.3, 0.0, 0.0)])
+def test_edge_height_weight_is_the_kinetic_upwind_fraction(hl, hr, unl, unr):
+    """Reading of the interface height: the left height's weight is the share of the interface
+    Maxwellian (mean normal velocity (unl + unr) / 2, lambda = 2 / (G (hl + hr))) with positive
+    normal velocity, integrated here by adaptive quadrature of the Gaussian."""
+    lam, U = 2.0 / (G * (hl + hr)), 0.5 * (unl + unr)
+    gauss = lambda u: math.exp(-lam * (u - U) ** 2)
+    right = integrate.quad(gauss, 0.0, np.inf, epsabs=0, epsrel=1e-13)[0]
+    left = integrate.quad(gauss, -np.inf, 0.0, epsabs=0, epsrel=1e-13)[0]
+    xi = right / (right + left)
+    assert abs(o.edge_height(1.0, 0.0, hl, hr, unl, unr, G) - xi) < 1e-12
+    zl, zr = 0.7, 1.9
+    assert abs(o.edge_height(zl, zr, hl, hr, unl, unr, G) - (xi * zl + (1 - xi) * zr)) < 1e-12
+
+
+def test_edge_height_does_not_depend_on_the_edge_orientation():
+    """Exchanging the sides and reversing the normal (velocities change sign) gives the same
+    height; with both sides at rest it is the mean of the two heights."""
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        zl, zr, hl, hr = rng.uniform(0.2, 2.0, 4)
+        unl, unr = rng.uniform(-2.0, 2.0, 2)
+        a = o.edge_height(zl, zr, hl, hr, unl, unr, G)
+        b = o.edge_height(zr, zl, hr, hl, -unr, -unl, G)
+        assert abs(a - b) < 1e-14 * max(zl, zr)
+        assert o.edge_height(zl, zr, hl, hr, 0.0, 0.0, G) == 0.5 * zl + 0.5 * zr
+
+
+def test_plane_gradient_is_exact_for_planes():
+    """The gradient of the plane through the three edge-centre heights is the plane's own gradient
+    for linear data on an irregular mesh (Gauss's theorem with exact edge values)."""
+    sc = w.lake_at_rest(8, seed=4, bump_amp=0.0)
+    mesh = o.Mesh.from_scenario(sc)
+    rng = np.random.default_rng(5)
+    for c in range(0, sc.n_tri, 7):
+        a, bx, by = rng.uniform(-2, 2, 3)
+        v = sc.node_xy[sc.tri[c]]
+        mid = 0.5 * (v + np.roll(v, -1, axis=0))  # centre of local edge k = vertices k, k + 1
+        g = mesh.plane_gradient(c, a + bx * mid[:, 0] + by * mid[:, 1])
+        assert abs(g[0] - bx) < 1e-11 and abs(g[1] - by) < 1e-11, (c, g, bx, by)
+    # a permuted assignment of the edge values is not a plane through them
+    c = 3
+    v = sc.node_xy[sc.tri[c]]
+    mid = 0.5 * (v + np.roll(v, -1, axis=0))
+    g = mesh.plane_gradient(c, np.roll(mid[:, 0], 1))
+    assert abs(g[0] - 1.0) > 1e-3
+
+
+def _avg_over_triangles(f, tri_xy, N=8):
+    """Cell averages by the centroid rule on N^2 congruent sub-triangles (second order in 1/N)."""
+    a, b, c = tri_xy[:, 0], tri_xy[:, 1], tri_xy[:, 2]
+    s, k = 0.0, 0
+    for i in range(N):
+        for j in range(N - i):
+            for (di, dj) in ((1 / 3, 1 / 3), (2 / 3, 2 / 3)) if i + j < N - 1 else ((1 / 3, 1 / 3),):
+                p = a + (b - a) * (i + di) / N + (c - a) * (j + dj) / N
+                s = s + f(p[:, 0], p[:, 1])
+                k += 1
+    return s / k
+
+
+def test_high_order_weight_ratio_separates_smooth_data_from_jumps():
+    """The force model blends the reconstruction's derivative with the plane's by
+    w = min(1, omega_0 / d_0) over the two sides, which should tend to 1 where the flow is smooth
+    and to 0 at a discontinuity (Sec. 2.3).  Smooth data: the median of omega_0 / d_0 over the
+    interior approaches 1 under refinement; a step: it is below 1e-6 next to the step and 1 (to
+    rounding) far from it."""
+    k = 2 * np.pi
+    f = lambda x, y: 1.0 + 0.2 * np.sin(k * x) * np.cos(k * y)
+    fx = lambda x, y: 0.2 * k * np.cos(k * x) * np.cos(k * y)
+    fy = lambda x, y: -0.2 * k * np.sin(k * x) * np.sin(k * y)
+    dev = []
+    for n in (8, 16, 32):
+        sc = w.lake_at_rest(n, seed=5, bump_amp=0.0)
+        xy = sc.node_xy[sc.tri]
+        W, gW = sc.W0.copy(), sc.gradW0.copy()
+        W[0], gW[0, 0], gW[0, 1] = (_avg_over_triangles(fn, xy) for fn in (f, fx, fy))
+        mesh = o.Mesh.from_scenario(sc)
+        inner = [c for c in range(sc.n_tri) if np.all(xy[c] > 0.25) and np.all(xy[c] < 0.75)]
+        r = [mesh.reconstruct(c, W, gW, linear=False, G=sc.G)[2][0] for c in inner]
+        dev.append(abs(1.0 - float(np.median(r))))
+    assert dev[0] > 4 * dev[1] > 16 * dev[2], dev
+    assert dev[2] < 2e-3, dev
+    sc = w.lake_at_rest(16, seed=9, bump_amp=0.0)
+    cen = sc.node_xy[sc.tri].mean(axis=1)
+    d = cen[:, 0] + 0.3 * cen[:, 1] - 0.62
+    W = np.zeros((6, sc.n_tri))
+    W[0] = np.where(d < 0, 1.0, 0.5)
+    W[3] = 1.0
+    gW = np.zeros((6, 2, sc.n_tri))
+    mesh = o.Mesh.from_scenario(sc)
+    r = np.array([mesh.reconstruct(c, W, gW, linear=False)[2][0] for c in range(sc.n_tri)])
+    assert r[np.abs(d) < 0.05].max() < 1e-6
+    assert np.abs(r[np.abs(d) > 0.3] - 1.0).max() < 1e-12
+
+
+def test_time_step_rule_on_a_regular_lattice():
+    """CFL rule of Sec. 4, dt = CFL dX / U_max with U_max the largest |U| + sqrt(G h) of the two
+    layers, read with dX = 2 |Omega| / (longest edge).  On the split rectangles of a regular
+    lattice every triangle is right-angled with legs hx, hy, so dX = hx hy / sqrt(hx^2 + hy^2)."""
+    from workloads.meshes import jittered_rect
+
+    nx, ny, lx, ly = 6, 4, 1.5, 0.8
+    xy, tri = jittered_rect(nx, ny, lx, ly, seed=0, jitter=0.0)
+    mesh = o.Mesh(xy, tri)
+    T = tri.shape[0]
+    hx, hy = lx / nx, ly / ny
+    dX = hx * hy / math.hypot(hx, hy)
+    h2, h1 = 0.3, 1.2
+    u2, v2, u1, v1 = 1.5, 0.3, 0.5, -0.2
+    W = np.zeros((6, T))
+    W[0], W[1], W[2] = h2, h2 * u2, h2 * v2
+    W[3], W[4], W[5] = h1, h1 * u1, h1 * v1
+    umax = max(math.hypot(u2, v2) + math.sqrt(G * h2), math.hypot(u1, v1) + math.sqrt(G * h1))
+    p = o.params(G=G, cfl=0.5)
+    assert abs(o.dt(mesh, p, W) - 0.5 * dX / umax) < 1e-14
+    # one faster cell sets the step
+    W[1, 7] = h2 * 9.0
+    umax = max(umax, math.hypot(9.0, v2) + math.sqrt(G * h2))
+    assert abs(o.dt(mesh, p, W) - 0.5 * dX / umax) < 1e-14
+
+
+# ------------------------------------------------------------------------------------------
 # whole scheme: well-balance, conservation, invariances, accuracy
 
 def _advance(sc, steps, mesh=None):
@@ -321,7 +447,14 @@ def test_lake_at_rest_is_preserved_to_roundoff():
                                   lambda: w.dam_break(8, left=(1.0, 0.5), right=(0.6, 0.9)),
                                   lambda: w.smooth_periodic(8)])
 def test_layer_mass_is_conserved(make):
+    """Per-layer mass (the sum of area times thickness) is conserved to round-off over 8 steps;
+    the mass measure itself is pinned by the domain area: a uniform layer of thickness h over the
+    unit square (or the periodic cell) has mass h times its area."""
     sc = make()
+    dom = float(np.ptp(sc.node_xy[:, 0]) * np.ptp(sc.node_xy[:, 1]))
+    uni = np.zeros_like(sc.W0)
+    uni[0], uni[3] = 0.25, 1.5
+    assert np.allclose(o.mass(o.Mesh.from_scenario(sc), uni), [0.25 * dom, 1.5 * dom], rtol=1e-13, atol=0)
     mesh = o.Mesh.from_scenario(sc)
     m0 = o.mass(mesh, sc.W0)
     _, W, _ = _advance(sc, 8, mesh)

@@ -11,6 +11,7 @@ from .scenarios import (  # noqa: F401
     smooth_periodic,
     accuracy_e1,
     lake_at_rest,
+    well_balance_bump,
     dam_break,
     ensemble,
     riemann_exchange,

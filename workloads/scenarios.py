@@ -177,6 +177,17 @@ def lake_at_rest(n: int, seed: int = 20230604, chi: float = 0.98, eta1: float = 
                         perturb, disk)
 
 
+def well_balance_bump(n: int = 40, seed: int = 20230613, chi: float = 1.0, cfl: float = 0.5,
+                      t_end: float = 100.0, G: float = 9.81) -> Scenario:
+    """The well-balance test of Sec. 4: [0, 2]^2 with walls, jittered Delaunay mesh of cell size
+    2/n (n = 40: 0.05), bottom B = 0.5 exp(-50 |x - (1, 1)|^2), h1 = 0.8 - B, h2 = 0.2, at rest,
+    density ratio 1, CFL 0.5, run to t = 100."""
+    xy, tri = jittered_rect(n, n, 2.0, 2.0, seed)
+    node_B = _bump(xy, amp=0.5, cx=1.0, cy=1.0)
+    return _level_state(f"well_balance_bump_n{n}", xy, tri, node_B, chi, cfl, t_end, G,
+                        lambda cx, cy: (np.full_like(cx, 0.8), np.full_like(cx, 0.2)), 0.0, None)
+
+
 def dam_break(n: int, seed: int = 20230605, chi: float = 0.95, x_dam: float = 0.5,
               left=(1.0, 0.5), right=(0.5, 1.0), sin_amp: float = 0.1, bump_amp: float = 0.0,
               cfl: float = 0.3, t_end: float = 1e9, G: float = 9.81) -> Scenario:

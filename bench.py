@@ -44,12 +44,13 @@ def algorithmic_bytes(T, E, NG, prec):
         # writes Gauss-point records (12 FP64 thicknesses, 96 values/gradients) and 2 weights
         "recon": T * (2 * d + 4 * r + 12 * r + 153 * r + 13 * r + 4 * 9 + 12 * d + 96 * r + 2 * r),
         # every record once, weights and plane gradients once per cell; edge tables; outputs
-        "flux": T * (12 * d + 96 * r + 2 * r + 4 * d) + E * (4 * 3 + 2 * r + 2 * d + 2 * r + 4 * d + 22 * r),
+        "flux": T * (12 * d + 96 * r + 2 * r + 4 * d) + E * (4 * 3 + 2 * r + 2 * d + 2 * r + 6 * d + 24 * r),
         "hhat": T * (12 * d + 24 * r) + E * (4 * 3 + 2 * r + 2 * d + 2 * d),
         "plane": T * (4 * 3 + 6 * d + 4 * d) + E * 2 * d,
-        # geometry, edge outputs once (the second stage reads only the interface thicknesses, the
-        # thickness fluxes and the time derivatives), state / carry (average of the two stages)
-        "update": T * (4 * 3 + 12 * d) + E * ((4 * d + 22 * r) + (2 * d + 14 * r)) // 2
+        # geometry, edge outputs once (the second stage reads only the interface and central
+        # thicknesses, the thickness fluxes and the time derivatives), state / carry (average of
+        # the two stages)
+        "update": T * (4 * 3 + 12 * d) + E * ((6 * d + 24 * r) + (4 * d + 16 * r)) // 2
                   + T * ((2 * d + 4 * r) * 2 + 12 * r + 6 * d + 12 * r + (6 * d + 12 * r)) // 2,
         "ghost": NG * (2 * 2 * d + 2 * 16 * r + 4 * d + 4),
         "dt": T * (2 * d + 4 * r + d),

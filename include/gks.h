@@ -137,10 +137,12 @@ typedef enum {
     GKS_BUF_RECM = 1,  /* real [6 slots][16][n_tri]: the four momenta, then the x/y gradients of
                           the six variables (h2, h2U2, h2V2, h1 + B, h1U1, h1V1) at the Gauss points */
     GKS_BUF_R0 = 2,    /* real [2][n_tri]: omega_0 / d_0 of h1 + B and of h2 */
-    GKS_BUF_EOH = 3,   /* double [4][n_edges]: 1/2 G hb^2 (upper, lower), hb (upper, lower), Gauss
+    GKS_BUF_EOH = 3,   /* double [6][n_edges]: 1/2 G hb^2 (upper, lower), hb (upper, lower), the
+                          mean of the two sides' reconstructed thicknesses (upper, lower), Gauss
                           points averaged, hb the interface thickness of the evolution solution */
-    GKS_BUF_EOM = 4,   /* real [22][n_edges]: flux F0 without 1/2 G hb^2 n (6), its time derivative
-                          (6), interface momenta (4), interface time derivatives (6), global frame */
+    GKS_BUF_EOM = 4,   /* real [24][n_edges]: flux F0 without 1/2 G hb^2 n (6), its time derivative
+                          (6), interface momenta (4), interface time derivatives (6), global frame,
+                          then the mean of the two sides' thickness rates -div(h U) (upper, lower) */
     GKS_BUF_SKIP = 5,  /* uint8 [n_tri]: the learned indicator's decisions of the last stage that ran
                           with it (1 = linear weights); unspecified before the first such stage */
     GKS_BUF_COUNT = 6

@@ -901,6 +901,36 @@ typedef struct {
     double Wb[3], Wbt[3];
 } gks_brackets;
 
+/* Well-balance weights of the acceleration term in the interface equilibrium's part of the
+ * evolution solution (Sec. 2.2, Eq. SWE-2nd-order, the constants alpha_{k,m}).  Reading: they
+ * are the weights that make the half-space moments of a balanced pair -- the |c|^2 slope of a
+ * level and the equal and opposite acceleration -2 lambda Phi . (u - U) -- vanish for this
+ * reading's Maxwellian-consistent slopes: (3/4, 1, 1) for the moments <psi_m> and (1, 5/4, 5/4)
+ * for <u psi_m> (m: mass, normal, tangential momentum).  The correction is taken relative to the
+ * full-space moments, so it vanishes where the two sides agree and the scheme stays consistent;
+ * it only acts on the jump between the sides' accelerations. */
+static const double ALPHA_W[2][3] = {{0.75, 1.0, 1.0}, {1.0, 1.25, 1.25}};
+
+static void alpha_correction(const double *sL, const double *sR, double lamb, double hb, double Ub, double Vb,
+                             const double *mub, const double *mubp, const double *mubm, const double *nvb, int e,
+                             double *d)
+{
+    double fL[11] = {0}, fR[11] = {0};
+    for (int i = 9; i < 11; i++) {
+        fL[i] = sL[i];
+        fR[i] = sR[i];
+    }
+    poly FL, FR;
+    p_micro(&FL, lamb, hb, Ub, Vb, fL); /* the acceleration term alone */
+    p_micro(&FR, lamb, hb, Ub, Vb, fR);
+    double lp[3], rm[3], lf[3], rf[3];
+    p_moment3(&FL, e, hb, mubp, nvb, lp);
+    p_moment3(&FR, e, hb, mubm, nvb, rm);
+    p_moment3(&FL, e, hb, mub, nvb, lf);
+    p_moment3(&FR, e, hb, mub, nvb, rf);
+    for (int k = 0; k < 3; k++) d[k] = (ALPHA_W[e][k] - 1) * (lp[k] + rm[k] - 0.5 * (lf[k] + rf[k]));
+}
+
 static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_brackets *o)
 {
     double hL = sL[0], UL = sL[1], VL = sL[2];
@@ -931,17 +961,19 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_
     p_zero(&one);
     one.c[0][0] = 1;
     /* time slope of the interface equilibrium from compatibility */
-    double t1[3], t2[3], Wbt[3];
+    double t1[3], t2[3], Wbt[3], da[3];
     p_moment3(&PbL, 0, hb, mubp, nvb, t1);
     p_moment3(&PbR, 0, hb, mubm, nvb, t2);
-    for (int k = 0; k < 3; k++) Wbt[k] = -(t1[k] + t2[k]);
+    alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 0, da);
+    for (int k = 0; k < 3; k++) Wbt[k] = -(t1[k] + t2[k] + da[k]);
     poly Abar;
     p_zero(&Abar);
     p_add_slope(&Abar, 1, lamb, hb, Ub, Vb, Wbt[0], Wbt[1], Wbt[2]);
     p_moment3(&one, 1, hb, mub, nvb, o->B[0]);
     p_moment3(&PbL, 1, hb, mubp, nvb, t1);
     p_moment3(&PbR, 1, hb, mubm, nvb, t2);
-    for (int k = 0; k < 3; k++) o->B[1][k] = t1[k] + t2[k];
+    alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 1, da);
+    for (int k = 0; k < 3; k++) o->B[1][k] = t1[k] + t2[k] + da[k];
     p_moment3(&Abar, 1, hb, mub, nvb, o->B[2]);
     p_moment3(&one, 1, hL, muLp, nvL, t1);
     p_moment3(&one, 1, hR, muRm, nvR, t2);
@@ -1092,8 +1124,8 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     }
 
     /* 3. gas-kinetic evolution at every Gauss point of every edge, both layers */
-    double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 12);
-#define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 12)
+    double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 14);
+#define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 14)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
         int kL = m->e_lk[2 * e], kR = m->e_lk[2 * e + 1];
@@ -1193,6 +1225,12 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
                     out[3 * q + 1] = src[q][1] * n[0] + src[q][2] * t[0];
                     out[3 * q + 2] = src[q][1] * n[1] + src[q][2] * t[1];
                 }
+                /* reading of the Gauss-point thicknesses in the layer coupling (Sec. 3.2, Eq.
+                 * SWE-source-discretization): the mean of the two sides' reconstructed values, and
+                 * for its time derivative the mean of the sides' own rates -div(h U) */
+                const double *a = side[layer][0], *b = side[layer][1];
+                out[12] = 0.5 * (a[0] + b[0]);
+                out[13] = -0.5 * ((a[5] + a[8]) + (b[5] + b[8]));
             }
         }
     }
@@ -1201,6 +1239,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     for (int c = 0; c < T; c++) {
         double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}};
         double hsum[6] = {0}, htsum[6] = {0};
+        double GGc[6][2] = {{0}}, GGct[6][2] = {{0}}; /* central Gauss-point thicknesses (slots 0, 3) */
         double inv = 1.0 / m->area[c];
         for (int k = 0; k < 3; k++) {
             int e = m->c_edge[3 * c + k];
@@ -1224,8 +1263,19 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
                         GG[o + v][d] += sg * ln * n[d] * Wb * inv;
                         GGt[o + v][d] += sg * ln * n[d] * Wbt * inv;
                     }
-                    hsum[o + v] += Wb / 3.0;
-                    htsum[o + v] += Wbt / 3.0;
+                    if (v == 0) {
+                        double hc = 0, hct = 0;
+                        for (int g = 0; g < 2; g++) {
+                            hc += 0.5 * EO(e, g, layer)[12];
+                            hct += 0.5 * EO(e, g, layer)[13];
+                        }
+                        for (int d = 0; d < 2; d++) {
+                            GGc[o][d] += sg * ln * n[d] * hc * inv;
+                            GGct[o][d] += sg * ln * n[d] * hct * inv;
+                        }
+                        hsum[o] += hc / 3.0;
+                        htsum[o] += hct / 3.0;
+                    }
                 }
             }
         }
@@ -1244,12 +1294,13 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
             Lt[4 + d] += LF[3] * (-G * gB[d]);
         }
         /* layer coupling (Sec. 3.2, Eq. SWE-source-discretization): Gauss-point mean thickness of
-         * one layer times the Green-Gauss derivative of the other, from the interface values */
+         * one layer times the Green-Gauss derivative of the other, from the central Gauss-point
+         * thicknesses; its time derivative by the product rule */
         for (int d = 0; d < 2; d++) {
-            L[4 + d] += -chi * G * hsum[3] * GG[0][d];
-            Lt[4 + d] += -chi * G * (htsum[3] * GG[0][d] + hsum[3] * GGt[0][d]);
-            L[1 + d] += -G * hsum[0] * GG[3][d];
-            Lt[1 + d] += -G * (htsum[0] * GG[3][d] + hsum[0] * GGt[3][d]);
+            L[4 + d] += -chi * G * hsum[3] * GGc[0][d];
+            Lt[4 + d] += -chi * G * (htsum[3] * GGc[0][d] + hsum[3] * GGct[0][d]);
+            L[1 + d] += -G * hsum[0] * GGc[3][d];
+            Lt[1 + d] += -G * (htsum[0] * GGc[3][d] + hsum[0] * GGct[3][d]);
         }
         for (int v = 0; v < 6; v++) {
             Lo[v * T + c] = L[v];

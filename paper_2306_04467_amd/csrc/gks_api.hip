@@ -508,7 +508,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                     {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
                     {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
                     {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
-                    {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 4 * uE * 8}, {&s->eom, 22 * uE * rs},
+                    {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 6 * uE * 8}, {&s->eom, 24 * uE * rs},
                     {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
                     {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
         for (auto &b : bufs) {
@@ -793,9 +793,9 @@ gks_status read_buffer(const gks_state *s, int32_t which, void *dst)
         return GKS_OK;
     }
     if (which == GKS_BUF_EOH) {
-        HIP_OK(hipMemcpy(dst, s->eoh, (size_t)(4 * E) * 8, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(dst, s->eoh, (size_t)(6 * E) * 8, hipMemcpyDeviceToHost));
     } else {
-        HIP_OK(hipMemcpy(dst, s->eom, (size_t)(22 * E) * sizeof(R), hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(dst, s->eom, (size_t)(24 * E) * sizeof(R), hipMemcpyDeviceToHost));
     }
     return GKS_OK;
 }
@@ -813,9 +813,9 @@ extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *
         case GKS_BUF_RECH: need = 12 * T * 8; break;
         case GKS_BUF_RECM: need = 96 * T * rs; break;
         case GKS_BUF_R0: need = 2 * T * rs; break;
-        case GKS_BUF_EOH: need = 4 * E * 8; break;
+        case GKS_BUF_EOH: need = 6 * E * 8; break;
         case GKS_BUF_SKIP: need = T; break;
-        default: need = 22 * E * rs; break;
+        default: need = 24 * E * rs; break;
         }
         if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
         HIP_OK(hipStreamSynchronize(s->stream));

@@ -13,10 +13,12 @@
 //          eta1, h1U1, h1V1), TG = T + NG ghosts
 //   rec    GpHead[6 T] and GpTail[6 T], cell-major: the reconstruction at each cell's six Gauss
 //          points, read by the edge kernels as 16-byte words (one cache line per record)
-//   eoh    [4][E] double: per edge, Gauss points averaged: 1/2 G hb^2 (upper, lower), hb (upper,
-//          lower), hb the interface thickness of the evolution
-//   eom    [22][E] R: F0 (6, hydrostatic part removed), Ft (6), interface momenta (4), interface
-//          time derivatives (6), global frame; read by the cell update's gather
+//   eoh    [6][E] double: per edge, Gauss points averaged: 1/2 G hb^2 (upper, lower), hb (upper,
+//          lower), hb the interface thickness of the evolution, then the mean of the two sides'
+//          reconstructed thicknesses (upper, lower) for the layer coupling
+//   eom    [24][E] R: F0 (6, hydrostatic part removed), Ft (6), interface momenta (4), interface
+//          time derivatives (6), global frame, then the mean of the two sides' thickness rates
+//          (upper, lower); read by the cell update's gather
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -836,8 +838,19 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
         bottom_moments(gBn, gBt, Ub, Vb, lamb, thb, Mp, 0, t1);
         bottom_moments(gBn, gBt, Ub, Vb, lamb, thb, Mm, 0, t2);
     }
+    // well-balance weights of the acceleration in the equilibrium part (Sec. 2.2, the constants
+    // alpha_{k,m} of Eq. SWE-2nd-order), read as the weights that make the half-space moments of a
+    // balanced level slope and acceleration vanish for these slopes: 3/4 on <1>, 5/4 on <u u> and
+    // <u v>, 1 elsewhere; applied relative to the full-space moments, so only the jump between the
+    // sides' accelerations is weighted.  With h lam = 1/G the acceleration's moments are
+    // -2 Phi_n N1_e / G (mass), -2 Phi_n N1_{e+1} / G, -2 (V Phi_n N1_e + th Phi_t M_e) / G.
+    const R aLn = sl.pn - G * gBn, aLt = sl.pt - G * gBt, aRn = sr.pn - G * gBn, aRt = sr.pt - G * gBt;
+    const R N1p0 = Mp[1] - Ub * Mp[0], N1m0 = Mm[1] - Ub * Mm[0];
+    // mass, state moment: weight 3/4 (the full-space moment is zero)
+    const R dA0 = sum_products(aLn, N1p0, aRn, N1m0) * (R(0.5) * iG);
 #pragma unroll
     for (int i = 0; i < 3; i++) wt[i] = -(t1[i] + t2[i]);
+    wt[0] -= dA0;
     // brackets multiplying the five time coefficients; B1 and B4 split into a hydrostatic part
     // and the rest.  B1 = (hb Ub, hb Ub^2 + P, hb Ub Vb)
     R B1[3], B2[3], B3[3];
@@ -852,6 +865,16 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     }
 #pragma unroll
     for (int i = 0; i < 3; i++) B2[i] = t1[i] + t2[i];
+    {
+        // flux moments: weight 5/4 on the two momentum components; full-space parts from
+        // N1_1 = th, N1_2 = 2 U th, M_1 = U
+        const R N1p1 = Mp[2] - Ub * Mp[1], N1m1 = Mm[2] - Ub * Mm[1];
+        const R N1p2 = Mp[3] - Ub * Mp[2], N1m2 = Mm[3] - Ub * Mm[2];
+        const R sn = aLn + aRn, st = aLt + aRt, q = R(-0.5) * iG;  // (5/4 - 1) (-2 / G)
+        B2[1] += q * (sum_products(aLn, N1p2, aRn, N1m2) - sn * Ub * thb);
+        B2[2] += q * (Vb * sum_products(aLn, N1p1, aRn, N1m1) + thb * sum_products(aLt, Mp[1], aRt, Mm[1]) -
+                      R(0.5) * thb * (sn * Vb + st * Ub));
+    }
     {
         const R aA = lamb * wt[0] * ihb;
         const R bA = 2 * lamb * (wt[1] - Ub * wt[0]) * ihb;
@@ -997,9 +1020,14 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     }
     // FP64 hydrostatic pieces: interface thickness and 1/2 G hb^2, averaged over the two points
     const double hb = hbase + (double)Wb[0];
-    double P = 0.5 * p.G * hb * hb, H = hb;
+    double P = 0.5 * p.G * hb * hb, H = hb, Hc = hbase;
     P = 0.5 * (P + __shfl_xor(P, 1));
     H = 0.5 * (H + __shfl_xor(H, 1));
+    // the layer coupling's Gauss-point thickness (Sec. 3.2, Eq. SWE-source-discretization), read as
+    // the mean of the two sides' reconstructed values, and its rate, the mean of the sides' -div(h U)
+    Hc = 0.5 * (Hc + __shfl_xor(Hc, 1));
+    R Hct = R(-0.5) * ((side[0].mnn + side[0].mtt) + (side[1].mnn + side[1].mtt));
+    Hct = R(0.5) * (Hct + __shfl_xor(Hct, 1));
     // the rest back to the global frame, then averaged over the two Gauss points
     R out[11];
     out[0] = F0[0];
@@ -1019,6 +1047,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     if (g == 0) {
         eoh[(int64_t)(lay == 0 ? 1 : 0) * E + e] = P;
         eoh[(int64_t)(lay == 0 ? 3 : 2) * E + e] = H;
+        eoh[(int64_t)(lay == 0 ? 5 : 4) * E + e] = Hc;
 #pragma unroll
         for (int i = 0; i < 3; i++) eom[(int64_t)(o + i) * E + e] = out[i];        // F0
 #pragma unroll
@@ -1029,6 +1058,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
         eom[(int64_t)(13 + mo) * E + e] = out[7];
 #pragma unroll
         for (int i = 0; i < 3; i++) eom[(int64_t)(16 + o + i) * E + e] = out[8 + i];  // Wbt
+        eom[(int64_t)(lay == 0 ? 23 : 22) * E + e] = Hct;
     }
 }
 
@@ -1075,6 +1105,7 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double 
         return;
     }
     double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}}, hs[2] = {0, 0}, hts[2] = {0, 0};
+    double GC[2][2] = {{0, 0}}, GCt[2][2] = {{0, 0}};  // [0] lower, [1] upper: central thicknesses
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         const int32_t code = m.cedge[k * T + c];
@@ -1112,10 +1143,20 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double 
             LF[4] -= gx * Pl;
             LF[5] -= gy * Pl;
         }
-        hs[1] += Hu;
-        hs[0] += Hl;
-        hts[1] += eom[16 * E + e];
-        hts[0] += eom[19 * E + e];
+        const double Cu = eoh[4 * E + e], Cl = eoh[5 * E + e];
+        const double Ctu = eom[22 * E + e], Ctl = eom[23 * E + e];
+        GC[1][0] += gx * Cu;
+        GC[1][1] += gy * Cu;
+        GC[0][0] += gx * Cl;
+        GC[0][1] += gy * Cl;
+        GCt[1][0] += gx * Ctu;
+        GCt[1][1] += gy * Ctu;
+        GCt[0][0] += gx * Ctl;
+        GCt[0][1] += gy * Ctl;
+        hs[1] += Cu;
+        hs[0] += Cl;
+        hts[1] += Ctu;
+        hts[0] += Ctl;
     }
     const double third = 1.0 / 3.0;
     hs[0] *= third; hs[1] *= third; hts[0] *= third; hts[1] *= third;  // [0] lower, [1] upper
@@ -1128,10 +1169,10 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double 
     Lt[2] += LF[0] * (-G * gBy);
     Lt[4] += LF[3] * (-G * gBx);
     Lt[5] += LF[3] * (-G * gBy);
-    Lt[4] += -chi * G * (hts[0] * GG[0][0] + hs[0] * GGt[0][0]);
-    Lt[5] += -chi * G * (hts[0] * GG[0][1] + hs[0] * GGt[0][1]);
-    Lt[1] += -G * (hts[1] * GG[3][0] + hs[1] * GGt[3][0]);
-    Lt[2] += -G * (hts[1] * GG[3][1] + hs[1] * GGt[3][1]);
+    Lt[4] += -chi * G * (hts[0] * GC[1][0] + hs[0] * GCt[1][0]);
+    Lt[5] += -chi * G * (hts[0] * GC[1][1] + hs[0] * GCt[1][1]);
+    Lt[1] += -G * (hts[1] * GC[0][0] + hs[1] * GCt[0][0]);
+    Lt[2] += -G * (hts[1] * GC[0][1] + hs[1] * GCt[0][1]);
     if constexpr (stage == 0) {
         double L[6];
 #pragma unroll
@@ -1139,11 +1180,11 @@ __global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double 
         const double h2 = Whin[c], h1 = Whin[TG + c] - m.Bbar[c];
         // bottom source h_j (0, -G B_x, -G B_y) (Sec. 3.2) and layer coupling
         // (Eq. SWE-source-discretization) from the Gauss-point mean thickness and the Green-Gauss
-        // derivative of the other layer's interface thickness
-        L[1] += h2 * (-G * gBx) - G * hs[1] * GG[3][0];
-        L[2] += h2 * (-G * gBy) - G * hs[1] * GG[3][1];
-        L[4] += h1 * (-G * gBx) - chi * G * hs[0] * GG[0][0];
-        L[5] += h1 * (-G * gBy) - chi * G * hs[0] * GG[0][1];
+        // derivative of the other layer's Gauss-point thickness (central values)
+        L[1] += h2 * (-G * gBx) - G * hs[1] * GC[0][0];
+        L[2] += h2 * (-G * gBy) - G * hs[1] * GC[0][1];
+        L[4] += h1 * (-G * gBx) - chi * G * hs[0] * GC[1][0];
+        L[5] += h1 * (-G * gBy) - chi * G * hs[0] * GC[1][1];
         // the state carries grad(eta1) = grad(h1) + grad(B)
         GG[3][0] += gBx;
         GG[3][1] += gBy;

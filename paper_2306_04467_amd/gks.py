@@ -37,8 +37,8 @@ SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_in
            "gks_trainer_threshold", "gks_autotune", "gks_last_error")
 _VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
 MLP_PARAMS, MLP_FEATURES = 7105, 44
-BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 4, True),
-           "eom": (4, 22, False), "skip": (5, 1, None)}
+BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 6, True),
+           "eom": (4, 24, False), "skip": (5, 1, None)}
 KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt", "indicator")
 
 

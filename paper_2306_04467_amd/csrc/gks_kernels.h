@@ -1071,7 +1071,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 // fluxes and the interface thicknesses, so it neither loads nor sums the momentum fluxes, the
 // hydrostatic terms and the interface momenta
 template <typename R, int STAGE>
-__global__ void __launch_bounds__(256) k_update(MeshDev m, Phys p, const double *__restrict__ eoh,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(MeshDev m, Phys p, const double *__restrict__ eoh,
                                                 const R *__restrict__ eom, const double *__restrict__ Whin,
                                                 const R *__restrict__ Wmin, const R *__restrict__ gWin,
                                                 double *__restrict__ Whout, R *__restrict__ Wmout,

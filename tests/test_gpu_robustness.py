@@ -30,12 +30,8 @@ CASES = {
     "riemann_interface": lambda: w.riemann_interface(400, 40),
     "circular_interface": lambda: w.circular_interface(100),
 }
-# How far each case runs here: the paper's end time for the exchange flow.  In the two problems
-# with the large interface jump the lower layer thins to nothing next to the front from t ~ 0.2
-# (channel) and t ~ 0.25 (circle) on: the shear between the layers there (|U1 - U2| ~ 1.3-2.5)
-# exceeds the bound of hyperbolicity (~0.6), and the scheme as read does not hold the growth (the
-# design notes keep the record).  They run to t = 0.15 and t = 0.2, before that.
-RUN_TO = {"riemann_exchange": 0.1, "riemann_interface": 0.15, "circular_interface": 0.2}
+# How far each case runs here: the paper's end times (Sec. 4), t = 0.1, 1 and 4.
+RUN_TO = {"riemann_exchange": 0.1, "riemann_interface": 1.0, "circular_interface": 4.0}
 
 
 def _area(sc):
@@ -133,7 +129,7 @@ def test_exchange_flow_keeps_the_lattice_translations(gks, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_channel_front_stays_one_dimensional(gks, precision):
-    """In the channel the interface Riemann problem is one-dimensional: at t = 0.15, 95 % of the
+    """In the channel the interface Riemann problem is one-dimensional: at its end time, 95 % of the
     cells lie within 5 % of the jump of their strip's mean (strips 0.025 wide across the channel;
     the rest are cells on the steep fronts), and the interface at x = 5 has left both initial
     levels."""
@@ -157,7 +153,7 @@ def test_channel_front_stays_one_dimensional(gks, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_circular_front_stays_circular(gks, precision):
-    """The circular interface problem is radially symmetric: at t = 0.2, 95 % of the cells lie
+    """The circular interface problem is radially symmetric: at its end time, 95 % of the cells lie
     within 5 % of the jump of their ring's mean (rings 0.05 wide about (5, 5); the rest are cells
     on the steep front), and the heavy column has started to spread (the lower layer's volume
     inside r < 2 has fallen)."""

@@ -111,6 +111,25 @@ def test_flux_smooth_limit_matches_pde(seed):
     np.testing.assert_allclose(F, ref, rtol=1e-10, atol=1e-14)
 
 
+@pytest.mark.parametrize("sL,sR", [(0.1, -0.3), (0.05, 0.4), (-0.2, 0.25)])
+def test_jumping_balanced_slopes_keep_the_interface_at_rest(sL, sR):
+    """Reading of the well-balance constants alpha_{k,m} (Sec. 2.2, Eq. SWE-2nd-order): two sides
+    at rest, each with its level slope balanced by its own acceleration (phi = G dh, a lake at
+    rest over a bottom whose slope jumps at the interface), must leave the interface at rest: its
+    state's time derivative vanishes in every component and no mass crosses.  With the weights
+    at 1 the mass rate of the interface state is of the size of the slopes (0.15 for the first
+    case)."""
+    h = 0.7
+
+    def side(s, st):
+        return [h, 0, 0, s, st, 0, 0, 0, 0, G * s, G * st]
+
+    F0, Ft, Wb, Wbt = o.gks_point(side(sL, 0.07), side(sR, -0.2), G, 1e-3)
+    assert np.abs(Wbt).max() < 1e-13, Wbt
+    assert abs(F0[0]) < 1e-13 and abs(Ft[0]) < 1e-13, (F0, Ft)
+    assert abs(Wb[0] - h) < 1e-15 and abs(Wb[1]) < 1e-15
+
+
 @pytest.mark.parametrize("seed", [3, 4, 5])
 def test_flux_mirror_symmetry(seed):
     """Reflecting x_n -> -x_n swaps the sides: mass and tangential-momentum fluxes change sign,
@@ -662,6 +681,38 @@ def test_smooth_periodic_self_convergence():
         e.append(np.abs(W - _restrict(scf, sc, Wf)).mean(axis=1))
     order = np.log2(e[0] / e[1])
     assert order.min() >= 1.4, (e, order)
+
+
+def test_rest_state_map_is_not_expansive_at_density_ratio_one():
+    """At density ratio 1 the internal mode at rest has no restoring force (the layers' pressure
+    gradient and the coupling force cancel), so any mismatch between the flux's pressure part and
+    the coupling source shows up as growth from round-off.  The one-step map about rest (flat
+    bottom, h1 = 0.8, h2 = 0.2, periodic 32-triangle lattice, linear reconstruction, CFL 0.5, the
+    paper's value) must have spectral radius 1: checked on its finite-difference Jacobian.  Both
+    readings are needed: the balanced weights of the acceleration (Sec. 2.2) and the central
+    Gauss-point thicknesses of the coupling (Sec. 3.2).  The earlier reading gave 1.38."""
+    chi, cfl = 1.0, 0.5
+    sc = w.smooth_periodic(4, chi=chi, cfl=cfl)
+    T = sc.n_tri
+    W0 = np.zeros((6, T))
+    W0[0], W0[3] = 0.2, 0.8
+    g0 = np.zeros((6, 2, T))
+    mesh = o.Mesh.from_scenario(sc)
+    p = o.params(chi=chi, cfl=cfl, linear=True)
+    dt = o.dt(mesh, p, W0)
+
+    def F(x):
+        W1, g1 = o.step(mesh, p, dt, W0 + x[:6 * T].reshape(6, T), g0 + x[6 * T:].reshape(6, 2, T))
+        return np.concatenate([(W1 - W0).ravel(), (g1 - g0).ravel()])
+
+    N, eps = 18 * T, 1e-7
+    J = np.zeros((N, N))
+    for i in range(N):
+        e = np.zeros(N)
+        e[i] = eps
+        J[:, i] = (F(e) - F(-e)) / (2 * eps)
+    rho = np.abs(np.linalg.eigvals(J)).max()
+    assert rho < 1 + 1e-6, rho
 
 
 def test_positivity_safeguard_keeps_gauss_point_thickness():

@@ -662,25 +662,28 @@ def _restrict(fine, coarse, Wf):
 
 
 def test_smooth_periodic_self_convergence():
-    """C1-type smooth two-layer flow on nested periodic meshes (16, 32, 64 squares a side) to
-    t = 0.05 with the linear reconstruction: the differences to the restricted finer solution fall
-    at an order of at least 1.4 in every component (measured 1.5-2.3).  The layer-coupling source
-    is second order (Sec. 3.2); on the next finer pair (32, 64, 128) the momenta fall at about first
-    order (1.0 upper, 1.4 lower) and the thicknesses at 1.6-2.1."""
+    """C1-type smooth two-layer flow on nested periodic meshes (32, 64, 128 squares a side) to
+    t = 0.05 with the linear reconstruction and a small relaxation constant (epsilon = 0.005 in
+    the collision time of Sec. 4): the differences to the restricted finer solution fall at second
+    order in every component (the layer-coupling source is second order, Sec. 3.2; measured
+    1.94-2.07).  With the paper's epsilon = 0.05 the viscous O(tau) = O(epsilon dt) part of the flux
+    limits the momenta to about first order on these meshes (1.0 upper, 1.4 lower)."""
     sols = {}
-    for n in (16, 32, 64):
+    for n in (32, 64, 128):
         sc = w.smooth_periodic(n, t_end=0.05)
         mesh = o.Mesh.from_scenario(sc)
-        W, _, t, _ = o.run(mesh, o.params_of(sc, linear=True), sc.W0, sc.gradW0, sc.t_end)
+        p = o.params_of(sc, linear=True)
+        p.eps = 0.005
+        W, _, t, _ = o.run(mesh, p, sc.W0, sc.gradW0, sc.t_end)
         assert abs(t - sc.t_end) < 1e-12
         sols[n] = (sc, W)
     e = []
-    for n in (16, 32):
+    for n in (32, 64):
         sc, W = sols[n]
         scf, Wf = sols[2 * n]
         e.append(np.abs(W - _restrict(scf, sc, Wf)).mean(axis=1))
     order = np.log2(e[0] / e[1])
-    assert order.min() >= 1.4, (e, order)
+    assert order.min() >= 1.85, (e, order)
 
 
 def test_rest_state_map_is_not_expansive_at_density_ratio_one():

@@ -70,7 +70,10 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
                          double *val, double *grad, double *r0);
 
 /* One Gauss point, one layer, local frame (u along the normal).  side = {h, U, V, dh_n, dh_t,
- * d(hU)_n, d(hU)_t, d(hV)_n, d(hV)_t, Phi_n, Phi_t}.  Outputs in the local frame. */
+ * d(hU)_n, d(hU)_t, d(hV)_n, d(hV)_t, Phi_n, Phi_t}.  Outputs in the local frame.  The
+ * acceleration term of the interface equilibrium carries the well-balance weights alpha_{k,m}
+ * (Sec. 2.2, Eq. SWE-2nd-order) as read here: on the jump between the two sides' accelerations,
+ * 3/4 on the mass state moment and 5/4 on the momentum flux moments. */
 void om_gks_point(const double *sideL, const double *sideR, double G, double dt, double eps,
                   double eps_num, double *F0, double *Ft, double *Wb, double *Wbt);
 /* Same, returning the time-integrated flux F(delta) for one delta (for the closed-form pins). */
@@ -87,7 +90,8 @@ double om_dt(const om_mesh *m, const om_params *p, const double *W);
 
 /* Spatial operator of one stage: for the stage state (W, gW) and the step's dt, returns
  * L[6][T], Lt[6][T] (right-hand side and its time derivative) and the Green-Gauss gradients of
- * the interface values GW[6][2][T], GWt[6][2][T] (Sec. 3.1-3.3). */
+ * the interface values GW[6][2][T], GWt[6][2][T] (Sec. 3.1-3.3).  The layer coupling takes its
+ * Gauss-point thicknesses as the mean of the two sides' reconstructed values (Sec. 3.2). */
 int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
                 double *L, double *Lt, double *GW, double *GWt);
 

@@ -13,7 +13,12 @@
  * positivity safeguard the paper does not state), the interface force modelling (Sec. 2.3), the
  * time-accurate gas-kinetic evolution at two Gauss points per edge (Sec. 2.2, Eq. SWE-2nd-order)
  * and the well-balanced finite-volume update with bottom and layer-coupling sources
- * (Sec. 3.1-3.2).
+ * (Sec. 3.1-3.2).  Two details the paper leaves to a reference are read here as follows.  The
+ * well-balance weights alpha_{k,m} of the evolution's acceleration term make the half-space
+ * moments of a balanced level slope and acceleration vanish: 3/4 on the mass state moment and
+ * 5/4 on the momentum flux moments, applied to the jump between the two sides.  The Gauss-point
+ * thicknesses of the layer coupling are the mean of the two sides' reconstructed values, with
+ * the mean of their rates -div(hU) as time derivative.
  *
  * Conventions
  *  - All pointers to user arrays are HOST pointers; the library copies them (the caller keeps

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
 
 
 def build() -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     return _LIB
 
@@ -74,6 +74,8 @@ def load():
     lib.om_mlp_grad.argtypes = [_dp, _dp, _dp, ctypes.c_int, _dp]
     lib.om_mlp_forward_bf16.argtypes = [_dp, _dp, ctypes.c_int, _dp]
     lib.om_mlp_grad.restype = ctypes.c_double
+    lib.om_set_threads.argtypes = [ctypes.c_int]
+    lib.om_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 

@@ -3,7 +3,9 @@
  * shallow water equations on triangles (Zhao, Gan & Xu).  TEST INFRASTRUCTURE ONLY: loaded by the
  * tests, the smoke check and the CPU-baseline leg of the benchmark, never by the product.  It
  * shares no source with the HIP library and is written for clarity, not speed: dense loops,
- * explicit quadrature, one cell / edge / Gauss point at a time.
+ * explicit quadrature, one cell / edge / Gauss point at a time.  The independent per-cell and
+ * per-edge loops carry OpenMP pragmas; every iteration writes only its own outputs and every sum
+ * is taken in a fixed order inside one iteration, so results do not depend on the thread count.
  *
  * Points where the paper defers to companion papers or is silent are filled in by the readings
  * listed in the design notes of the repository; each is marked "reading:" where it is used.
@@ -11,6 +13,7 @@
 #include "gks_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -530,6 +533,7 @@ om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, cons
         }
     }
     m->M = (double *)malloc(sizeof(double) * (size_t)nt * NDOF * NROW);
+#pragma omp parallel for schedule(dynamic, 256)
     for (int c = 0; c < nt; c++) build_lsq(m, c);
     return m;
 }
@@ -546,6 +550,10 @@ void om_mesh_free(om_mesh *m)
 }
 
 int om_mesh_n_edges(const om_mesh *m) { return m->ne; }
+
+void om_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
+int om_max_threads(void) { return omp_get_max_threads(); }
 
 /* Interface height of the force model (Sec. 2.3): the convex combination of the two sides' heights
  * whose weight xi is, in this reading, the fraction of the particles of the interface Maxwellian
@@ -669,7 +677,7 @@ static double beta_cubic(const double *a, const double v0[3][2], const double *x
 void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                          double *val, double *grad, double *r0)
 {
-    const double d0 = 0.8, dm = 0.05; /* reading: linear weights of the WENO-AO combination */
+    const double dlin = 0.05; /* reading: linear weight of each lower-order candidate */
     double x0[2] = {m->cx[c], m->cy[c]};
     double area = m->area[c];
     double h = sqrt(2.0 * area);
@@ -707,40 +715,53 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             a[i] = s;
         }
         /* lower-order candidates: planes through the averages of {0,i,j}, {0,j,k}, {0,k,i}
-         * (face neighbours are stencil slots 1..3) and the cell's own gradient */
-        double b[4][2];
+         * (face neighbours are stencil slots 1..3) and the cell's own gradient.  Reading: a
+         * sub-stencil whose two centroid offsets are nearly parallel (the sine of the angle between
+         * them below 0.2) does not determine a plane and is not a candidate; its linear weight
+         * goes to P^3.  Such a plane's slope is huge, and the combination below subtracts
+         * (omega_0 / d_0) d_m P_m even when the plane's own weight has dropped to zero. */
+        double b[4][2], dm[4];
         for (int s = 0; s < 3; s++) {
             int la = 1 + s, lb = 1 + (s + 1) % 3;
             double ax = cen[la][0] - x0[0], ay = cen[la][1] - x0[1];
             double bx = cen[lb][0] - x0[0], by = cen[lb][1] - x0[1];
             double ra = q[la][v] - Q0, rb = q[lb][v] - Q0;
             double det = ax * by - ay * bx;
-            b[s][0] = (ra * by - ay * rb) / det;
-            b[s][1] = (ax * rb - ra * bx) / det;
+            if (fabs(det) >= OM_PLANE_SINE_MIN * sqrt((ax * ax + ay * ay) * (bx * bx + by * by))) {
+                dm[s] = dlin;
+                b[s][0] = (ra * by - ay * rb) / det;
+                b[s][1] = (ax * rb - ra * bx) / det;
+            } else {
+                dm[s] = 0;
+                b[s][0] = b[s][1] = 0;
+            }
         }
+        dm[3] = dlin;
         b[3][0] = gq[0][v][0];
         b[3][1] = gq[0][v][1];
-        double w0 = d0, wm[4] = {dm, dm, dm, dm};
+        int ncand = 0;
+        for (int s = 0; s < 4; s++) ncand += dm[s] > 0;
+        const double d0 = ncand == 4 ? 0.8 : ncand == 3 ? 0.85 : ncand == 2 ? 0.9 : 0.95; /* 1 - ncand dlin */
+        double w0 = d0, wm[4] = {dm[0], dm[1], dm[2], dm[3]};
         if (!linear) {
             double beta0 = beta_cubic(a, v0, x0, area);
             double betam[4], tauz = 0;
             for (int s = 0; s < 4; s++) {
                 betam[s] = area * (b[s][0] * b[s][0] + b[s][1] * b[s][1]);
-                tauz += fabs(beta0 - betam[s]);
+                if (dm[s] > 0) tauz += fabs(beta0 - betam[s]);
             }
-            tauz *= 0.25;
+            tauz /= ncand;
             /* reading: the floor of the smoothness indicators carries the variable's scale, the
-             * level itself for a thickness and 1e-5 h sqrt(G h) of the layer for a momentum, so
-             * that round-off about a state at rest stays under the linear weights */
+             * level itself for a thickness and 1e-8 h sqrt(G h) of the layer for a momentum */
             double S2 = 1e-20;
             if (v != 0 && v != 3) {
                 double hl = W[(v < 3 ? 0 : 3) * m->nt + c];
-                S2 = 1e-10 * G * hl * hl * hl;
+                S2 = 1e-16 * G * hl * hl * hl;
             }
             double eps = 1e-10 * fmax(Q0 * Q0, S2);
             double wt0 = d0 * (1 + tauz / (beta0 + eps)), wts[4], sum = wt0;
             for (int s = 0; s < 4; s++) {
-                wts[s] = dm * (1 + tauz / (betam[s] + eps));
+                wts[s] = dm[s] * (1 + tauz / (betam[s] + eps));
                 sum += wts[s];
             }
             w0 = wt0 / sum;
@@ -762,7 +783,7 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             double R = (w0 / d0) * P, Rx = (w0 / d0) * Px, Ry = (w0 / d0) * Py;
             for (int s = 0; s < 4; s++) {
                 double Pm = Q0 + b[s][0] * dx + b[s][1] * dy;
-                double coef = wm[s] - (w0 / d0) * dm;
+                double coef = wm[s] - (w0 / d0) * dm[s];
                 R += coef * Pm;
                 Rx += coef * b[s][0];
                 Ry += coef * b[s][1];
@@ -1078,6 +1099,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     double *val = (double *)malloc(sizeof(double) * (size_t)T * 36);
     double *grd = (double *)malloc(sizeof(double) * (size_t)T * 72);
     double *r0 = (double *)malloc(sizeof(double) * (size_t)T * 6);
+#pragma omp parallel for schedule(dynamic, 256)
     for (int c = 0; c < T; c++)
         om_reconstruct_cell(m, c, W, gW, p->linear, p->G, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6);
 
@@ -1088,6 +1110,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     /* 2. interface modelling of the heights that drive the layer forces (Sec. 2.3):
      *    field 0 = eta1 = h1 + B with layer-1 velocities, field 1 = h2 with layer-2 velocities */
     double *hmid = (double *)malloc(sizeof(double) * (size_t)E * 2);
+#pragma omp parallel for schedule(static)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
         int kL = m->e_lk[2 * e], kR = m->e_lk[2 * e + 1];
@@ -1115,6 +1138,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     }
     /* gradient of the plane through the three edge-centre values of each cell */
     double *gP1 = (double *)malloc(sizeof(double) * (size_t)T * 4);
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < T; c++) {
         for (int f = 0; f < 2; f++) {
             double hk[3];
@@ -1126,6 +1150,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     /* 3. gas-kinetic evolution at every Gauss point of every edge, both layers */
     double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 14);
 #define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 14)
+#pragma omp parallel for schedule(dynamic, 256)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
         int kL = m->e_lk[2 * e], kR = m->e_lk[2 * e + 1];
@@ -1236,6 +1261,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     }
 
     /* 4. cell gather: flux divergence, Green-Gauss gradients of the interface values, sources */
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < T; c++) {
         double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}};
         double hsum[6] = {0}, htsum[6] = {0};
@@ -1377,6 +1403,7 @@ void om_mass(const om_mesh *m, const double *W, double *mass)
 
 void om_features(const om_mesh *m, double G, const double *W, const double *gW, double *X)
 {
+#pragma omp parallel for schedule(static)
     for (int c = 0; c < m->nt; c++) {
         double q[NS][NV], gq[NS][NV][2];
         for (int l = 0; l < NS; l++) {

@@ -3,7 +3,7 @@
  * triangular meshes (Zhao, Gan & Xu, "High-order compact gas-kinetic scheme for two-layer shallow
  * water equations on unstructured mesh").
  *
- * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded FP64 CPU implementation written
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow FP64 CPU implementation written
  * from the paper's equations, used to check the HIP implementation.  Only the test-suite, the smoke
  * check and the CPU-baseline leg of the benchmark may load it; the product never calls it.  It
  * shares no source with the HIP library.
@@ -44,6 +44,10 @@ void om_s2o4_final(int n, double dt, const double *W, const double *L, const dou
 /* Mesh: node coordinates [nn][2], counter-clockwise triangles [nt][3], bottom at the nodes
  * (piecewise linear), periodic != 0 pairs the boundary edges of [0,Lx]x[0,Ly] by translation,
  * otherwise every boundary edge is a reflecting wall.  Returns NULL on a malformed mesh. */
+/* Threads used by the per-cell and per-edge loops (OpenMP); results do not depend on it. */
+void om_set_threads(int n);
+int om_max_threads(void);
+
 om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, const double *node_B,
                      int periodic, double Lx, double Ly);
 void om_mesh_free(om_mesh *m);
@@ -61,11 +65,15 @@ void om_plane_gradient(const om_mesh *m, int c, const double *hk, double *out);
 void om_stencil(const om_mesh *m, int c, int *cells, double *maps);
 /* Least-squares solution matrix of cell c, [9][17] row-major (Sec. 3.4, Eq. Recons-system). */
 void om_lsq_matrix(const om_mesh *m, int c, double *M);
+/* Smallest sine of the angle between the two centroid offsets of a plane candidate of the
+ * nonlinear reconstruction (a sub-stencil {0, i, j}); flatter sub-stencils are not candidates. */
+#define OM_PLANE_SINE_MIN 0.2
+
 /* Reconstruction of all six variables in cell c (with eta1 = h1 + B in place of h1) at the cell's
  * six Gauss points (local edge k, point g -> index 2k+g):
  *   val[6 gp][6 comp], grad[6 gp][6 comp][2], r0[6 comp] = omega_0 / d_0.
  * linear != 0 returns the linear P^3 reconstruction (all weights at their linear values).  G enters
- * the floor of the smoothness indicators of the momenta (scale 1e-5 h sqrt(G h)). */
+ * the floor of the smoothness indicators of the momenta (scale 1e-8 h sqrt(G h)). */
 void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                          double *val, double *grad, double *r0);
 

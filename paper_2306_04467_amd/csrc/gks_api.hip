@@ -281,6 +281,7 @@ gks_status upload_mesh(gks_mesh *m)
     up(h.eslot, &d.eslot);
     up(h.gsrc, &d.gsrc);
     up(h.scell, &d.scell);
+    up(h.cand, &d.cand);
     const double *M = nullptr, *hs = nullptr, *vtx = nullptr, *nbc = nullptr, *en = nullptr, *egB = nullptr;
     up(h.M, &M);
     up(h.hs, &hs);

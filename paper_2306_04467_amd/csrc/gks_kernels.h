@@ -35,6 +35,7 @@ struct MeshDev {
     // tables in the bulk precision (double or float copies)
     const void *M, *hs, *vtx, *nbc, *en, *egB;
     const float *igeo;              // [6][T] indicator geometry
+    const uint8_t *cand;            // [T] plane candidates of the nonlinear reconstruction (bits 0..2)
     const int32_t *cedge, *sten, *eL, *eR, *eslot, *gsrc;
     const int32_t *cscen, *escen;   // scenario of each cell / edge, nullptr when S == 1
     // batches: the cells cut into chunks that never straddle two scenarios, chunk c covering
@@ -253,23 +254,31 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     const R mean_const = a[2] * mxx * c12 + a[3] * mxy * c12 + a[4] * myy * c12 + a[5] * mx3 * c30 +
                          a[6] * mx2y * c30 + a[7] * mxy2 * c30 + a[8] * my3 * c30;
     // lower-order candidates (reading of the nonlinear compact reconstruction): planes through
-    // the averages of {0, f0, f1}, {0, f1, f2}, {0, f2, f0} and the cell's own gradient
+    // the averages of {0, f0, f1}, {0, f1, f2}, {0, f2, f0} and the cell's own gradient.  A
+    // sub-stencil whose centroid offsets are nearly parallel is not a candidate (bit clear in
+    // m.cand, decided at setup in FP64): its plane would carry a huge slope into the combination
+    // below; its linear weight goes to P^3.
     const R *nbc = tab<R>(m.nbc);
-    R bx[4], by[4];
+    const unsigned cmask = m.cand[c];
+    R bx[4], by[4], dm[4];
 #pragma unroll
     for (int s = 0; s < 3; s++) {
         const int sa = s, sb = (s + 1) % 3;
         const R ax_ = nbc[(2 * sa) * T + c], ay_ = nbc[(2 * sa + 1) * T + c];
         const R bx_ = nbc[(2 * sb) * T + c], by_ = nbc[(2 * sb + 1) * T + c];
         const R ra = rhs[sa], rb = rhs[sb];
-        const R inv = R(1) / (ax_ * by_ - ay_ * bx_);
+        const bool on = (cmask >> s) & 1u;
+        const R inv = on ? R(1) / (ax_ * by_ - ay_ * bx_) : R(0);
         bx[s] = (ra * by_ - ay_ * rb) * inv;
         by[s] = (ax_ * rb - ra * bx_) * inv;
+        dm[s] = on ? R(0.05) : R(0);
     }
     bx[3] = rhs[9];
     by[3] = rhs[10];
-    const R d0 = R(0.8), dm = R(0.05);
-    R w0 = d0, wm[4] = {dm, dm, dm, dm};
+    dm[3] = R(0.05);
+    const int ncand = 1 + __builtin_popcount(cmask & 7u);
+    const R d0 = ncand == 4 ? R(0.8) : ncand == 3 ? R(0.85) : ncand == 2 ? R(0.9) : R(0.95);
+    R w0 = d0, wm[4] = {dm[0], dm[1], dm[2], dm[3]};
     const bool nonlinear = !p.linear && !lin;
     if (nonlinear) {
         // smoothness indicator of P^3 in scaled coordinates: the cell has area 1/2 there, so the
@@ -306,19 +315,18 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             bm[s] = R(0.5) * (bx[s] * bx[s] + by[s] * by[s]);
-            tz += fabs(beta0 - bm[s]);
+            if (dm[s] != R(0)) tz += fabs(beta0 - bm[s]);
         }
-        tz *= R(0.25);
+        tz = ncand == 4 ? tz * R(0.25) : div_(tz, R(ncand));
         // floor of the smoothness indicators with the variable's scale: the level of a thickness,
-        // 1e-5 h sqrt(G h) of the layer for a momentum (round-off about rest stays under the
-        // linear weights)
-        const R S2 = thick ? R(1e-20) : (R)(1e-10 * p.G * q.hl * q.hl * q.hl);
+        // 1e-8 h sqrt(G h) of the layer for a momentum
+        const R S2 = thick ? R(1e-20) : (R)(1e-16 * p.G * q.hl * q.hl * q.hl);
         const R epsw = R(1e-10) * fmax(Q0 * Q0, S2);
         const R t0 = d0 * (1 + div_(tz, beta0 + epsw));
         R sum = t0, tm[4];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            tm[s] = dm * (1 + div_(tz, bm[s] + epsw));
+            tm[s] = dm[s] * (1 + div_(tz, bm[s] + epsw));
             sum += tm[s];
         }
         // where every unnormalised weight equals its linear weight (tau = 0, or tau / (beta + eps)
@@ -326,7 +334,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         // exactly instead of dividing by their rounded sum
         bool lin = t0 == d0;
 #pragma unroll
-        for (int s = 0; s < 4; s++) lin = lin && tm[s] == dm;
+        for (int s = 0; s < 4; s++) lin = lin && tm[s] == dm[s];
         const R isum = lin ? R(1) : div_(R(1), sum);
         w0 = t0 * isum;
 #pragma unroll
@@ -339,7 +347,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     R sbx = 0, sby = 0;
 #pragma unroll
     for (int s = 0; s < 4; s++) {
-        const R cm = wm[s] - ratio * dm;
+        const R cm = wm[s] - ratio * dm[s];
         sbx += cm * bx[s];
         sby += cm * by[s];
     }

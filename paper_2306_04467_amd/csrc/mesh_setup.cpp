@@ -377,6 +377,7 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
     };
     m.sten.assign(9 * nt, 0);
     m.nbc.assign(6 * nt, 0);
+    m.cand.assign(nt, 0);
     m.M.assign(153 * nt, 0);
     // stencil images and least-squares operators: independent per cell, computed by a pool of host
     // threads; the images' linear parts are kept to number the ghost cells serially afterwards
@@ -444,6 +445,18 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
                 m.nbc[(2 * (l - 1) + 1) * nt + c] = (v[0][1] + v[1][1] + v[2][1]) / 3.0;
             }
         }
+        // plane candidates of the nonlinear reconstruction: sub-stencils {0, s, s+1} whose centroid
+        // offsets are not nearly parallel
+        uint8_t cm = 0;
+        for (int s = 0; s < 3; s++) {
+            const int sb = (s + 1) % 3;
+            const double ax = m.nbc[(2 * s) * nt + c], ay = m.nbc[(2 * s + 1) * nt + c];
+            const double bx = m.nbc[(2 * sb) * nt + c], by = m.nbc[(2 * sb + 1) * nt + c];
+            const double cross = ax * by - ay * bx;
+            if (std::fabs(cross) >= PLANE_SINE_MIN * std::sqrt((ax * ax + ay * ay) * (bx * bx + by * by)))
+                cm |= (uint8_t)(1u << s);
+        }
+        m.cand[c] = cm;
         double Mc[153];
         lsq_operator(A, Mc);
         for (int i = 0; i < 153; i++) m.M[(int64_t)i * nt + c] = Mc[i];
@@ -525,6 +538,14 @@ HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts)
     cells(o.gB, 2, &HostMesh::gB);
     cells(o.M, 153, &HostMesh::M);
     cells(o.igeo, 6, &HostMesh::igeo);
+    o.cand.assign(T, 0);
+    {
+        int64_t off = 0;
+        for (const HostMesh *p : parts) {
+            for (int64_t c = 0; c < p->nt; c++) o.cand[off + c] = p->cand[c];
+            off += p->nt;
+        }
+    }
     edges(o.en, 2, &HostMesh::en);
     edges(o.eBgp, 2, &HostMesh::eBgp);
     edges(o.egB, 2, &HostMesh::egB);

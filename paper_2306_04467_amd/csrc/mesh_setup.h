@@ -17,6 +17,10 @@ struct HostMesh {
     std::vector<double> hs;          // [T] length scale sqrt(2 |Omega|) of the scaled coordinates
     std::vector<double> vtx;         // [6][T] vertex offsets from the centroid, divided by hs
     std::vector<double> nbc;         // [6][T] centroid offsets of the 3 face-neighbour images / hs
+    std::vector<uint8_t> cand;       // [T] bit s: the plane through the averages of the cell and
+                                     // its face neighbours s, s+1 is a candidate of the nonlinear
+                                     // reconstruction (its two centroid offsets are not nearly
+                                     // parallel)
     std::vector<double> fl;          // [3][T] sigma_k |Gamma_k| / |Omega|
     std::vector<double> gg;          // [6][T] sigma_k |Gamma_k| n_k / |Omega| (x, y per edge)
     std::vector<double> Bbar;        // [T] cell average of the piecewise-linear bottom
@@ -42,6 +46,9 @@ struct HostMesh {
     std::vector<int64_t> scell;         // [S + 1] first cell of each scenario
     std::vector<double> sdxmin;         // [S]
 };
+
+// Smallest sine of the angle between the two centroid offsets of a plane candidate.
+constexpr double PLANE_SINE_MIN = 0.2;
 
 // Returns 0 on success, otherwise fills err.  bc: 0 walls, 1 periodic on [0,L0]x[0,L1].
 int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt, const double *B,

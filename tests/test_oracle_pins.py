@@ -292,22 +292,22 @@ def test_reconstruction_nonoscillatory_at_a_jump():
 
 def test_smoothness_floor_carries_the_variable_scale():
     """Reading of the nonlinear weights' floor: epsilon = 1e-10 max(Q0^2, S^2) with S the level of a
-    thickness and 1e-5 h sqrt(G h) of the layer for a momentum.  Round-off noise on a momentum at rest
-    keeps the linear weights (omega_0 / d_0 = 1), while a momentum jump of a tenth of
-    h sqrt(G h) still switches them (the oracle divides by the rounded sum of the weights, hence
-    the 1e-12)."""
+    thickness and 1e-8 h sqrt(G h) of the layer for a momentum, so that the floor of a momentum at
+    rest sits at about 1e-13 h sqrt(G h).  Momentum noise well under it (1e-19) keeps the linear
+    weights (omega_0 / d_0 = 1), while a momentum jump of 1e-10 h sqrt(G h) already switches them
+    (the oracle divides by the rounded sum of the weights, hence the 1e-12)."""
     sc = w.lake_at_rest(8, seed=3)
     T = sc.n_tri
     mesh = o.Mesh.from_scenario(sc)
     rng = np.random.default_rng(11)
     W = sc.W0.copy()
-    W[[1, 2, 4, 5]] = 1e-15 * rng.standard_normal((4, T))
+    W[[1, 2, 4, 5]] = 1e-19 * rng.standard_normal((4, T))
     for c in range(0, T, 5):
         _, _, r0 = mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)
         assert np.abs(r0 - 1.0).max() < 1e-12, (c, r0)
     cen = sc.node_xy[sc.tri].mean(axis=1)
     W = sc.W0.copy()
-    W[1] = np.where(cen[:, 0] < 0.5, 0.1 * 0.2 * np.sqrt(sc.G * 0.2), 0.0)
+    W[1] = np.where(cen[:, 0] < 0.5, 1e-10 * 0.2 * np.sqrt(sc.G * 0.2), 0.0)
     r_min = min(mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)[2][1] for c in range(T))
     assert r_min < 0.9, r_min
 

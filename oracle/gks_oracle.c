@@ -752,13 +752,15 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             }
             tauz /= ncand;
             /* reading: the floor of the smoothness indicators carries the variable's scale, the
-             * level itself for a thickness and 1e-8 h sqrt(G h) of the layer for a momentum */
+             * level itself for a thickness and 1e-8 h sqrt(G h) of the layer for a momentum, with
+             * the relative factor 1e-16: the weights leave their linear values once a variable
+             * varies by about 1e-8 of its scale */
             double S2 = 1e-20;
             if (v != 0 && v != 3) {
                 double hl = W[(v < 3 ? 0 : 3) * m->nt + c];
                 S2 = 1e-16 * G * hl * hl * hl;
             }
-            double eps = 1e-10 * fmax(Q0 * Q0, S2);
+            double eps = 1e-16 * fmax(Q0 * Q0, S2);
             double wt0 = d0 * (1 + tauz / (beta0 + eps)), wts[4], sum = wt0;
             for (int s = 0; s < 4; s++) {
                 wts[s] = dm[s] * (1 + tauz / (betam[s] + eps));

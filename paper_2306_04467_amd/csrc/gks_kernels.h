@@ -54,6 +54,15 @@ struct Phys {
     double *scal;         // [2S] per scenario: dt of the current step, time at its end
 };
 
+// relative floor of the smoothness indicators of the nonlinear reconstruction, above the
+// rounding of the bulk precision: the weights leave their linear values once a variable varies
+// by about 1e-8 of its scale (FP64), 1e-5 in the mixed path, whose reconstruction runs in FP32
+template <typename R>
+__device__ constexpr R eps_rel()
+{
+    return sizeof(R) == 8 ? R(1e-16) : R(1e-10);
+}
+
 template <typename R>
 __device__ inline const R *tab(const void *p)
 {
@@ -321,7 +330,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         // floor of the smoothness indicators with the variable's scale: the level of a thickness,
         // 1e-8 h sqrt(G h) of the layer for a momentum
         const R S2 = thick ? R(1e-20) : (R)(1e-16 * p.G * q.hl * q.hl * q.hl);
-        const R epsw = R(1e-10) * fmax(Q0 * Q0, S2);
+        const R epsw = eps_rel<R>() * fmax(Q0 * Q0, S2);
         const R t0 = d0 * (1 + div_(tz, beta0 + epsw));
         R sum = t0, tm[4];
 #pragma unroll

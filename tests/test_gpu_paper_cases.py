@@ -44,6 +44,8 @@ def _e1_error(gks, n, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_accuracy_table_on_gpu(gks, precision):
+    """At most 3 times and at least a quarter of the printed errors, mean order >= 1.9 (see the
+    oracle pin of the same table: the nonlinear weights cost the paper's order on this problem)."""
     with open(os.path.join(GOLDEN, "accuracy_table.json")) as f:
         gold = json.load(f)
     errs = {"1/8": _e1_error(gks, 16, precision), "1/16": _e1_error(gks, 32, precision),
@@ -51,22 +53,21 @@ def test_accuracy_table_on_gpu(gks, precision):
     print(f"[paper] E1 {precision}: {errs}", flush=True)
     for v, key in ((0, "h1"), (1, "h2")):
         for row, e in errs.items():
-            # the paper states neither its mesh nor its L1 normalisation: same magnitude (factor 5)
             ref = gold["rows"][row][key]
-            assert ref / 5 < e[v] < 5 * ref, (key, row, e[v], ref)
-        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.8
+            assert ref / 4 < e[v] < 3 * ref, (key, row, e[v], ref)
+        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.9
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_lake_at_rest_1000_steps(gks, precision):
     """The unperturbed 520,200-triangle lake at rest (bump 0.5 exp(-50 r^2), lower level 0.8, upper
     layer 0.2, density ratio 0.98, walls) over 1000 steps: momenta against h sqrt(G h), levels
-    against h.  The state is an exact fixed point of the scheme, but round-off seeds modes that the
-    compact gradient update amplifies at a few cells of this jittered mesh while the reconstruction
-    runs on its linear weights (the oracle does the same on a patch of the mesh); the nonlinear
-    weights switch on near the momentum floor of the smoothness indicators (1e-10 of the scale) and
-    hold the deviation there.  The test pins that level and finiteness: the paper's bound (1e-8) for
-    FP32, a tighter one for FP64, not round-off."""
+    against h.  The state is an exact fixed point of the scheme.  Round-off seeds modes that the
+    compact gradient update amplifies at a few obtuse cells of this jittered mesh while the
+    reconstruction runs on its linear weights (the oracle does the same on a patch of the mesh);
+    the nonlinear weights engage at the floor of the smoothness indicators, which sits near
+    round-off for a momentum at rest, and hold the deviation there: 1e-12 of the scale in FP64
+    (measured 7e-14 / 2e-13), 1e-10 in the mixed path, whose momenta are single precision."""
     sc = w.lake_at_rest(510)
     m = gks.Mesh.from_scenario(sc)
     st = gks.State.from_scenario(m, sc, precision=precision)
@@ -80,19 +81,21 @@ def test_lake_at_rest_1000_steps(gks, precision):
         dh = max(np.abs(W[3] - sc.W0[3]).max() / 0.3, np.abs(W[0] - sc.W0[0]).max() / 0.2)
         print(f"[paper] lake at rest {precision} {250 * (k + 1)} steps: scaled max|hU| {mom:.2e} "
               f"max|dh| {dh:.2e}", flush=True)
-        bound = 1e-9 if precision == "fp64" else 1e-8
+        bound = 1e-12 if precision == "fp64" else 1e-10
         assert mom < bound and dh < bound
 
 
 @pytest.mark.parametrize("chi,precision,bound", [(0.9, "fp64", 1e-11), (0.9, "fp32", 1e-6),
-                                                 (1.0, "fp64", 1e-4), (1.0, "fp32", 1e-4)])
+                                                 (1.0, "fp64", 1e-8), (1.0, "fp32", 1e-4)])
 def test_well_balance_test_to_t100(gks, chi, precision, bound):
     """The well-balance test of Sec. 4 ([0, 2]^2, cell size 0.05, bump 0.5 exp(-50 r^2) at the
     centre, h1 = 0.8 - B, h2 = 0.2, CFL 0.5, walls) run to its end time t = 100, about 46,000
-    steps.  At the paper's density ratio 1 the internal mode has no restoring force; the run
-    reaches t = 100 with deviations near 1e-5 (the paper reports < 1e-8).  At 0.9 the deviation
-    stays at round-off in FP64 (measured 2e-13) and at single-precision rounding in FP32-mixed,
-    whose momenta are single precision."""
+    steps.  At the paper's density ratio 1 the internal mode has no restoring force and the linear
+    scheme lets it grow from round-off; the nonlinear weights hold it at their floor, 1e-8 of the
+    level in FP64: the paper's bound (< 1e-8, measured 9.8e-9).  The mixed path's floor sits at
+    1e-5 of the level, above single-precision rounding (measured 1.1e-5).  At 0.9 the deviation
+    stays at round-off in FP64 (measured 2.6e-13) and at single-precision rounding in the mixed
+    path, whose momenta are single precision."""
     import dataclasses
 
     sc = dataclasses.replace(w.well_balance_bump(40), chi=chi)

@@ -291,25 +291,33 @@ def test_reconstruction_nonoscillatory_at_a_jump():
 
 
 def test_smoothness_floor_carries_the_variable_scale():
-    """Reading of the nonlinear weights' floor: epsilon = 1e-10 max(Q0^2, S^2) with S the level of a
-    thickness and 1e-8 h sqrt(G h) of the layer for a momentum, so that the floor of a momentum at
-    rest sits at about 1e-13 h sqrt(G h).  Momentum noise well under it (1e-19) keeps the linear
-    weights (omega_0 / d_0 = 1), while a momentum jump of 1e-10 h sqrt(G h) already switches them
-    (the oracle divides by the rounded sum of the weights, hence the 1e-12)."""
+    """Reading of the nonlinear weights' floor: epsilon = 1e-16 max(Q0^2, S^2) with S the level of a
+    thickness and 1e-8 h sqrt(G h) of the layer for a momentum, so that the weights of a momentum
+    at rest leave their linear values once it varies by about 1e-16 h sqrt(G h), and those of a
+    thickness once it varies by about 1e-8 of its level.  Momentum noise a thousand times under
+    that scale keeps the linear weights (omega_0 / d_0 = 1 to 1e-6), a momentum jump a thousand
+    times above it switches them; the same for a thickness at its own scale."""
     sc = w.lake_at_rest(8, seed=3)
     T = sc.n_tri
     mesh = o.Mesh.from_scenario(sc)
     rng = np.random.default_rng(11)
+    hc = 0.2 * np.sqrt(sc.G * 0.2)       # upper layer: h2 = 0.2
     W = sc.W0.copy()
-    W[[1, 2, 4, 5]] = 1e-19 * rng.standard_normal((4, T))
+    W[[1, 2]] = 1e-19 * hc * rng.standard_normal((2, T))
     for c in range(0, T, 5):
         _, _, r0 = mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)
-        assert np.abs(r0 - 1.0).max() < 1e-12, (c, r0)
+        assert np.abs(r0[[1, 2]] - 1.0).max() < 1e-6, (c, r0)
     cen = sc.node_xy[sc.tri].mean(axis=1)
     W = sc.W0.copy()
-    W[1] = np.where(cen[:, 0] < 0.5, 1e-10 * 0.2 * np.sqrt(sc.G * 0.2), 0.0)
+    W[1] = np.where(cen[:, 0] < 0.5, 1e-13 * hc, 0.0)
     r_min = min(mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)[2][1] for c in range(T))
     assert r_min < 0.9, r_min
+    # thickness h2 = 0.2: a step of 1e-11 of it keeps the linear weights, a step of 1e-5 does not
+    for amp, linear_kept in ((1e-11, True), (1e-5, False)):
+        W = sc.W0.copy()
+        W[0] = 0.2 * (1 + np.where(cen[:, 0] < 0.5, amp, 0.0))
+        r = min(mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)[2][0] for c in range(T))
+        assert (r > 1 - 1e-6) == linear_kept, (amp, r)
 
 
 # ------------------------------------------------------------------------------------------
@@ -548,20 +556,50 @@ def _e1_error(n, linear=False):
 
 
 def test_accuracy_table_magnitude_and_order():
-    """Sec. 4.1 accuracy test (table of L1 errors at t = 0.1): same magnitude as the printed
-    errors at h_re = 1/8 .. 1/32 and at least second-order convergence with the nonlinear
-    weights (which leave their linear values on this under-resolved Gaussian)."""
-    with open(os.path.join(GOLDEN, "accuracy_table.json")) as f:
-        gold = json.load(f)
-    errs = {"1/8": _e1_error(16), "1/16": _e1_error(32), "1/32": _e1_error(64)}
+    """Sec. 4.1 accuracy test (table of L1 errors at t = 0.1): at most 3 times and at least a
+    quarter of the printed errors at h_re = 1/8 .. 1/32 (the coarsest mesh here is more accurate
+    than the paper's), and the mean order over that range at least 1.9 with the
+    nonlinear weights (measured 1.98 for h1, 1.92 for h2), which leave their linear values at the
+    peak of this under-resolved Gaussian.  The paper's own figures (errors within a factor 2, mean
+    order 3.4) are the strict expected failure below."""
+    errs = _e1_table()
+    gold = _gold()
     for v, key in ((0, "h1"), (1, "h2")):
         for row, e in errs.items():
-            # the paper does not state its mesh or the L1 normalisation: agree within a factor 5
+            # the paper does not state its mesh or the L1 normalisation
             ref = gold["rows"][row][key]
-            assert ref / 5 < e[v] < 5 * ref, (key, row, e[v], ref)
-        # mean order over h_re = 1/8 .. 1/32
-        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.8
+            assert ref / 4 < e[v] < 3 * ref, (key, row, e[v], ref)
+        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) > 1.9
 
+
+@pytest.mark.xfail(strict=True, reason="the nonlinear weights cost the order on the accuracy problem: "
+                   "a mesh-scaled floor of the smoothness indicators (h^2 Q0^2) restores it (orders 3.4 and "
+                   "4.1) but then the neutral internal mode of the well-balance test at density ratio 1 "
+                   "grows from round-off by a factor 10 per unit time; the floor is kept at 1e-16 Q0^2")
+def test_accuracy_table_at_the_papers_figures():
+    """Sec. 4.1: errors within a factor 2 of the printed ones at h_re = 1/16 and 1/32 and a mean
+    order of at least 2.6 over 1/8 .. 1/32 (the paper prints 3.4)."""
+    errs = _e1_table()
+    gold = _gold()
+    for v, key in ((0, "h1"), (1, "h2")):
+        for row in ("1/16", "1/32"):
+            ref = gold["rows"][row][key]
+            assert ref / 2 < errs[row][v] < 2 * ref, (key, row, errs[row][v], ref)
+        assert 0.5 * math.log2(errs["1/8"][v] / errs["1/32"][v]) >= 2.6
+
+
+_E1_CACHE = {}
+
+
+def _e1_table():
+    if not _E1_CACHE:
+        _E1_CACHE.update({"1/8": _e1_error(16), "1/16": _e1_error(32), "1/32": _e1_error(64)})
+    return _E1_CACHE
+
+
+def _gold():
+    with open(os.path.join(GOLDEN, "accuracy_table.json")) as f:
+        return json.load(f)
 
 
 def test_accuracy_problem_with_linear_weights_is_near_fourth_order():

@@ -134,6 +134,14 @@ gks_status gks_state_time(const gks_state *st, int32_t s, double *t, double *dt)
 /* Per-layer mass sum |Omega_j| h_j in FP64 of scenario s (s = -1: all cells), mass[0] = upper
  * layer (h2), mass[1] = lower (h1); a deterministic device reduction; synchronising. */
 gks_status gks_state_mass(const gks_state *st, int32_t s, double mass[2]);
+/* For callers that cannot allocate device memory (code under graph capture preparation, tight
+ * serving loops, harnesses that forbid hipMalloc): gks_state_mass with the same arguments, result
+ * and kernel, whose 256 block partial sums go to a file-scope device array of 4 KiB (one copy per
+ * device, held until the process ends) instead of a buffer of the state.  It calls no hipMalloc,
+ * hipFree or other allocating routine.  The block grid strides over any number of
+ * cells, so no mesh exceeds the array.  Calls that overlap on one device (from several threads or
+ * streams) share that array and race; calls on one stream are ordered and do not. */
+gks_status gks_state_mass_noalloc(const gks_state *st, int32_t s, double mass[2]);
 
 /* Intermediate arrays of the last stage, for tests and inspection tools. */
 typedef enum {

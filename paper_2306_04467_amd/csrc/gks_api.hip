@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1367,5 +1368,68 @@ extern "C" gks_status gks_autotune(gks_state *s, int32_t reps, int32_t *chosen)
         if (r == GKS_OK && chosen)
             for (int k = 0; k < GKS_KERNEL_COUNT; k++) chosen[k] = s->bs[k];
         return r;
+    });
+}
+
+// ---------------------------------------------------------------------------------------------
+// allocation-free mass query: the block partial sums of k_mass_partial go to a file-scope device
+// array instead of the state's buffer
+
+namespace {
+
+constexpr int MASS_PARTS = 256;  // blocks of the mass reduction, one (upper, lower) pair each
+constexpr int MAX_DEVICES = 64;
+
+// 4 KiB on every device the library runs on, held until the process ends.  In host code the name
+// is only a stand-in for the symbol: kernels and copies use the address from scratch_of().
+static __device__ __align__(256) double scratch[2 * MASS_PARTS];
+
+std::mutex g_scratch_mu;
+double *g_scratch[MAX_DEVICES] = {};
+
+// this device's copy of scratch, looked up once per device with that device current
+gks_status scratch_of(int dev, double **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(GKS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        int prev = 0;
+        HIP_OK(hipGetDevice(&prev));
+        if (prev != dev) HIP_OK(hipSetDevice(dev));
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev != dev) (void)hipSetDevice(prev);
+        if (e != hipSuccess || !p) return fail(GKS_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch[dev];
+    return GKS_OK;
+}
+
+}  // namespace
+
+extern "C" gks_status gks_state_mass_noalloc(const gks_state *s, int32_t scen, double mass[2])
+{
+    return guarded([&]() -> gks_status {
+        if (!s || !mass || scen < -1 || scen >= s->md.S) return fail(GKS_EINVAL, "bad mass query");
+        double *part_d = nullptr;
+        gks_status st = scratch_of(s->mesh->device, &part_d);
+        if (st != GKS_OK) return st;
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t c0 = scen < 0 ? 0 : h.scell[scen], c1 = scen < 0 ? h.nt : h.scell[scen + 1];
+        // every block writes its pair, so nothing needs clearing; the grid strides over any number
+        // of cells, so every mesh fits the fixed-size scratch
+        hipLaunchKernelGGL(gks::k_mass_partial, dim3(MASS_PARTS), dim3(256), 0, s->stream, s->md,
+                           s->Wh[s->half ? 1 : 0], c0, c1, part_d);
+        HIP_OK(hipGetLastError());
+        double part[2 * MASS_PARTS];
+        HIP_OK(hipMemcpyAsync(part, part_d, sizeof(part), hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+        mass[0] = mass[1] = 0;
+        for (int b = 0; b < MASS_PARTS; b++) {
+            mass[0] += part[2 * b];
+            mass[1] += part[2 * b + 1];
+        }
+        return GKS_OK;
     });
 }

@@ -30,7 +30,7 @@ PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 # every entry point declared in include/gks.h
 SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_info", "gks_mesh_scenario",
            "gks_state_init", "gks_state_destroy", "gks_stage", "gks_step", "gks_batch_step", "gks_state_read",
-           "gks_state_time", "gks_state_mass", "gks_state_buffer", "gks_profile", "gks_profile_read",
+           "gks_state_time", "gks_state_mass", "gks_state_mass_noalloc", "gks_state_buffer", "gks_profile", "gks_profile_read",
            "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
            "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
            "gks_trainer_info", "gks_trainer_grad", "gks_trainer_fit", "gks_trainer_params", "gks_trainer_logits",
@@ -82,6 +82,7 @@ def load():
     lib.gks_state_read.argtypes = [_vp, _dp, _dp, _dp]
     lib.gks_state_time.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
     lib.gks_state_mass.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_state_mass_noalloc.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_buffer.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64]
     lib.gks_profile.argtypes = [_vp, ctypes.c_int32]
     lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, _i64p]

@@ -112,8 +112,9 @@ void gks_state_destroy(gks_state *st);
 /* One S2O4 stage (Sec. 3.3, Eq. SWE-fully-discrete).  stage = 0 turns W^n into W^{n+1/2} and
  * stores what stage 1 needs; stage = 1 turns W^{n+1/2} into W^{n+1}.  Stages must alternate
  * 0, 1, 0, ... (GKS_EINVAL otherwise).  dt: host pointer to the step size for stage 0 (single
- * scenario only), or NULL to use the CFL step computed on the device; must be NULL for stage 1
- * (the step size is reused). */
+ * scenario only; clipped on the device so that t never passes t_end, like the CFL step), or NULL
+ * to use the CFL step computed on the device; must be NULL for stage 1 (the step size is
+ * reused). */
 gks_status gks_stage(gks_state *st, int32_t stage, const double *dt);
 /* n_steps full steps, every scenario with its own CFL time step computed on the device (no host
  * synchronisation).  A scenario that has reached its t_end is left unchanged by later steps.  If
@@ -142,6 +143,28 @@ gks_status gks_state_mass(const gks_state *st, int32_t s, double mass[2]);
  * cells, so no mesh exceeds the array.  Calls that overlap on one device (from several threads or
  * streams) share that array and race; calls on one stream are ordered and do not. */
 gks_status gks_state_mass_noalloc(const gks_state *st, int32_t s, double mass[2]);
+
+/* Non-finite detection (a diagnostic of the cell update, Sec. 3.3): every cell update records on
+ * the device, without a host round trip, the smallest cell index whose new state has a
+ * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B).  gks_state_check
+ * synchronises and returns GKS_ENONFINITE with *first_bad = that cell (index into the
+ * concatenated cells of a batch), or GKS_OK with *first_bad = -1 (first_bad may be NULL).  The
+ * synchronising calls gks_state_read, gks_state_time, gks_state_mass and gks_step with dt_last
+ * return GKS_ENONFINITE too, after filling their outputs.  The flag stays set until a checkpoint
+ * taken before the failure is loaded. */
+gks_status gks_state_check(const gks_state *st, int64_t *first_bad);
+
+/* Checkpoint / restart.  gks_state_checkpoint_size gives the byte count of a checkpoint of this
+ * state; gks_state_save writes the raw device state (h2 and h1 + B in FP64, momenta and gradients
+ * in the state's precision, ghost cells, each scenario's time and last step, the non-finite flag)
+ * behind a small header into the caller's host buffer `blob` (synchronising; GKS_EINVAL between
+ * stage 0 and stage 1 or if `bytes` is too small).  gks_state_load restores such a checkpoint into
+ * a state of the same mesh and precision (GKS_EINVAL otherwise), so that k steps, a checkpoint,
+ * a load and k more steps give the same bits as 2k steps.  Indicator, autotuner and graph settings
+ * are not part of a checkpoint. */
+gks_status gks_state_checkpoint_size(const gks_state *st, int64_t *bytes);
+gks_status gks_state_save(const gks_state *st, void *blob, int64_t bytes);
+gks_status gks_state_load(gks_state *st, const void *blob, int64_t bytes);
 
 /* Intermediate arrays of the last stage, for tests and inspection tools. */
 typedef enum {

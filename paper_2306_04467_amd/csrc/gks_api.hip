@@ -112,6 +112,7 @@ struct gks_state {
     double *scal = nullptr, *part = nullptr, *chi = nullptr, *tend = nullptr;
     uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
     uint8_t *need = nullptr;    // cells whose plane gradient of the force model is used
+    unsigned long long *bad = nullptr;  // first cell updated to a non-finite / non-positive state
     // threads per block of the edge and cell kernels (per kernel class), chosen by gks_autotune
     int bs[GKS_KERNEL_COUNT] = {256, 192, 256, 256, 256, 256, 256, 256};
     int nparts = 0;
@@ -344,6 +345,35 @@ gks_status ensure_f32(gks_mesh *m)
     return GKS_OK;
 }
 
+// checkpoint: a fixed header, then the raw device state (levels and thicknesses in FP64, momenta
+// and gradients in the state's precision, ghosts included), the per-scenario (dt, t) pairs and
+// the non-finite flag
+struct CkptHeader {
+    uint32_t magic, version;
+    int32_t prec, S;
+    int64_t T, NG;
+};
+constexpr uint32_t CKPT_MAGIC = 0x474b5331u;  // "GKS1"
+
+int64_t ckpt_bytes(const gks_state *s)
+{
+    const gks::HostMesh &h = s->mesh->host;
+    const int64_t TG = h.nt + h.ng, rs = s->prec == GKS_FP64 ? 8 : 4;
+    return (int64_t)sizeof(CkptHeader) + 2 * TG * 8 + 16 * TG * rs + 2 * (int64_t)h.S * 8 + 8;
+}
+
+// the non-finite flag of a state whose stream has been synchronised: GKS_ENONFINITE naming the
+// first bad cell, or GKS_OK
+gks_status check_bad(const gks_state *s, int64_t *first)
+{
+    unsigned long long v = ~0ull;
+    HIP_OK(hipMemcpy(&v, s->bad, 8, hipMemcpyDeviceToHost));
+    if (first) *first = v == ~0ull ? -1 : (int64_t)v;
+    if (v == ~0ull) return GKS_OK;
+    return fail(GKS_ENONFINITE, "non-finite value or non-positive layer thickness after an update, first at cell " +
+                                    std::to_string(v));
+}
+
 template <typename R>
 void to_real(const std::vector<double> &src, std::vector<unsigned char> &dst)
 {
@@ -512,7 +542,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                     {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
                     {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 6 * uE * 8}, {&s->eom, 24 * uE * rs},
                     {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
-                    {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}};
+                    {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}, {(void **)&s->bad, 8}};
         for (auto &b : bufs) {
             hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
             if (e != hipSuccess) {
@@ -534,6 +564,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         s->p.chi = s->chi;
         s->p.t_end = s->tend;
         s->p.scal = s->scal;
+        s->p.bad = s->bad;
         std::vector<unsigned char> bm, bg;
         if (prec == GKS_FP64) {
             to_real<double>(wm, bm);
@@ -550,6 +581,8 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
             HIP_OK(hipMemcpy(s->chi, chi.data(), S * 8, hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(s->tend, tend.data(), S * 8, hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(s->scal, scal.data(), 2 * S * 8, hipMemcpyHostToDevice));
+            const unsigned long long none = ~0ull;
+            HIP_OK(hipMemcpy(s->bad, &none, 8, hipMemcpyHostToDevice));
             HIP_OK(hipMemset(s->Wh[1], 0, 2 * TG * 8));
             HIP_OK(hipMemset(s->Wm[1], 0, 4 * TG * rs));
             HIP_OK(hipMemset(s->gW[1], 0, 12 * TG * rs));
@@ -651,6 +684,7 @@ gks_status gks_step(gks_state *s, int32_t n_steps, double *dt_last)
             HIP_OK(hipMemcpyAsync(sc, s->scal, sizeof(sc), hipMemcpyDeviceToHost, s->stream));
             HIP_OK(hipStreamSynchronize(s->stream));
             *dt_last = sc[0];
+            return check_bad(s, nullptr);
         }
         return GKS_OK;
     });
@@ -722,7 +756,7 @@ gks_status gks_state_read(const gks_state *s, double *W, double *gradW, double *
                         gradW[(2 * v + d) * T + c] = v == 3 ? g[(2 * v + d) * TG + c] - h.gB[d * T + c] : g[(2 * v + d) * TG + c];
         }
         if (t) return gks_state_time(s, 0, t, nullptr);
-        return GKS_OK;
+        return check_bad(s, nullptr);
     });
 }
 
@@ -735,7 +769,7 @@ gks_status gks_state_time(const gks_state *s, int32_t scen, double *t, double *d
         HIP_OK(hipMemcpy(sc, s->scal + 2 * scen, sizeof(sc), hipMemcpyDeviceToHost));
         if (t) *t = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
         if (dt) *dt = sc[0];
-        return GKS_OK;
+        return check_bad(s, nullptr);
     });
 }
 
@@ -757,6 +791,78 @@ gks_status gks_state_mass(const gks_state *s, int32_t scen, double mass[2])
             mass[0] += part[2 * b];
             mass[1] += part[2 * b + 1];
         }
+        return check_bad(s, nullptr);
+    });
+}
+
+gks_status gks_state_check(const gks_state *s, int64_t *first_bad)
+{
+    return guarded([&]() -> gks_status {
+        if (!s) return fail(GKS_EINVAL, "null state");
+        HIP_OK(hipStreamSynchronize(s->stream));
+        return check_bad(s, first_bad);
+    });
+}
+
+gks_status gks_state_checkpoint_size(const gks_state *s, int64_t *bytes)
+{
+    return guarded([&]() -> gks_status {
+        if (!s || !bytes) return fail(GKS_EINVAL, "null argument");
+        *bytes = ckpt_bytes(s);
+        return GKS_OK;
+    });
+}
+
+gks_status gks_state_save(const gks_state *s, void *blob, int64_t bytes)
+{
+    return guarded([&]() -> gks_status {
+        if (!s || !blob) return fail(GKS_EINVAL, "null argument");
+        if (s->half) return fail(GKS_EINVAL, "a checkpoint cannot be taken between stage 0 and stage 1");
+        if (bytes < ckpt_bytes(s)) return fail(GKS_EINVAL, "checkpoint buffer too small");
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t TG = h.nt + h.ng, rs = s->prec == GKS_FP64 ? 8 : 4;
+        CkptHeader hd{CKPT_MAGIC, 1u, s->prec, h.S, h.nt, h.ng};
+        unsigned char *p = static_cast<unsigned char *>(blob);
+        std::memcpy(p, &hd, sizeof(hd));
+        p += sizeof(hd);
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(p, s->Wh[0], 2 * TG * 8, hipMemcpyDeviceToHost));
+        p += 2 * TG * 8;
+        HIP_OK(hipMemcpy(p, s->Wm[0], 4 * TG * rs, hipMemcpyDeviceToHost));
+        p += 4 * TG * rs;
+        HIP_OK(hipMemcpy(p, s->gW[0], 12 * TG * rs, hipMemcpyDeviceToHost));
+        p += 12 * TG * rs;
+        HIP_OK(hipMemcpy(p, s->scal, 2 * (size_t)h.S * 8, hipMemcpyDeviceToHost));
+        p += 2 * (size_t)h.S * 8;
+        HIP_OK(hipMemcpy(p, s->bad, 8, hipMemcpyDeviceToHost));
+        return GKS_OK;
+    });
+}
+
+gks_status gks_state_load(gks_state *s, const void *blob, int64_t bytes)
+{
+    return guarded([&]() -> gks_status {
+        if (!s || !blob) return fail(GKS_EINVAL, "null argument");
+        if (bytes < ckpt_bytes(s)) return fail(GKS_EINVAL, "checkpoint too short for this state");
+        const gks::HostMesh &h = s->mesh->host;
+        CkptHeader hd;
+        std::memcpy(&hd, blob, sizeof(hd));
+        if (hd.magic != CKPT_MAGIC || hd.version != 1u) return fail(GKS_EINVAL, "not a checkpoint of this library");
+        if (hd.prec != s->prec || hd.S != h.S || hd.T != h.nt || hd.NG != h.ng)
+            return fail(GKS_EINVAL, "checkpoint of another mesh or precision");
+        const int64_t TG = h.nt + h.ng, rs = s->prec == GKS_FP64 ? 8 : 4;
+        const unsigned char *p = static_cast<const unsigned char *>(blob) + sizeof(hd);
+        HIP_OK(hipStreamSynchronize(s->stream));
+        HIP_OK(hipMemcpy(s->Wh[0], p, 2 * TG * 8, hipMemcpyHostToDevice));
+        p += 2 * TG * 8;
+        HIP_OK(hipMemcpy(s->Wm[0], p, 4 * TG * rs, hipMemcpyHostToDevice));
+        p += 4 * TG * rs;
+        HIP_OK(hipMemcpy(s->gW[0], p, 12 * TG * rs, hipMemcpyHostToDevice));
+        p += 12 * TG * rs;
+        HIP_OK(hipMemcpy(s->scal, p, 2 * (size_t)h.S * 8, hipMemcpyHostToDevice));
+        p += 2 * (size_t)h.S * 8;
+        HIP_OK(hipMemcpy(s->bad, p, 8, hipMemcpyHostToDevice));
+        s->half = 0;
         return GKS_OK;
     });
 }

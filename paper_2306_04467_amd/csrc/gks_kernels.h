@@ -52,6 +52,8 @@ struct Phys {
     const double *chi;    // [S] density ratio
     const double *t_end;  // [S]
     double *scal;         // [2S] per scenario: dt of the current step, time at its end
+    unsigned long long *bad;  // smallest cell whose updated state is non-finite or has a layer
+                              // thickness <= 0 (all ones: none), kept until the state is reloaded
 };
 
 // relative floor of the smoothness indicators of the nonlinear reconstruction, above the
@@ -1205,6 +1207,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         // the state carries grad(eta1) = grad(h1) + grad(B)
         GG[3][0] += gBx;
         GG[3][1] += gBy;
+        bool ok = true;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
             const double w = (v == 0) ? Whin[c] : (v == 3) ? Whin[TG + c] : (double)Wmin[mom_slot(v) * TG + c];
@@ -1213,6 +1216,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = ws;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)ws;
+            ok = ok && (v == 0 ? ws > 0 : v == 3 ? ws - m.Bbar[c] > 0 : isfinite(ws));
             Wc[v * T + c] = w + dt * L[v] + (dt * dt / 6.0) * Lt[v];
 #pragma unroll
             for (int d = 0; d < 2; d++) {
@@ -1220,7 +1224,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Gc[(2 * v + d) * T + c] = (R)GG[v][d];
             }
         }
+        if (!ok) atomicMin(p.bad, (unsigned long long)c);
     } else {
+        bool ok = true;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
             const double wn = Wc[v * T + c] + (dt * dt / 3.0) * Lt[v];
@@ -1228,10 +1234,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = wn;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)wn;
+            ok = ok && (v == 0 ? wn > 0 : v == 3 ? wn - m.Bbar[c] > 0 : isfinite(wn));
 #pragma unroll
             for (int d = 0; d < 2; d++)
                 gWout[(2 * v + d) * TG + c] = (R)((double)Gc[(2 * v + d) * T + c] + dt * GGt[v][d]);
         }
+        if (!ok) atomicMin(p.bad, (unsigned long long)c);
     }
 }
 
@@ -1284,9 +1292,13 @@ __device__ inline void set_step(const MeshDev &m, const Phys &p, int s, double s
 {
     double dt = p.cfl * m.sdxmin[s] / smax;
     const double t = p.scal[2 * s + 1];
-    if (t + dt > p.t_end[s]) dt = p.t_end[s] - t;
+    double tn = t + dt;
+    if (tn > p.t_end[s]) {  // the last step ends exactly at t_end; none ever goes back
+        dt = fmax(0.0, p.t_end[s] - t);
+        tn = fmax(t, p.t_end[s]);
+    }
     p.scal[2 * s] = dt;
-    p.scal[2 * s + 1] = t + dt;
+    p.scal[2 * s + 1] = tn;
 }
 
 __global__ void __launch_bounds__(DT_BLOCK) k_dt_final(MeshDev m, Phys p, const double *__restrict__ part, int nparts)
@@ -1323,11 +1335,18 @@ __global__ void __launch_bounds__(64) k_dt_scenario(MeshDev m, Phys p, const dou
     if (threadIdx.x == 0) set_step(m, p, s, v);
 }
 
+// an explicit step of a single scenario, clipped like the CFL step so that t never passes t_end
 __global__ void k_set_dt(Phys p, double dt)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double t = p.scal[1];
+        double tn = t + dt;
+        if (tn > p.t_end[0]) {
+            dt = fmax(0.0, p.t_end[0] - t);
+            tn = fmax(t, p.t_end[0]);
+        }
         p.scal[0] = dt;
-        p.scal[1] += dt;
+        p.scal[1] = tn;
     }
 }
 

@@ -30,7 +30,8 @@ PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 # every entry point declared in include/gks.h
 SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_info", "gks_mesh_scenario",
            "gks_state_init", "gks_state_destroy", "gks_stage", "gks_step", "gks_batch_step", "gks_state_read",
-           "gks_state_time", "gks_state_mass", "gks_state_mass_noalloc", "gks_state_buffer", "gks_profile", "gks_profile_read",
+           "gks_state_time", "gks_state_mass", "gks_state_mass_noalloc", "gks_state_check",
+           "gks_state_checkpoint_size", "gks_state_save", "gks_state_load", "gks_state_buffer", "gks_profile", "gks_profile_read",
            "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
            "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
            "gks_trainer_info", "gks_trainer_grad", "gks_trainer_fit", "gks_trainer_params", "gks_trainer_logits",
@@ -83,6 +84,10 @@ def load():
     lib.gks_state_time.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
     lib.gks_state_mass.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_mass_noalloc.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_state_check.argtypes = [_vp, _i64p]
+    lib.gks_state_checkpoint_size.argtypes = [_vp, _i64p]
+    lib.gks_state_save.argtypes = [_vp, _vp, ctypes.c_int64]
+    lib.gks_state_load.argtypes = [_vp, _vp, ctypes.c_int64]
     lib.gks_state_buffer.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int64]
     lib.gks_profile.argtypes = [_vp, ctypes.c_int32]
     lib.gks_profile_read.argtypes = [_vp, ctypes.c_int32, _dp, _i64p]
@@ -259,6 +264,26 @@ class State:
         m = np.zeros(2)
         _check(load().gks_state_mass(self._h, int(s), _d(m)))
         return m
+
+    def check(self):
+        """First cell updated to a non-finite or non-positive-thickness state, or -1 (no raise)."""
+        first = ctypes.c_int64(-1)
+        code = load().gks_state_check(self._h, ctypes.byref(first))
+        if code not in (GKS_OK, GKS_ENONFINITE):
+            _check(code)
+        return first.value
+
+    def save(self):
+        """Checkpoint of the state as bytes (see gks_state_save)."""
+        n = ctypes.c_int64()
+        _check(load().gks_state_checkpoint_size(self._h, ctypes.byref(n)))
+        blob = np.zeros(n.value, dtype=np.uint8)
+        _check(load().gks_state_save(self._h, blob.ctypes.data_as(_vp), blob.nbytes))
+        return blob.tobytes()
+
+    def load(self, blob):
+        buf = np.frombuffer(blob, dtype=np.uint8).copy()
+        _check(load().gks_state_load(self._h, buf.ctypes.data_as(_vp), buf.nbytes))
 
     def buffer(self, name):
         """Intermediate array of the last stage (see gks_buffer in include/gks.h)."""

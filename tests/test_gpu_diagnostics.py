@@ -1,0 +1,80 @@
+"""Diagnostics of the C ABI on the GPU: the device-side non-finite flag of the cell update and
+checkpoint / restart.
+
+* An explicit stage-0 step far beyond the CFL limit (passed through gks_stage, nothing written
+  into the state directly) drives layer thicknesses negative; the flag must name the smallest
+  such cell, which the oracle's own half step with the same size identifies independently, and
+  the synchronising calls must report GKS_ENONFINITE.
+* k steps, a checkpoint, a load into a fresh state and k more steps give the bits of 2k steps, in
+  both precisions; a checkpoint does not load into a state of another mesh."""
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gks():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_04467_amd as g
+
+    g.load()
+    return g
+
+
+def _bad_cells(W):
+    return np.nonzero(~np.isfinite(W).all(axis=0) | (W[0] <= 0) | (W[3] <= 0))[0]
+
+
+def test_non_finite_flag_names_the_first_bad_cell(gks):
+    sc = w.lake_at_rest(10, perturb=0.15, seed=9)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc)
+    assert st.check() == -1
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    dt = 60 * o.dt(om, p, sc.W0)                      # far beyond the CFL step
+    Wr, _ = o.step(om, p, dt, sc.W0, sc.gradW0, nstages=1)
+    bad_ref = _bad_cells(Wr)
+    assert bad_ref.size > 0
+    h = np.minimum(Wr[0], Wr[3])
+    assert np.all(np.abs(h[np.isfinite(h)]) > 1e-6)   # no thickness near the decision
+    st.stage(0, dt)
+    first = st.check()
+    print(f"[diag] oracle bad cells {bad_ref[:8]} ..., flag {first}", flush=True)
+    assert first == bad_ref[0]
+    with pytest.raises(gks.GksError) as ei:
+        st.read()
+    assert ei.value.code == gks.GKS_ENONFINITE
+    assert str(first) in str(ei.value)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_checkpoint_restart_is_bitwise(gks, precision):
+    sc = w.lake_at_rest(40, perturb=1e-2, seed=12)
+    m = gks.Mesh.from_scenario(sc)
+    a = gks.State.from_scenario(m, sc, precision=precision)
+    a.step(30)
+    Wa, gWa, ta = a.read()
+    b = gks.State.from_scenario(m, sc, precision=precision)
+    b.step(15)
+    blob = b.save()
+    c = gks.State.from_scenario(m, sc, precision=precision)
+    c.load(blob)
+    c.step(15)
+    Wc, gWc, tc = c.read()
+    assert ta == tc and np.array_equal(Wa, Wc) and np.array_equal(gWa, gWc)
+    # the checkpoint is of this mesh and precision only, and never taken between the stages
+    other = w.lake_at_rest(12, perturb=1e-2, seed=12)
+    d = gks.State.from_scenario(gks.Mesh.from_scenario(other), other, precision=precision)
+    with pytest.raises(gks.GksError):
+        d.load(blob)
+    c.stage(0)
+    with pytest.raises(gks.GksError):
+        c.save()

@@ -138,3 +138,23 @@ def test_mixed_precision_full_size_step(gks):
             err.append((a * np.abs(W[v] - Wr[v])).sum() / den)
     print(f"   rel-L1 {max(err):.2e}", flush=True)
     assert max(err) <= 1e-5, err
+
+
+def test_explicit_step_past_t_end_is_clipped(gks):
+    """An explicit stage-0 step that would pass t_end is clipped to it, and later CFL steps are
+    empty (step size 0, state unchanged), never negative."""
+    sc = w.lake_at_rest(8, perturb=1e-2, seed=4)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, t_end=0.01)
+    st.stage(0, 0.004)
+    st.stage(1)
+    st.stage(0, 0.05)             # 0.004 + 0.05 passes t_end = 0.01
+    st.stage(1)
+    t, dt = st.time()
+    assert t == 0.01 and abs(dt - 0.006) < 1e-15, (t, dt)
+    W1, gW1, _ = st.read()
+    assert st.step(3, want_dt=True) == 0.0
+    st.stage(0, 0.02)
+    st.stage(1)
+    W2, gW2, t2 = st.read()
+    assert t2 == 0.01 and np.array_equal(W1, W2) and np.array_equal(gW1, gW2)

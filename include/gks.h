@@ -223,7 +223,7 @@ gks_status gks_profile_read(gks_state *st, int32_t kernel, double *total_ms, int
  * size of the layer's momentum variation log10((sm + 1e-12 a) / a) / 4, sm the largest stencil
  * difference of its two momentum components, a = h sqrt(G h) (X[36] lower, X[37] upper); the 3
  * face neighbours' areas over |Omega_c| (X[38..40]) and the 3 edge lengths over hs (X[41..43]).
- * Inference uses bf16 operands with float accumulation (v_mfma_f32_32x32x8_bf16); a cell is
+ * Inference uses bf16 operands with float accumulation (v_mfma_f32_32x32x16_bf16); a cell is
  * skipped when its logit exceeds the threshold.
  * ------------------------------------------------------------------------------------------ */
 

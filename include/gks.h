@@ -56,7 +56,11 @@ typedef enum {
 
 typedef enum {
     GKS_BC_WALL = 0,      /* every boundary edge is a reflecting wall (mirror ghost cells) */
-    GKS_BC_PERIODIC = 1   /* boundary edges of [0,Lx] x [0,Ly] are paired by translation */
+    GKS_BC_PERIODIC = 1,  /* boundary edges of [0,Lx] x [0,Ly] are paired by translation */
+    GKS_BC_FREE = 2       /* every boundary edge is free (zero-gradient, transmissive): the ghost
+                             beyond it is the mirror image of the cell with every component,
+                             momentum included, extended evenly, and mass crosses it (the free
+                             boundary of the paper's accuracy test, Sec. 4.1) */
 } gks_bc;
 
 typedef enum {

@@ -125,17 +125,21 @@ def _f64(a):
 class Mesh:
     """Oracle mesh: connectivity, stencils and least-squares matrices built in plain C."""
 
-    def __init__(self, node_xy, tri, node_B=None, periodic_L=None):
+    BC = {"wall": 0, "periodic": 1, "free": 2}
+
+    def __init__(self, node_xy, tri, node_B=None, periodic_L=None, boundary=None):
         lib = load()
         self.node_xy = _f64(node_xy)
         self.tri = np.ascontiguousarray(tri, dtype=np.int32)
         self.node_B = _f64(node_B if node_B is not None else np.zeros(self.node_xy.shape[0]))
         self.n_tri = int(self.tri.shape[0])
         per = periodic_L is not None
+        if boundary is None:
+            boundary = "periodic" if per else "wall"
         Lx, Ly = (periodic_L if per else (0.0, 0.0))
         self._h = lib.om_mesh_new(_d(self.node_xy), self.node_xy.shape[0],
                                   self.tri.ctypes.data_as(_ip), self.n_tri, _d(self.node_B),
-                                  int(per), float(Lx), float(Ly))
+                                  self.BC[boundary], float(Lx), float(Ly))
         if not self._h:
             raise ValueError("oracle rejected the mesh")
         self.n_edges = lib.om_mesh_n_edges(self._h)
@@ -147,7 +151,8 @@ class Mesh:
 
     @classmethod
     def from_scenario(cls, sc):
-        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None)
+        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None,
+                   boundary=sc.boundary)
 
     def geometry(self):
         a, x, y = (np.zeros(self.n_tri) for _ in range(3))

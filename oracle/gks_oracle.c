@@ -95,6 +95,7 @@ struct om_mesh {
     double *xy, *B;
     int *tri;
     int periodic;
+    int free_bc; /* boundary edges are free (zero-gradient) instead of walls */
     double Lx, Ly;
     /* cells */
     double *area, *cx, *cy, *Bbar, *Bx, *By, *dX;
@@ -267,7 +268,8 @@ static void nb_image(const om_mesh *m, int c, int k, int *nc, amap *T, int *back
     int e = m->c_edge[3 * c + k];
     if (m->c_side[3 * c + k] == 0) {
         int r = m->e_cell[2 * e + 1];
-        if (r < 0) { /* reading: a wall neighbour is the mirror image of the cell itself */
+        if (r < 0) { /* reading: beyond a wall or a free boundary edge lies the mirror image of the
+                      * cell itself (its state seen through image_state) */
             double p[2], q[2];
             vtx(m, c, k, p);
             vtx(m, c, k + 1, q);
@@ -363,13 +365,16 @@ static void build_lsq(om_mesh *m, int c)
 }
 
 om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, const double *node_B,
-                     int periodic, double Lx, double Ly)
+                     int bc, double Lx, double Ly)
 {
+    if (bc < 0 || bc > 2) return NULL;
+    const int periodic = bc == 1;
     quad_init();
     om_mesh *m = (om_mesh *)calloc(1, sizeof(om_mesh));
     m->nn = nn;
     m->nt = nt;
     m->periodic = periodic;
+    m->free_bc = bc == 2;
     m->Lx = Lx;
     m->Ly = Ly;
     m->xy = (double *)malloc(sizeof(double) * 2 * nn);
@@ -615,9 +620,11 @@ void om_lsq_matrix(const om_mesh *m, int c, double *M)
 
 /* variables of cell n seen through the map R (linear part of its image map): six averages in the
  * reconstruction's variable set (eta1 = h1 + B replaces h1, Sec. 3.2 water-level technique) and
- * their gradients [6][2].  Scalars keep their value; momenta rotate with R; gradients of scalars
- * rotate with R, gradients of momenta as R (grad m) R^T. */
-static void image_state(const om_mesh *m, int n, const double R[2][2], const double *W,
+ * their gradients [6][2].  Scalars keep their value; gradients of scalars rotate with R.  With
+ * vec != 0 momenta rotate with R and their gradients as R (grad m) R^T (walls: the momentum is a
+ * vector that reflects); with vec = 0 (free boundaries) every momentum component extends evenly
+ * like a scalar: value kept, gradient (grad m) R^T. */
+static void image_state(const om_mesh *m, int n, const double R[2][2], int vec, const double *W,
                         const double *gW, double *q, double *gq)
 {
     int T = m->nt;
@@ -632,17 +639,19 @@ static void image_state(const om_mesh *m, int n, const double R[2][2], const dou
     g[3][1] += m->By[n];
     for (int layer = 0; layer < 2; layer++) {
         int o = 3 * layer;
+        const double I[2][2] = {{1, 0}, {0, 1}};
+        const double(*V)[2] = vec ? R : I; /* the map of momentum vectors */
         double mv[2] = {w[o + 1], w[o + 2]}, rm[2];
-        map_vec(R, mv, rm);
+        map_vec(V, mv, rm);
         q[o] = w[o];
         q[o + 1] = rm[0];
         q[o + 2] = rm[1];
         map_vec(R, g[o], gq + 2 * o);
-        /* grad of momentum: Gm[a][d] = d m_a / d x_d */
+        /* grad of momentum: Gm[a][d] = d m_a / d x_d  ->  V Gm R^T */
         double Gm[2][2] = {{g[o + 1][0], g[o + 1][1]}, {g[o + 2][0], g[o + 2][1]}};
         double RG[2][2], RGRt[2][2];
         for (int i = 0; i < 2; i++)
-            for (int j = 0; j < 2; j++) RG[i][j] = R[i][0] * Gm[0][j] + R[i][1] * Gm[1][j];
+            for (int j = 0; j < 2; j++) RG[i][j] = V[i][0] * Gm[0][j] + V[i][1] * Gm[1][j];
         for (int i = 0; i < 2; i++)
             for (int j = 0; j < 2; j++) RGRt[i][j] = RG[i][0] * R[j][0] + RG[i][1] * R[j][1];
         gq[2 * (o + 1)] = RGRt[0][0];
@@ -685,7 +694,7 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
     for (int l = 0; l < NS; l++) {
         int n = m->st_cell[NS * c + l];
         const amap *T = &m->st_map[NS * c + l];
-        image_state(m, n, T->R, W, gW, q[l], &gq[l][0][0]);
+        image_state(m, n, T->R, !m->free_bc, W, gW, q[l], &gq[l][0][0]);
         double cn[2] = {m->cx[n], m->cy[n]};
         map_point(T, cn, cen[l]);
     }
@@ -1070,23 +1079,26 @@ double om_dt(const om_mesh *m, const om_params *p, const double *W)
 /* ----------------------------------------------------------------------------------------- */
 /* one stage of the spatial operator                                                          */
 
-/* mirror of a Gauss-point record across the wall with unit normal n (R = I - 2 n n^T) */
-static void mirror_record(const double *n, const double *val, const double *grad, double *mval,
+/* mirror of a Gauss-point record across the boundary edge with unit normal n (R = I - 2 n n^T):
+ * vec != 0 a wall (momentum reflected), vec = 0 a free boundary (every component even) */
+static void mirror_record(const double *n, int vec, const double *val, const double *grad, double *mval,
                           double *mgrad)
 {
     double R[2][2] = {{1 - 2 * n[0] * n[0], -2 * n[0] * n[1]}, {-2 * n[0] * n[1], 1 - 2 * n[1] * n[1]}};
+    const double I[2][2] = {{1, 0}, {0, 1}};
+    const double(*V)[2] = vec ? R : I;
     for (int layer = 0; layer < 2; layer++) {
         int o = 3 * layer;
         mval[o] = val[o];
         double mv[2] = {val[o + 1], val[o + 2]}, rm[2];
-        map_vec(R, mv, rm);
+        map_vec(V, mv, rm);
         mval[o + 1] = rm[0];
         mval[o + 2] = rm[1];
         map_vec(R, grad + 2 * o, mgrad + 2 * o);
         double Gm[2][2] = {{grad[2 * (o + 1)], grad[2 * (o + 1) + 1]}, {grad[2 * (o + 2)], grad[2 * (o + 2) + 1]}};
         double RG[2][2];
         for (int i = 0; i < 2; i++)
-            for (int j = 0; j < 2; j++) RG[i][j] = R[i][0] * Gm[0][j] + R[i][1] * Gm[1][j];
+            for (int j = 0; j < 2; j++) RG[i][j] = V[i][0] * Gm[0][j] + V[i][1] * Gm[1][j];
         for (int i = 0; i < 2; i++)
             for (int j = 0; j < 2; j++) mgrad[2 * (o + 1 + i) + j] = RG[i][0] * R[j][0] + RG[i][1] * R[j][1];
     }
@@ -1124,7 +1136,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
             if (R >= 0) {
                 memcpy(vr, REC_VAL(R, kR, 1 - g), sizeof(vr));
             } else {
-                mirror_record(n, vl, REC_GRD(L, kL, g), vr, gr);
+                mirror_record(n, !m->free_bc, vl, REC_GRD(L, kL, g), vr, gr);
             }
             double Bg = m->e_Bgp[2 * e + g];
             for (int f = 0; f < 2; f++) {
@@ -1194,7 +1206,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
                 memcpy(vs[1], REC_VAL(R, kR, 1 - g), sizeof(vs[1]));
                 memcpy(gs[1], REC_GRD(R, kR, 1 - g), sizeof(gs[1]));
             } else {
-                mirror_record(n, vs[0], gs[0], vs[1], gs[1]);
+                mirror_record(n, !m->free_bc, vs[0], gs[0], vs[1], gs[1]);
             }
             double Bg = m->e_Bgp[2 * e + g];
             double side[2][2][11]; /* [layer: 0 lower, 1 upper][side][...] */
@@ -1241,7 +1253,7 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
             for (int layer = 0; layer < 2; layer++) {
                 double F0[3], Ft[3], Wb[3], Wbt[3];
                 om_gks_point(side[layer][0], side[layer][1], G, dt, p->eps, p->eps_num, F0, Ft, Wb, Wbt);
-                if (R < 0) { /* reflecting wall: no mass crosses */
+                if (R < 0 && !m->free_bc) { /* reflecting wall: no mass crosses */
                     F0[0] = 0;
                     Ft[0] = 0;
                 }
@@ -1410,7 +1422,7 @@ void om_features(const om_mesh *m, double G, const double *W, const double *gW, 
         double q[NS][NV], gq[NS][NV][2];
         for (int l = 0; l < NS; l++) {
             int n = m->st_cell[NS * c + l];
-            image_state(m, n, m->st_map[NS * c + l].R, W, gW, q[l], &gq[l][0][0]);
+            image_state(m, n, m->st_map[NS * c + l].R, !m->free_bc, W, gW, q[l], &gq[l][0][0]);
         }
         double h = sqrt(2.0 * m->area[c]);
         double *x = X + (size_t)c * MLP_IN;

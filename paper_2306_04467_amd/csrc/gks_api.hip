@@ -401,7 +401,8 @@ gks_status gks_mesh_create(const double *node_xy, int64_t n_nodes, const int32_t
 {
     return guarded([&]() -> gks_status {
         if (!out || !node_xy || !tri || n_nodes <= 0 || n_tri <= 0) return fail(GKS_EINVAL, "bad mesh arguments");
-        if (bc != GKS_BC_WALL && bc != GKS_BC_PERIODIC) return fail(GKS_EINVAL, "unknown boundary kind");
+        if (bc != GKS_BC_WALL && bc != GKS_BC_PERIODIC && bc != GKS_BC_FREE)
+            return fail(GKS_EINVAL, "unknown boundary kind");
         if (n_tri > (int64_t)1 << 29) return fail(GKS_EINVAL, "mesh too large for 32-bit cell indices");
         *out = nullptr;
         gks_mesh *m = new gks_mesh();

@@ -125,23 +125,26 @@ __global__ void k_ghost_fill(MeshDev m, double *__restrict__ Wh, R *__restrict__
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= m.NG) return;
-    const int64_t TG = m.T + m.NG, s = m.gsrc[g], d = m.T + g;
-    const double a = m.gR[g], b = m.gR[m.NG + g], c = m.gR[2 * m.NG + g], e = m.gR[3 * m.NG + g];
+    const int64_t TG = m.T + m.NG, s = m.gsrc[g], d = m.T + g, NG = m.NG;
+    // R (a b; c e) maps gradient directions, V (va vb; vc ve) momentum vectors: V = R across a
+    // wall, V = I across a free boundary (each component extended evenly)
+    const double a = m.gR[g], b = m.gR[NG + g], c = m.gR[2 * NG + g], e = m.gR[3 * NG + g];
+    const double va = m.gR[4 * NG + g], vb = m.gR[5 * NG + g], vc = m.gR[6 * NG + g], ve = m.gR[7 * NG + g];
 #pragma unroll
     for (int l = 0; l < 2; l++) {  // l = 0 upper (paper components 0..2), 1 lower (3..5)
         const int o = 3 * l;
         Wh[l * TG + d] = Wh[l * TG + s];
         const double mx = Wm[(2 * l) * TG + s], my = Wm[(2 * l + 1) * TG + s];
-        Wm[(2 * l) * TG + d] = (R)(a * mx + b * my);
-        Wm[(2 * l + 1) * TG + d] = (R)(c * mx + e * my);
+        Wm[(2 * l) * TG + d] = (R)(va * mx + vb * my);
+        Wm[(2 * l + 1) * TG + d] = (R)(vc * mx + ve * my);
         const double hx = gW[(2 * o) * TG + s], hy = gW[(2 * o + 1) * TG + s];
         gW[(2 * o) * TG + d] = (R)(a * hx + b * hy);
         gW[(2 * o + 1) * TG + d] = (R)(c * hx + e * hy);
-        // momentum gradient G[i][j] = d m_i / d x_j  ->  R G R^T
+        // momentum gradient G[i][j] = d m_i / d x_j  ->  V G R^T
         const double g00 = gW[(2 * o + 2) * TG + s], g01 = gW[(2 * o + 3) * TG + s];
         const double g10 = gW[(2 * o + 4) * TG + s], g11 = gW[(2 * o + 5) * TG + s];
-        const double r00 = a * g00 + b * g10, r01 = a * g01 + b * g11;
-        const double r10 = c * g00 + e * g10, r11 = c * g01 + e * g11;
+        const double r00 = va * g00 + vb * g10, r01 = va * g01 + vb * g11;
+        const double r10 = vc * g00 + ve * g10, r11 = vc * g01 + ve * g11;
         gW[(2 * o + 2) * TG + d] = (R)(r00 * a + r01 * b);
         gW[(2 * o + 3) * TG + d] = (R)(r00 * c + r01 * e);
         gW[(2 * o + 4) * TG + d] = (R)(r10 * a + r11 * b);
@@ -620,10 +623,10 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, co
                 zr = qr.h[hq];
                 hr = f == 0 ? zr - Bg : zr;
                 unr = ((double)qr.q[mq] * nx + (double)qr.q[mq + 1] * ny) / hr;
-            } else {  // mirror state across the wall
+            } else {  // mirror state across a wall; the same state across a free boundary
                 zr = zl;
                 hr = hl;
-                unr = -unl;
+                unr = Rc == -1 ? -unl : unl;
             }
             // reading: xi is the kinetic fraction of particles moving from left to right
             const double lb = 2.0 / (p.G * (hl + hr));
@@ -1018,12 +1021,20 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
         q.pn = ax * nx + ay * ny;
         q.pt = ax * tx + ay * ty;
     }
-    if (Rc < 0) {  // wall: mirror image of the left side
+    if (Rc == -1) {  // wall: mirror image of the left side
         side[1] = side[0];
         side[1].U = -side[0].U;
         side[1].hn = -side[0].hn;
         side[1].en = -side[0].en;
         side[1].mnt = -side[0].mnt;
+        side[1].mtn = -side[0].mtn;
+        side[1].pn = -side[0].pn;
+        h64[1] = h64[0];
+    } else if (Rc < 0) {  // free boundary: every component extended evenly across the edge
+        side[1] = side[0];
+        side[1].hn = -side[0].hn;
+        side[1].en = -side[0].en;
+        side[1].mnn = -side[0].mnn;
         side[1].mtn = -side[0].mtn;
         side[1].pn = -side[0].pn;
         h64[1] = h64[0];
@@ -1033,7 +1044,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     const R gBn = lay == 0 ? gBx * nx + gBy * ny : R(0), gBt = lay == 0 ? gBx * tx + gBy * ty : R(0);
     R F0[3], Ft[3], Wb[3], Wbt[3];
     gks_point<R>(side[0], side[1], hbase, gBn, gBt, G, (R)p.eps, (R)p.eps_num, dt, F0, Ft, Wb, Wbt);
-    if (Rc < 0) {
+    if (Rc == -1) {  // no mass crosses a wall
         F0[0] = 0;
         Ft[0] = 0;
     }

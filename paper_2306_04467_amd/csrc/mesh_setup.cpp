@@ -154,7 +154,11 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
             err = "triangle references a node out of range";
             return 1;
         }
-    const bool periodic = (bc == 1);
+    const bool periodic = (bc == 1), freebc = (bc == 2);
+    if (bc < 0 || bc > 2) {
+        err = "unknown boundary kind";
+        return 1;
+    }
     if (periodic && (!L || !(L[0] > 0) || !(L[1] > 0))) {
         err = "periodic mesh needs positive periods";
         return 1;
@@ -373,6 +377,12 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
         gR.push_back(T.b);
         gR.push_back(T.c);
         gR.push_back(T.d);
+        // the map of the momentum vector: the same reflection across walls; none across free
+        // boundaries, where every component extends evenly like a scalar
+        gR.push_back(freebc ? 1.0 : T.a);
+        gR.push_back(freebc ? 0.0 : T.b);
+        gR.push_back(freebc ? 0.0 : T.c);
+        gR.push_back(freebc ? 1.0 : T.d);
         return (int32_t)(nt + g);
     };
     m.sten.assign(9 * nt, 0);
@@ -487,9 +497,12 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
         }
         for (int k = 0; k < 3; k++) m.igeo[(3 + k) * nt + c] = std::fabs(m.fl[k * nt + c]) * m.area[c] / m.hs[c];
     }
-    m.gR.assign(4 * std::max<int64_t>(m.ng, 1), 0);
+    m.gR.assign(8 * std::max<int64_t>(m.ng, 1), 0);
     for (int64_t g = 0; g < m.ng; g++)
-        for (int i = 0; i < 4; i++) m.gR[i * m.ng + g] = gR[4 * g + i];
+        for (int i = 0; i < 8; i++) m.gR[i * m.ng + g] = gR[8 * g + i];
+    if (freebc)
+        for (int64_t e = 0; e < ne; e++)
+            if (m.eR[e] < 0) m.eR[e] = -2;
     m.S = 1;
     m.scell = {0, nt};
     m.sdxmin = {m.dxmin};
@@ -555,7 +568,7 @@ HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts)
     o.eR.assign(E, 0);
     o.eslot.assign(E, 0);
     o.gsrc.assign(NG, 0);
-    o.gR.assign(4 * std::max<int64_t>(NG, 1), 0);
+    o.gR.assign(8 * std::max<int64_t>(NG, 1), 0);
     o.cscen.assign(T, 0);
     o.escen.assign(E, 0);
     o.scell.assign(o.S + 1, 0);
@@ -580,12 +593,12 @@ HostMesh concat_host_meshes(const std::vector<const HostMesh *> &parts)
         for (int64_t e = 0; e < p->ne; e++) {
             o.escen[eoff + e] = s;
             o.eL[eoff + e] = (int32_t)(p->eL[e] + coff);
-            o.eR[eoff + e] = p->eR[e] >= 0 ? (int32_t)(p->eR[e] + coff) : -1;
+            o.eR[eoff + e] = p->eR[e] >= 0 ? (int32_t)(p->eR[e] + coff) : p->eR[e];
             o.eslot[eoff + e] = p->eslot[e];
         }
         for (int64_t g = 0; g < p->ng; g++) {
             o.gsrc[goff + g] = (int32_t)(p->gsrc[g] + coff);
-            for (int i = 0; i < 4; i++) o.gR[i * NG + goff + g] = p->gR[i * p->ng + g];
+            for (int i = 0; i < 8; i++) o.gR[i * NG + goff + g] = p->gR[i * p->ng + g];
         }
         coff += p->nt;
         eoff += p->ne;

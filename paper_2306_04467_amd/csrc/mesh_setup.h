@@ -31,14 +31,17 @@ struct HostMesh {
     std::vector<double> igeo;        // [6][T] indicator geometry: area ratios of the 3 face
                                      // neighbours, then the 3 edge lengths over hs
     // edges
-    std::vector<int32_t> eL, eR;     // [E] left / right cell, eR = -1 on walls
+    std::vector<int32_t> eL, eR;     // [E] left / right cell, eR = -1 on walls, -2 on free
+                                     // (zero-gradient) boundaries
     std::vector<int32_t> eslot;      // [E] local edge index in L | (in R << 2)
     std::vector<double> en;          // [2][E] unit normal from L to R
     std::vector<double> eBgp;        // [2][E] bottom at the two Gauss points (L orientation)
     std::vector<double> egB;         // [2][E] single-valued bottom gradient at the edge
     // ghosts
     std::vector<int32_t> gsrc;       // [NG] source cell
-    std::vector<double> gR;          // [4][NG] orthogonal map applied to the source state
+    std::vector<double> gR;          // [8][NG] orthogonal map of the ghost image (applied to
+                                     // gradient directions), then the map of momentum vectors
+                                     // (the same across walls, the identity across free edges)
     // scenarios (independent meshes concatenated into one); a single mesh has S = 1 and
     // empty cscen / escen
     int32_t S = 1;
@@ -50,7 +53,8 @@ struct HostMesh {
 // Smallest sine of the angle between the two centroid offsets of a plane candidate.
 constexpr double PLANE_SINE_MIN = 0.2;
 
-// Returns 0 on success, otherwise fills err.  bc: 0 walls, 1 periodic on [0,L0]x[0,L1].
+// Returns 0 on success, otherwise fills err.  bc: 0 walls, 1 periodic on [0,L0]x[0,L1], 2 free
+// (zero-gradient) boundaries.
 int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt, const double *B,
                     int bc, const double *L, HostMesh &m, std::string &err);
 

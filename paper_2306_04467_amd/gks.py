@@ -23,7 +23,8 @@ _fp = ctypes.POINTER(ctypes.c_float)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
 
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EDEVICE, GKS_EMESH, GKS_ENONFINITE, GKS_EUNSUPPORTED = range(7)
-GKS_BC_WALL, GKS_BC_PERIODIC = 0, 1
+GKS_BC_WALL, GKS_BC_PERIODIC, GKS_BC_FREE = 0, 1, 2
+BOUNDARIES = {"wall": GKS_BC_WALL, "periodic": GKS_BC_PERIODIC, "free": GKS_BC_FREE}
 GKS_FP64, GKS_FP32_MIXED = 0, 1
 PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 
@@ -149,17 +150,18 @@ def current_stream():
 
 
 class Mesh:
-    def __init__(self, node_xy=None, tri=None, node_B=None, periodic_L=None, _handle=None):
+    def __init__(self, node_xy=None, tri=None, node_B=None, periodic_L=None, _handle=None, boundary=None):
         lib = load()
         if _handle is None:
             self.node_xy = _f64(node_xy)
             self.tri = np.ascontiguousarray(tri, dtype=np.int32)
             nB = None if node_B is None else _f64(node_B)
             per = None if periodic_L is None else _f64(periodic_L)
+            if boundary is None:
+                boundary = "periodic" if per is not None else "wall"
             h = _vp()
             _check(lib.gks_mesh_create(_d(self.node_xy), self.node_xy.shape[0], self.tri.ctypes.data_as(_i32p),
-                                       self.tri.shape[0], None if nB is None else _d(nB),
-                                       GKS_BC_PERIODIC if per is not None else GKS_BC_WALL,
+                                       self.tri.shape[0], None if nB is None else _d(nB), BOUNDARIES[boundary],
                                        None if per is None else _d(per), ctypes.byref(h)))
             _handle = h
         self._h = _handle
@@ -169,7 +171,8 @@ class Mesh:
 
     @classmethod
     def from_scenario(cls, sc):
-        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None)
+        return cls(sc.node_xy, sc.tri, sc.node_B, sc.periodic_L if sc.boundary == "periodic" else None,
+                   boundary=sc.boundary)
 
     @classmethod
     def batch(cls, meshes):

@@ -10,6 +10,9 @@ from .scenarios import (  # noqa: F401
     Scenario,
     smooth_periodic,
     accuracy_e1,
+    accuracy_e1_free,
+    uniform_stream,
+    free_outflow,
     lake_at_rest,
     well_balance_bump,
     dam_break,

@@ -26,7 +26,7 @@ class Scenario:
     node_xy: np.ndarray          # [N, 2] f64
     tri: np.ndarray              # [T, 3] i32, counter-clockwise
     node_B: np.ndarray           # [N] f64 bottom at nodes (piecewise linear)
-    boundary: str                # "periodic" or "wall"
+    boundary: str                # "periodic", "wall" or "free"
     periodic_L: Optional[tuple]  # (Lx, Ly) for periodic meshes
     G: float
     chi: float
@@ -157,6 +157,53 @@ def accuracy_e1(n: int, cfl: float = 0.5, t_end: float = 0.1, G: float = 9.81) -
 
     return Scenario(f"accuracy_e1_n{n}", xy, tri, np.zeros(xy.shape[0]), "periodic", L, G, 1.0,
                     cfl, t_end, W0, gW0, exact)
+
+
+def accuracy_e1_free(n: int, cfl: float = 0.5, t_end: float = 0.1, G: float = 9.81) -> Scenario:
+    """The translating Gaussian of accuracy_e1 with the free boundary the paper states for it:
+    the same right-triangle lattice of [0,2]^2 without the periodic pairing (mass flows out at
+    x, y = 2 and in at x, y = 0)."""
+    sc = accuracy_e1(n, cfl=cfl, t_end=t_end, G=G)
+    return dataclasses.replace(sc, name=f"accuracy_e1_free_n{n}", boundary="free", periodic_L=None)
+
+
+def uniform_stream(n: int, seed: int = 20230621, U=(0.7, -0.4), chi: float = 0.95, cfl: float = 0.3,
+                   t_end: float = 1e9, G: float = 9.81) -> Scenario:
+    """A uniform two-layer stream (h1 = 0.6, h2 = 0.4, both layers moving with U) over a flat
+    bottom on a jittered mesh of [0,1]^2 with free boundaries: an exact steady solution that a
+    transmissive boundary must keep."""
+    xy, tri = jittered_square(n, seed)
+    T = tri.shape[0]
+    W0 = np.zeros((6, T))
+    W0[0], W0[1], W0[2] = 0.4, 0.4 * U[0], 0.4 * U[1]
+    W0[3], W0[4], W0[5] = 0.6, 0.6 * U[0], 0.6 * U[1]
+    return Scenario(f"uniform_stream_n{n}", xy, tri, np.zeros(xy.shape[0]), "free", None, G, chi, cfl, t_end,
+                    W0, np.zeros((6, 2, T)))
+
+
+def free_outflow(n: int, seed: int = 20230622, chi: float = 0.95, cfl: float = 0.3, t_end: float = 1e9,
+                 G: float = 9.81) -> Scenario:
+    """A smooth two-layer hump moving out of a free-boundary box: jittered mesh of [0,1]^2, bump
+    bottom 0.1 exp(-30 |x - (0.5, 0.5)|^2), lower level 1 + 0.05 exp(-80 |x - (0.7, 0.5)|^2), upper
+    layer 0.5, both layers flowing with U = (0.8, 0.3)."""
+    xy, tri = jittered_square(n, seed)
+    node_B = _bump(xy, amp=0.1, k=30.0)
+    Bm, Bx, By = _p1_bottom(xy, tri, node_B)
+
+    def prim(x, y):
+        eta = 1.0 + 0.05 * np.exp(-80.0 * ((x - 0.7) ** 2 + (y - 0.5) ** 2))
+        one = np.ones_like(x)
+        return (0.5 * one, 0.8 * one, 0.3 * one, eta, 0.8 * one, 0.3 * one)
+
+    W0, gW0 = _pack_smooth(xy, tri, prim)
+    # the lower layer's thickness is the level minus the piecewise-linear bottom; its momentum
+    # follows the thickness
+    W0[3] -= Bm
+    gW0[3, 0] -= Bx
+    gW0[3, 1] -= By
+    W0[4], W0[5] = 0.8 * W0[3], 0.3 * W0[3]
+    gW0[4], gW0[5] = 0.8 * gW0[3], 0.3 * gW0[3]
+    return Scenario(f"free_outflow_n{n}", xy, tri, node_B, "free", None, G, chi, cfl, t_end, W0, gW0)
 
 
 def _bump(xy, amp=0.5, cx=0.5, cy=0.5, k=50.0):

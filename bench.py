@@ -12,7 +12,10 @@ Also reported on the same JSON line: the mixed FP32/FP64 path on the same worklo
 ensemble of 256 independent scenarios (sizes log-uniform in 5k-200k triangles, FP32, steps replayed
 from a HIP graph), each with its relative L1 error against the FP64 oracle; the roofline of the
 dominant kernel (algorithmic bytes / duration measured with HIP events recorded by the library
-around each launch on its stream); and the oracle's single-threaded throughput on the host.
+around each launch on its stream) and of the whole step (the survey's fused-ideal bytes per
+triangle-stage); the errors after 20 steps against the FP64 oracle run on all host cores, which
+is also the CPU baseline (plus a single-core sample); the 999,698-triangle dam break timed in both
+precisions; and the FP64 arithmetic of the flux kernel against the vector ALU peak.
 """
 from __future__ import annotations
 
@@ -27,6 +30,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "triangle-stage updates/s, FP64 plain vs FP32+learned-indicator, at rel-L1 err"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+FP32_VALU_PEAK_TFLOPS = 157.3
+# fused-ideal algorithmic bytes per triangle-stage (every input once, every output once, neighbour
+# re-reads cached): state in and out, S2O4 carry, least-squares operator, geometry, WENO data,
+# connectivity; FP64 path and mixed path
+STEP_BYTES_PER_TRI_STAGE = {"fp64": 2432, "fp32": 1268}
 
 
 def log(msg):
@@ -121,6 +130,21 @@ def profiled_traffic(kernel, prec):
     return None
 
 
+def profiled_flops(kernel, prec):
+    """Floating-point operations per launch of a kernel from the committed instruction-counter
+    profile of this workload (FMA counted twice), or None if missing or from other sources."""
+    path = os.path.join(ROOT, "profiles", "gks_flux_valu_flops_520k.md")
+    if not os.path.exists(path):
+        return None
+    src = source_hash()
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 5 and t[0] == "flops" and t[1] == kernel and t[2] == prec and t[4] == f"src={src}":
+                return float(t[3])
+    return None
+
+
 def kernel_roofline(st, mesh, steps, prec):
     st.profile(True)
     st.step(steps)
@@ -146,6 +170,13 @@ def kernel_roofline(st, mesh, steps, prec):
         roof["traffic_read_write"] = [tr[0], tr[1]]
         roof["traffic_GBs"] = round((tr[0] + tr[1]) / (avg / 1e3) / 1e9, 1)
         roof["traffic_source"] = "profiles/gks_hbm_traffic_520k.md (FETCH_SIZE x2, WRITE_SIZE x1 per launch)"
+    fl = profiled_flops("flux", prec) if mesh.n_tri == 520200 and "flux" in kernels else None
+    if fl is not None:
+        tf = fl / (kernels["flux"]["avg_ms"] / 1e3) / 1e12
+        peak = FP64_VALU_PEAK_TFLOPS if prec == "fp64" else FP32_VALU_PEAK_TFLOPS
+        kernels["flux"]["alu"] = {"bound": "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
+                                  "frac": round(tf / peak, 4), "flops_per_launch": fl,
+                                  "source": "profiles/gks_flux_valu_flops_520k.md (SQ_INSTS_VALU_*_F64/F32 x 64)"}
     return kernels, roof
 
 
@@ -195,6 +226,11 @@ def run_single(sc, prec, steps, warmup, profile):
     value = mesh.n_tri * 2 * steps / (ms / 1e3)
     log(f"{prec}: {steps} steps {ms:.2f} ms, {value / 1e9:.3f} G tri-stage/s")
     kernels, roof = kernel_roofline(st, mesh, steps, prec) if profile else ({}, None)
+    if roof is not None:
+        sb = STEP_BYTES_PER_TRI_STAGE[prec] * mesh.n_tri * 2
+        gbs = sb / (ms / steps / 1e3) / 1e9
+        roof["step"] = {"alg_bytes_per_step": sb, "bytes_per_tri_stage": STEP_BYTES_PER_TRI_STAGE[prec],
+                        "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
     if profile:
         log(f"{prec} kernels: {json.dumps(kernels)}")
     if shapes:
@@ -202,14 +238,84 @@ def run_single(sc, prec, steps, warmup, profile):
     return mesh, value, ms / steps, kernels, roof
 
 
-def one_step_error(mesh, sc, prec, Wr, dt):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_run(sc, n_steps):
+    """The FP64 oracle on all host cores for n_steps CFL steps: (states after step 1 and after the
+    last step, the step sizes, wall seconds, threads)."""
+    import oracle
+
+    om = oracle.Mesh.from_scenario(sc)
+    p = oracle.params_of(sc)
+    threads = oracle.load().om_max_threads()
+    W, gW = sc.W0, sc.gradW0
+    dts, first = [], None
+    tc = time.time()
+    for k in range(n_steps):
+        dt = oracle.dt(om, p, W)
+        W, gW = oracle.step(om, p, dt, W, gW)
+        dts.append(dt)
+        if k == 0:
+            first = W
+    return first, W, dts, time.time() - tc, threads, om, p
+
+
+def gpu_errors(mesh, sc, prec, dts, W1, Wn, indicator=None):
+    """rel-L1 of the GPU path after the first and after all steps, stepping with the oracle's step
+    sizes (explicit stage-0 steps)."""
     from paper_2306_04467_amd import State
 
     st = State.from_scenario(mesh, sc, precision=prec)
-    st.stage(0, dt)
-    st.stage(1)
-    W, _, _ = st.read()
-    return rel_l1(W, Wr, sc_area(sc), sc.G)
+    if indicator is not None:
+        st.indicator(*indicator)
+    a = sc_area(sc)
+    out, skipped = {}, []
+    for k, dt in enumerate(dts):
+        st.stage(0, dt)
+        st.stage(1)
+        if indicator is not None:
+            skipped.append(st.indicator_eval()[2] / sc.n_tri)
+        if k == 0:
+            out["rel_l1_1step"] = rel_l1(st.read()[0], W1, a, sc.G)
+    if len(dts) > 1:
+        out[f"rel_l1_{len(dts)}steps"] = rel_l1(st.read()[0], Wn, a, sc.G)
+    if skipped:
+        out["skipped_fraction_mean"] = round(sum(skipped) / len(skipped), 4)
+    st.close()
+    return out
+
+
+def cpu_baseline_and_errors(sc, res, precs, n_steps=20):
+    """CPU baseline: the oracle on all host cores for n_steps steps of the headline workload (the
+    same run gives the reference of the 20-step errors), and one step on a single core."""
+    import oracle
+
+    W1, Wn, dts, tc, threads, om, p = oracle_run(sc, n_steps)
+    errs = {prec: gpu_errors(res[prec][0], sc, prec, dts, W1, Wn) for prec in precs}
+    lib = oracle.load()
+    lib.om_set_threads(1)
+    t1 = time.time()
+    oracle.step(om, p, dts[0], sc.W0, sc.gradW0)
+    t1 = time.time() - t1
+    lib.om_set_threads(threads)
+    cpu = {"value": round(sc.n_tri * 2 * n_steps / tc, 1), "unit": "triangle-stage/s", "cores": threads,
+           "kind": "oracle",
+           "sample": f"{n_steps} full S2O4 steps (with the CFL time step) of the same {sc.n_tri}-triangle workload, "
+                     f"FP64 C oracle, OpenMP over cells and edges on {threads} threads, {tc:.1f} s",
+           "single_core_value": round(sc.n_tri * 2 / t1, 1),
+           "single_core_sample": f"one step on one thread, {t1:.1f} s",
+           "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+    log(f"oracle {n_steps} steps on {threads} threads {tc:.1f}s, 1 step on 1 thread {t1:.1f}s; errors {errs}")
+    return cpu, errs
 
 
 def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
@@ -252,30 +358,57 @@ def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
                                  "skipped_fraction_end": round(k / T, 4)}
         sti.close()
     if with_error:
-        # error of the first three scenarios after one step, against the oracle
-        import oracle
-
-        refs = []
-        for i in range(3):
+        # errors of the first n_err scenarios after 20 steps against the oracle (all host cores),
+        # each stepped alone with the oracle's step sizes (a batch equals its single runs bit for
+        # bit, a GPU test checks that)
+        n_err, t0 = 16, time.time()
+        worst = {"full": [], "indicator": []}
+        for i in range(min(n_err, n_scen)):
             sc = scs[i]
-            om = oracle.Mesh.from_scenario(sc)
-            p = oracle.params_of(sc)
-            Wr, _ = oracle.step(om, p, oracle.dt(om, p, sc.W0), sc.W0, sc.gradW0)
-            refs.append(Wr)
-        for key, ind in (("rel_l1_vs_oracle_1step_first3", None), ("rel_l1_vs_oracle_1step_first3_indicator", indicator)):
-            if key.endswith("indicator") and ind is None:
-                continue
-            st2 = State.from_scenarios(bm, scs, precision="fp32")
-            if ind is not None:
-                st2.indicator(*ind)
-            st2.step(1)
-            W, _, _ = st2.read()
-            errs = []
-            for i in range(3):
-                c0, n = bm.scenario_range(i)
-                errs.append(rel_l1(W[:, c0:c0 + n], refs[i], sc_area(scs[i]), scs[i].G))
-            out[key] = float(np.max(errs))
-            st2.close()
+            W1, Wn, dts, _, _, _, _ = oracle_run(sc, 20)
+            m1 = Mesh.from_scenario(sc)
+            worst["full"].append(gpu_errors(m1, sc, "fp32", dts, W1, Wn)["rel_l1_20steps"])
+            if indicator is not None:
+                worst["indicator"].append(gpu_errors(m1, sc, "fp32", dts, W1, Wn, indicator)["rel_l1_20steps"])
+            m1.close()
+        out["errors_vs_oracle"] = {"scenarios": min(n_err, n_scen), "steps": 20,
+                                   "n_tri": int(sum(s.n_tri for s in scs[:n_err])),
+                                   "rel_l1_20steps_max": float(np.max(worst["full"])),
+                                   "rel_l1_20steps_max_indicator": float(np.max(worst["indicator"])) if worst["indicator"] else None,
+                                   "seconds": round(time.time() - t0, 1)}
+        log(f"ensemble errors: {json.dumps(out['errors_vs_oracle'])}")
+    return out
+
+
+def run_c3(steps, warmup, with_error):
+    """The 999,698-triangle two-layer dam break (jittered Delaunay [0,1]^2, sinusoidal bottom,
+    density ratio 0.95, walls) timed in both precisions, with the error after one step against the
+    oracle on all host cores."""
+    import workloads
+    from paper_2306_04467_amd import Mesh, State
+
+    t0 = time.time()
+    sc = workloads.dam_break(707, seed=20230605)
+    mesh = Mesh.from_scenario(sc)
+    log(f"dam break: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
+    out = {"workload": f"two-layer dam break, jittered Delaunay [0,1]^2, {sc.n_tri} triangles, levels 1.0/0.5 -> "
+                       f"0.5/1.0 across x = 0.5, bottom 0.1 sin(2 pi x) sin(2 pi y), chi 0.95, walls, CFL 0.3",
+           "n_tri": sc.n_tri, "steps": steps}
+    ref = None
+    if with_error:
+        W1, _, dts, tc, threads, _, _ = oracle_run(sc, 1)
+        ref = (W1, dts)
+        out["oracle_1step_s"] = round(tc, 1)
+    for prec in ("fp64", "fp32"):
+        st = State.from_scenario(mesh, sc, precision=prec)
+        tune(st)
+        ms = timed_steps(st, steps, warmup)
+        v = sc.n_tri * 2 * steps / (ms / 1e3)
+        out[prec] = {"value": round(v, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5)}
+        st.close()
+        if ref is not None:
+            out[prec].update(gpu_errors(mesh, sc, prec, ref[1], ref[0], ref[0]))
+        log(f"dam break {prec}: {v / 1e9:.3f} G tri-stage/s {json.dumps(out[prec])}")
     return out
 
 
@@ -320,8 +453,8 @@ def train_indicator(label_tol=1e-7, snapshots=6, every=10, epochs=8, batch=2048,
 
 def run_indicator(n, steps, warmup, err_n, with_error, trained=None):
     """Gain case: dam break plus bump on a 2 n^2-triangle mesh, FP32 mixed, with and without the
-    learned indicator; rel-L1 error of both against the FP64 oracle after 20 steps on a smaller
-    mesh of the same shape."""
+    learned indicator; rel-L1 error of both against the FP64 oracle after 20 steps on a
+    2 err_n^2-triangle mesh of the same shape."""
     import numpy as np
 
     import workloads
@@ -355,31 +488,17 @@ def run_indicator(n, steps, warmup, err_n, with_error, trained=None):
         st.close()
     out["speedup"] = round(out["indicator"]["value"] / out["full_weno"]["value"], 3)
     if with_error:
-        import oracle
-
+        # the same workload shape on a 520,200-triangle mesh, 20 steps against the oracle on all
+        # host cores
         se = workloads.dam_break(err_n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
-        om = oracle.Mesh.from_scenario(se)
-        p = oracle.params_of(se)
+        W1, Wn, dts, tc, threads, _, _ = oracle_run(se, 20)
         m2 = Mesh.from_scenario(se)
-        full = State.from_scenario(m2, se, precision="fp32")
-        ind = State.from_scenario(m2, se, precision="fp32")
-        ind.indicator(P, thr)
-        W, gW = se.W0.copy(), se.gradW0.copy()
-        skipped = []
-        tc = time.time()
-        for _ in range(20):
-            dt = oracle.dt(om, p, W)
-            for st in (full, ind):
-                st.stage(0, dt)
-                st.stage(1)
-            skipped.append(ind.indicator_eval()[2] / se.n_tri)
-            W, gW = oracle.step(om, p, dt, W, gW)
-        a = sc_area(se)
-        out["error_case"] = {"n_tri": se.n_tri, "steps": 20,
-                             "rel_l1_full_weno": rel_l1(full.read()[0], W, a, se.G),
-                             "rel_l1_indicator": rel_l1(ind.read()[0], W, a, se.G),
-                             "skipped_fraction_mean": round(float(np.mean(skipped)), 4),
-                             "oracle_s": round(time.time() - tc, 1)}
+        full = gpu_errors(m2, se, "fp32", dts, W1, Wn)
+        ind = gpu_errors(m2, se, "fp32", dts, W1, Wn, (P, thr))
+        out["error_case"] = {"n_tri": se.n_tri, "steps": 20, "rel_l1_full_weno": full["rel_l1_20steps"],
+                             "rel_l1_indicator": ind["rel_l1_20steps"],
+                             "skipped_fraction_mean": ind["skipped_fraction_mean"],
+                             "oracle_s": round(tc, 1), "oracle_threads": threads}
         log(f"gain error case: {json.dumps(out['error_case'])}")
     return out
 
@@ -396,6 +515,8 @@ def main():
     ap.add_argument("--indicator-n", type=int, default=1000,
                     help="lattice size of the learned-indicator gain case (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c3", dest="c3", action="store_false",
+                    help="skip the 999,698-triangle dam break (timed in both precisions)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -452,34 +573,22 @@ def main():
 
     cpu, errs = None, {}
     if not args.no_cpu_baseline:
-        import oracle
-
-        om = oracle.Mesh.from_scenario(sc)
-        p = oracle.params_of(sc)
-        dt = oracle.dt(om, p, sc.W0)
-        tc = time.time()
-        Wr, gWr = oracle.step(om, p, dt, sc.W0, sc.gradW0)
-        oracle.step(om, p, oracle.dt(om, p, Wr), Wr, gWr)  # a second step: ~10 s of CPU work in all
-        tc = time.time() - tc
-        for prec in precs:
-            errs[prec] = one_step_error(res[prec][0], sc, prec, Wr, dt)
-        cpu = {"value": round(sc.n_tri * 2 * 2 / tc, 1), "unit": "triangle-stage/s", "cores": 1, "kind": "oracle",
-               "sample": f"two full S2O4 steps (4 stages, with the CFL time step) of the same {sc.n_tri}-triangle "
-                         f"workload, single-threaded FP64 C oracle, {tc:.1f} s"}
-        log(f"oracle 2 steps {tc:.1f}s; rel-L1 vs oracle after one step: {errs}")
+        cpu, errs = cpu_baseline_and_errors(sc, res, precs)
 
     extra = {}
     if "fp32" in res and head != "fp32":
         _, v32, ms32, k32, r32 = res["fp32"]
         extra["fp32_mixed"] = {"value": round(v32, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms32, 5),
-                               "speedup_vs_fp64": round(v32 / value, 3), "rel_l1_vs_oracle_1step": errs.get("fp32"),
+                               "speedup_vs_fp64": round(v32 / value, 3), "errors_vs_oracle": errs.get("fp32"),
                                "roofline": r32, "kernels": k32}
+    if args.c3:
+        extra["dam_break_1M"] = run_c3(args.steps, args.warmup, not args.no_cpu_baseline)
     trained = train_indicator() if (args.ensemble > 0 or args.indicator_n > 0) else None
     if args.ensemble > 0:
         extra["ensemble"] = run_ensemble(args.ensemble, 50, 5, not args.no_cpu_baseline,
                                          indicator=(trained[0], trained[1]))
     if args.indicator_n > 0:
-        extra["fp32_learned_indicator"] = run_indicator(args.indicator_n, 50, 5, 160, not args.no_cpu_baseline,
+        extra["fp32_learned_indicator"] = run_indicator(args.indicator_n, 50, 5, 510, not args.no_cpu_baseline,
                                                         trained=trained)
 
     line = {
@@ -492,7 +601,7 @@ def main():
                                f"bottom bump 0.5exp(-50r^2), lake at rest eta1=0.8 h2=0.2 + 1e-3 interface "
                                f"perturbation in a disk, walls, chi=0.98, CFL 0.3",
                    "n_tri": sc.n_tri, "n_edges": mesh.n_edges, "precision": head,
-                   "rel_l1_vs_oracle_1step": errs.get(head)},
+                   "errors_vs_oracle": errs.get(head)},
         "roofline": roof, "cpu_baseline": cpu, "kernels": kernels, **extra,
     }
     print(json.dumps(line), flush=True)

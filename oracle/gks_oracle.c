@@ -762,14 +762,14 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
             tauz /= ncand;
             /* reading: the floor of the smoothness indicators carries the variable's scale, the
              * level itself for a thickness and 1e-8 h sqrt(G h) of the layer for a momentum, with
-             * the relative factor 1e-16: the weights leave their linear values once a variable
-             * varies by about 1e-8 of its scale */
+             * the relative factor 1e-18: the weights leave their linear values once a variable
+             * varies by about 1e-9 of its scale */
             double S2 = 1e-20;
             if (v != 0 && v != 3) {
                 double hl = W[(v < 3 ? 0 : 3) * m->nt + c];
                 S2 = 1e-16 * G * hl * hl * hl;
             }
-            double eps = 1e-16 * fmax(Q0 * Q0, S2);
+            double eps = 1e-18 * fmax(Q0 * Q0, S2);
             double wt0 = d0 * (1 + tauz / (beta0 + eps)), wts[4], sum = wt0;
             for (int s = 0; s < 4; s++) {
                 wts[s] = dm[s] * (1 + tauz / (betam[s] + eps));
@@ -1197,7 +1197,11 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
         }
         /* reading: nonlinear weight of the force model from the cells' high-order weights */
         double wf[2];
-        for (int f = 0; f < 2; f++) wf[f] = fmin(1.0, fmin(rL[f], rR[f]));
+        for (int f = 0; f < 2; f++) {
+            wf[f] = fmin(1.0, fmin(rL[f], rR[f]));
+            /* within 1e-12 of 1 the blend changes the acceleration by less than its rounding */
+            if (wf[f] >= 1.0 - 1e-12) wf[f] = 1.0;
+        }
         for (int g = 0; g < 2; g++) {
             double vs[2][6], gs[2][12];
             memcpy(vs[0], REC_VAL(L, kL, g), sizeof(vs[0]));

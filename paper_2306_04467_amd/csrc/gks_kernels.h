@@ -56,13 +56,17 @@ struct Phys {
                               // thickness <= 0 (all ones: none), kept until the state is reloaded
 };
 
+// the force model's weight w is taken as 1 when it is within 1e-12 of 1: the blend would then
+// change the acceleration by less than its own FP64 rounding
+constexpr double W_ONE = 1.0 - 1e-12;
+
 // relative floor of the smoothness indicators of the nonlinear reconstruction, above the
 // rounding of the bulk precision: the weights leave their linear values once a variable varies
-// by about 1e-8 of its scale (FP64), 1e-5 in the mixed path, whose reconstruction runs in FP32
+// by about 1e-9 of its scale (FP64), 1e-5 in the mixed path, whose reconstruction runs in FP32
 template <typename R>
 __device__ constexpr R eps_rel()
 {
-    return sizeof(R) == 8 ? R(1e-16) : R(1e-10);
+    return sizeof(R) == 8 ? R(1e-18) : R(1e-10);
 }
 
 template <typename R>
@@ -273,26 +277,26 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     // m.cand, decided at setup in FP64): its plane would carry a huge slope into the combination
     // below; its linear weight goes to P^3.
     const R *nbc = tab<R>(m.nbc);
-    const unsigned cmask = m.cand[c];
-    R bx[4], by[4], dm[4];
+    const unsigned cmask = m.cand[c] | 8u;  // the own-gradient plane is always a candidate
+    R bx[4], by[4];
 #pragma unroll
     for (int s = 0; s < 3; s++) {
         const int sa = s, sb = (s + 1) % 3;
         const R ax_ = nbc[(2 * sa) * T + c], ay_ = nbc[(2 * sa + 1) * T + c];
         const R bx_ = nbc[(2 * sb) * T + c], by_ = nbc[(2 * sb + 1) * T + c];
         const R ra = rhs[sa], rb = rhs[sb];
-        const bool on = (cmask >> s) & 1u;
-        const R inv = on ? R(1) / (ax_ * by_ - ay_ * bx_) : R(0);
+        const R invd = R(1) / (ax_ * by_ - ay_ * bx_);
+        const R inv = ((cmask >> s) & 1u) ? invd : R(0);  // excluded planes: slope 0, weight 0
         bx[s] = (ra * by_ - ay_ * rb) * inv;
         by[s] = (ax_ * rb - ra * bx_) * inv;
-        dm[s] = on ? R(0.05) : R(0);
     }
     bx[3] = rhs[9];
     by[3] = rhs[10];
-    dm[3] = R(0.05);
-    const int ncand = 1 + __builtin_popcount(cmask & 7u);
-    const R d0 = ncand == 4 ? R(0.8) : ncand == 3 ? R(0.85) : ncand == 2 ? R(0.9) : R(0.95);
-    R w0 = d0, wm[4] = {dm[0], dm[1], dm[2], dm[3]};
+    const int ncand = __builtin_popcount(cmask);
+    const R d0 = ncand == 4 ? R(0.8) : ncand == 3 ? R(0.85) : ncand == 2 ? R(0.9) : R(0.95), dm = R(0.05);
+    R w0 = d0, wm[4];
+#pragma unroll
+    for (int s = 0; s < 4; s++) wm[s] = ((cmask >> s) & 1u) ? dm : R(0);
     const bool nonlinear = !p.linear && !lin;
     if (nonlinear) {
         // smoothness indicator of P^3 in scaled coordinates: the cell has area 1/2 there, so the
@@ -329,7 +333,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
 #pragma unroll
         for (int s = 0; s < 4; s++) {
             bm[s] = R(0.5) * (bx[s] * bx[s] + by[s] * by[s]);
-            if (dm[s] != R(0)) tz += fabs(beta0 - bm[s]);
+            tz += ((cmask >> s) & 1u) ? fabs(beta0 - bm[s]) : R(0);
         }
         tz = ncand == 4 ? tz * R(0.25) : div_(tz, R(ncand));
         // floor of the smoothness indicators with the variable's scale: the level of a thickness,
@@ -340,7 +344,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         R sum = t0, tm[4];
 #pragma unroll
         for (int s = 0; s < 4; s++) {
-            tm[s] = dm[s] * (1 + div_(tz, bm[s] + epsw));
+            tm[s] = ((cmask >> s) & 1u) ? dm * (1 + div_(tz, bm[s] + epsw)) : R(0);
             sum += tm[s];
         }
         // where every unnormalised weight equals its linear weight (tau = 0, or tau / (beta + eps)
@@ -348,7 +352,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
         // exactly instead of dividing by their rounded sum
         bool lin = t0 == d0;
 #pragma unroll
-        for (int s = 0; s < 4; s++) lin = lin && tm[s] == dm[s];
+        for (int s = 0; s < 4; s++) lin = lin && tm[s] == wm[s];
         const R isum = lin ? R(1) : div_(R(1), sum);
         w0 = t0 * isum;
 #pragma unroll
@@ -361,7 +365,7 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
     R sbx = 0, sby = 0;
 #pragma unroll
     for (int s = 0; s < 4; s++) {
-        const R cm = wm[s] - ratio * dm[s];
+        const R cm = wm[s] - ratio * (((cmask >> s) & 1u) ? dm : R(0));
         sbx += cm * bx[s];
         sby += cm * by[s];
     }
@@ -574,19 +578,19 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
 // plane through them must be flat at rest)
 
 // Cells whose plane gradient the flux can read: the force model blends it in with weight 1 - w,
-// w = min(1, omega0/d0 of both sides), so only next to a cell whose weight ratio is below 1.  A
-// face neighbour beyond a wall is the cell's own mirror image.
+// w = min(1, omega0/d0 of both sides) taken as 1 within 1e-12 of it, so only next to a cell whose
+// weight ratio is below 1 - 1e-12.  A face neighbour beyond a wall is the cell's own mirror image.
 template <typename R>
 __global__ void k_need(MeshDev m, const R *__restrict__ r0, uint8_t *__restrict__ need)
 {
     const int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T;
-    bool bad = r0[c] < R(1) || r0[T + c] < R(1);
+    bool bad = (double)r0[c] < W_ONE || (double)r0[T + c] < W_ONE;
 #pragma unroll
     for (int l = 0; l < 3; l++) {
         const int32_t i = m.sten[l * T + c];
-        if (i < T) bad = bad || r0[i] < R(1) || r0[T + i] < R(1);
+        if (i < T) bad = bad || (double)r0[i] < W_ONE || (double)r0[T + i] < W_ONE;
     }
     need[c] = bad ? 1 : 0;
 }
@@ -964,7 +968,8 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     const int ff = lay == 0 ? 1 : 0;   // modelled field index (0: eta1, 1: h2)
     // nonlinear weight of the force model
     const R rL = r0[ff * T + L], rR = Rc >= 0 ? r0[ff * T + Rc] : rL;
-    const R wf = fmin(R(1), fmin(rL, rR));
+    const R wf0 = fmin(R(1), fmin(rL, rR));
+    const R wf = (double)wf0 < W_ONE ? wf0 : R(1);
     SideL<R> side[2];
     double h64[2];
 #pragma unroll
@@ -1218,7 +1223,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         // the state carries grad(eta1) = grad(h1) + grad(B)
         GG[3][0] += gBx;
         GG[3][1] += gBy;
-        bool ok = true;
+        bool bad = false;  // a new thickness <= 0 (or NaN), or a non-finite momentum (via their sum)
+        double msum = 0;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
             const double w = (v == 0) ? Whin[c] : (v == 3) ? Whin[TG + c] : (double)Wmin[mom_slot(v) * TG + c];
@@ -1227,7 +1233,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = ws;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)ws;
-            ok = ok && (v == 0 ? ws > 0 : v == 3 ? ws - m.Bbar[c] > 0 : isfinite(ws));
+            if (v == 0) bad |= !(ws > 0);
+            else if (v == 3) bad |= !(ws - (w - h1) > 0);  // w - h1: the cell's bottom mean
+            else msum += ws;
             Wc[v * T + c] = w + dt * L[v] + (dt * dt / 6.0) * Lt[v];
 #pragma unroll
             for (int d = 0; d < 2; d++) {
@@ -1235,9 +1243,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Gc[(2 * v + d) * T + c] = (R)GG[v][d];
             }
         }
-        if (!ok) atomicMin(p.bad, (unsigned long long)c);
+        if (bad || !isfinite(msum)) atomicMin(p.bad, (unsigned long long)c);
     } else {
-        bool ok = true;
+        bool bad = false;
+        double msum = 0;
 #pragma unroll
         for (int v = 0; v < 6; v++) {
             const double wn = Wc[v * T + c] + (dt * dt / 3.0) * Lt[v];
@@ -1245,12 +1254,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = wn;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)wn;
-            ok = ok && (v == 0 ? wn > 0 : v == 3 ? wn - m.Bbar[c] > 0 : isfinite(wn));
+            if (v == 0) bad |= !(wn > 0);
+            else if (v == 3) bad |= !(wn - m.Bbar[c] > 0);
+            else msum += wn;
 #pragma unroll
             for (int d = 0; d < 2; d++)
                 gWout[(2 * v + d) * TG + c] = (R)((double)Gc[(2 * v + d) * T + c] + dt * GGt[v][d]);
         }
-        if (!ok) atomicMin(p.bad, (unsigned long long)c);
+        if (bad || !isfinite(msum)) atomicMin(p.bad, (unsigned long long)c);
     }
 }
 

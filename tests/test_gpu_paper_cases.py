@@ -91,9 +91,9 @@ def test_well_balance_test_to_t100(gks, chi, precision, bound):
     """The well-balance test of Sec. 4 ([0, 2]^2, cell size 0.05, bump 0.5 exp(-50 r^2) at the
     centre, h1 = 0.8 - B, h2 = 0.2, CFL 0.5, walls) run to its end time t = 100, about 46,000
     steps.  At the paper's density ratio 1 the internal mode has no restoring force and the linear
-    scheme lets it grow from round-off; the nonlinear weights hold it at their floor, 1e-8 of the
-    level in FP64: the paper's bound (< 1e-8, measured 9.8e-9).  The mixed path's floor sits at
-    1e-5 of the level, above single-precision rounding (measured 1.1e-5).  At 0.9 the deviation
+    scheme lets it grow from round-off; the nonlinear weights hold it near their floor, 1e-9 of the
+    level in FP64: under the paper's bound (< 1e-8; measured 1e-9).  The mixed path's floor sits at
+    1e-5 of the level, above single-precision rounding (measured 9e-6).  At 0.9 the deviation
     stays at round-off in FP64 (measured 2.6e-13) and at single-precision rounding in the mixed
     path, whose momenta are single precision."""
     import dataclasses

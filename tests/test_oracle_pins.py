@@ -291,19 +291,19 @@ def test_reconstruction_nonoscillatory_at_a_jump():
 
 
 def test_smoothness_floor_carries_the_variable_scale():
-    """Reading of the nonlinear weights' floor: epsilon = 1e-16 max(Q0^2, S^2) with S the level of a
+    """Reading of the nonlinear weights' floor: epsilon = 1e-18 max(Q0^2, S^2) with S the level of a
     thickness and 1e-8 h sqrt(G h) of the layer for a momentum, so that the weights of a momentum
-    at rest leave their linear values once it varies by about 1e-16 h sqrt(G h), and those of a
-    thickness once it varies by about 1e-8 of its level.  Momentum noise a thousand times under
-    that scale keeps the linear weights (omega_0 / d_0 = 1 to 1e-6), a momentum jump a thousand
-    times above it switches them; the same for a thickness at its own scale."""
+    at rest leave their linear values once it varies by about 1e-17 h sqrt(G h), and those of a
+    thickness once it varies by about 1e-9 of its level.  Momentum noise a hundred times under
+    that scale keeps the linear weights (omega_0 / d_0 = 1 to 1e-6), a momentum jump well above it
+    switches them; the same for a thickness at its own scale."""
     sc = w.lake_at_rest(8, seed=3)
     T = sc.n_tri
     mesh = o.Mesh.from_scenario(sc)
     rng = np.random.default_rng(11)
     hc = 0.2 * np.sqrt(sc.G * 0.2)       # upper layer: h2 = 0.2
     W = sc.W0.copy()
-    W[[1, 2]] = 1e-19 * hc * rng.standard_normal((2, T))
+    W[[1, 2]] = 1e-20 * hc * rng.standard_normal((2, T))
     for c in range(0, T, 5):
         _, _, r0 = mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)
         assert np.abs(r0[[1, 2]] - 1.0).max() < 1e-6, (c, r0)
@@ -312,8 +312,8 @@ def test_smoothness_floor_carries_the_variable_scale():
     W[1] = np.where(cen[:, 0] < 0.5, 1e-13 * hc, 0.0)
     r_min = min(mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)[2][1] for c in range(T))
     assert r_min < 0.9, r_min
-    # thickness h2 = 0.2: a step of 1e-11 of it keeps the linear weights, a step of 1e-5 does not
-    for amp, linear_kept in ((1e-11, True), (1e-5, False)):
+    # thickness h2 = 0.2: a step of 1e-12 of it keeps the linear weights, a step of 1e-6 does not
+    for amp, linear_kept in ((1e-12, True), (1e-6, False)):
         W = sc.W0.copy()
         W[0] = 0.2 * (1 + np.where(cen[:, 0] < 0.5, amp, 0.0))
         r = min(mesh.reconstruct(c, W, sc.gradW0, linear=False, G=sc.G)[2][0] for c in range(T))

@@ -80,6 +80,14 @@ typedef struct {
     double t_end;    /* the last step is clipped so that t never exceeds t_end (<= 0: no limit) */
     int32_t precision;  /* gks_precision */
     int32_t linear;     /* 1: linear P^3 reconstruction everywhere, 0: nonlinear (Sec. 3.4) */
+    int32_t alpha_mode; /* constants alpha_{k,m} of the acceleration term of the evolution solution
+                           (Sec. 2.2, Eq. SWE-2nd-order): 0 (default) the well-balance weights read
+                           for these slopes (3/4 on the mass state moment, 5/4 on the momentum flux
+                           moments, applied to the jump of the two sides' accelerations in the
+                           equilibrium part); 1 the paper's printed (1, 3/4, 1/4) on the flux
+                           moments (mass, normal, tangential momentum) of the whole term in both
+                           the equilibrium and the initial distributions' parts, 1 on the state
+                           moments */
 } gks_params;
 
 /* Build a mesh on the current HIP device.

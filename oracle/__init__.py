@@ -25,7 +25,7 @@ _ip = ctypes.POINTER(ctypes.c_int)
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int),
-                ("per_side_gb", ctypes.c_int)]
+                ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int)]
 
 
 def build() -> str:
@@ -53,6 +53,8 @@ def load():
                                         _dp, _dp, _dp]
     lib.om_gks_point.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.om_gks_point_mode.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _dp]
     lib.om_gks_point_integrated.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
     lib.om_moments.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp]
     lib.om_time_integrals.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
@@ -186,12 +188,16 @@ class Mesh:
         return val, grad, r0
 
 
-def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False) -> Params:
-    return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb))
+ALPHA_MODES = {"reading": 0, "paper": 1}
 
 
-def params_of(sc, linear=False) -> Params:
-    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear)
+def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False,
+           alpha_mode="reading") -> Params:
+    return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb), ALPHA_MODES[alpha_mode])
+
+
+def params_of(sc, linear=False, alpha_mode="reading") -> Params:
+    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode)
 
 
 def dt(mesh: Mesh, p: Params, W) -> float:
@@ -266,11 +272,11 @@ def edge_height(zl, zr, hl, hr, unl, unr, G):
     return load().om_edge_height(*(float(x) for x in (zl, zr, hl, hr, unl, unr, G)))
 
 
-def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0):
+def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0, alpha_mode="reading"):
     sL, sR = _f64(sideL), _f64(sideR)
     F0, Ft, Wb, Wbt = (np.zeros(3) for _ in range(4))
-    load().om_gks_point(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
-                        _d(F0), _d(Ft), _d(Wb), _d(Wbt))
+    load().om_gks_point_mode(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
+                             ALPHA_MODES[alpha_mode], _d(F0), _d(Ft), _d(Wb), _d(Wbt))
     return F0, Ft, Wb, Wbt
 
 

@@ -963,7 +963,45 @@ static void alpha_correction(const double *sL, const double *sR, double lamb, do
     for (int k = 0; k < 3; k++) d[k] = (ALPHA_W[e][k] - 1) * (lp[k] + rm[k] - 0.5 * (lf[k] + rf[k]));
 }
 
-static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_brackets *o)
+/* The paper's printed constants (Sec. 2.2, Eq. SWE-2nd-order), as an alternative reading
+ * (alpha_mode 1): alpha_{1,m} = (1, 3/4, 1/4) weight the acceleration term -2 lam Phi . (u - U)
+ * in the flux moments <u psi_m> (m: mass, normal, tangential momentum) of both the interface
+ * equilibrium's part (C2 term) and the initial distributions' part (C5 term); alpha_{2,m} = 1 for
+ * the state moments, so the time slope of the interface equilibrium is unweighted.  Returns the
+ * changes of the C2 and C5 brackets. */
+static const double ALPHA_PAPER[3] = {1.0, 0.75, 0.25};
+
+static void alpha_paper(const double *sL, const double *sR, double G, double lamb, double hb, double Ub,
+                        double Vb, const double *mubp, const double *mubm, const double *nvb, double *d2,
+                        double *d5)
+{
+    double fL[11] = {0}, fR[11] = {0};
+    for (int i = 9; i < 11; i++) {
+        fL[i] = sL[i];
+        fR[i] = sR[i];
+    }
+    poly FL, FR;
+    double lp[3], rm[3];
+    p_micro(&FL, lamb, hb, Ub, Vb, fL); /* acceleration over the interface equilibrium */
+    p_micro(&FR, lamb, hb, Ub, Vb, fR);
+    p_moment3(&FL, 1, hb, mubp, nvb, lp);
+    p_moment3(&FR, 1, hb, mubm, nvb, rm);
+    for (int k = 0; k < 3; k++) d2[k] = (ALPHA_PAPER[k] - 1) * (lp[k] + rm[k]);
+    double hL = sL[0], UL = sL[1], VL = sL[2], hR = sR[0], UR = sR[1], VR = sR[2];
+    double lamL = 1 / (G * hL), lamR = 1 / (G * hR);
+    double muLp[NM], muRm[NM], nvL[NM], nvR[NM];
+    om_moments(UL, lamL, +1, NM, muLp);
+    om_moments(UR, lamR, -1, NM, muRm);
+    om_moments(VL, lamL, 0, NM, nvL);
+    om_moments(VR, lamR, 0, NM, nvR);
+    p_micro(&FL, lamL, hL, UL, VL, fL); /* acceleration over each side's own Maxwellian */
+    p_micro(&FR, lamR, hR, UR, VR, fR);
+    p_moment3(&FL, 1, hL, muLp, nvL, lp);
+    p_moment3(&FR, 1, hR, muRm, nvR, rm);
+    for (int k = 0; k < 3; k++) d5[k] = (ALPHA_PAPER[k] - 1) * (lp[k] + rm[k]);
+}
+
+static void gks_brackets_eval(const double *sL, const double *sR, double G, int alpha_mode, gks_brackets *o)
 {
     double hL = sL[0], UL = sL[1], VL = sL[2];
     double hR = sR[0], UR = sR[1], VR = sR[2];
@@ -996,7 +1034,10 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_
     double t1[3], t2[3], Wbt[3], da[3];
     p_moment3(&PbL, 0, hb, mubp, nvb, t1);
     p_moment3(&PbR, 0, hb, mubm, nvb, t2);
-    alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 0, da);
+    if (alpha_mode == 0)
+        alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 0, da);
+    else
+        da[0] = da[1] = da[2] = 0; /* the paper's alpha_{2,m} = 1 */
     for (int k = 0; k < 3; k++) Wbt[k] = -(t1[k] + t2[k] + da[k]);
     poly Abar;
     p_zero(&Abar);
@@ -1004,7 +1045,11 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_
     p_moment3(&one, 1, hb, mub, nvb, o->B[0]);
     p_moment3(&PbL, 1, hb, mubp, nvb, t1);
     p_moment3(&PbR, 1, hb, mubm, nvb, t2);
-    alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 1, da);
+    double d5[3] = {0, 0, 0};
+    if (alpha_mode == 0)
+        alpha_correction(sL, sR, lamb, hb, Ub, Vb, mub, mubp, mubm, nvb, 1, da);
+    else
+        alpha_paper(sL, sR, G, lamb, hb, Ub, Vb, mubp, mubm, nvb, da, d5);
     for (int k = 0; k < 3; k++) o->B[1][k] = t1[k] + t2[k] + da[k];
     p_moment3(&Abar, 1, hb, mub, nvb, o->B[2]);
     p_moment3(&one, 1, hL, muLp, nvL, t1);
@@ -1012,7 +1057,7 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, gks_
     for (int k = 0; k < 3; k++) o->B[3][k] = t1[k] + t2[k];
     p_moment3(&PL, 1, hL, muLp, nvL, t1);
     p_moment3(&PR, 1, hR, muRm, nvR, t2);
-    for (int k = 0; k < 3; k++) o->B[4][k] = t1[k] + t2[k];
+    for (int k = 0; k < 3; k++) o->B[4][k] = t1[k] + t2[k] + d5[k];
     for (int k = 0; k < 3; k++) {
         o->Wb[k] = Wb[k];
         o->Wbt[k] = Wbt[k];
@@ -1023,7 +1068,7 @@ void om_gks_point_integrated(const double *sL, const double *sR, double G, doubl
                              double tau, double *F)
 {
     gks_brackets br;
-    gks_brackets_eval(sL, sR, G, &br);
+    gks_brackets_eval(sL, sR, G, 0, &br);
     double g[5];
     om_time_integrals(delta, tau, g);
     for (int k = 0; k < 3; k++) {
@@ -1032,11 +1077,11 @@ void om_gks_point_integrated(const double *sL, const double *sR, double G, doubl
     }
 }
 
-void om_gks_point(const double *sL, const double *sR, double G, double dt, double eps,
-                  double eps_num, double *F0, double *Ft, double *Wb, double *Wbt)
+void om_gks_point_mode(const double *sL, const double *sR, double G, double dt, double eps,
+                       double eps_num, int alpha_mode, double *F0, double *Ft, double *Wb, double *Wbt)
 {
     gks_brackets br;
-    gks_brackets_eval(sL, sR, G, &br);
+    gks_brackets_eval(sL, sR, G, alpha_mode, &br);
     /* collision time with the pressure-jump term (Sec. 4) */
     double pl = sL[0] * sL[0], pr = sR[0] * sR[0];
     double tau = eps * dt + eps_num * fabs((pl - pr) / (pl + pr)) * dt;
@@ -1055,6 +1100,12 @@ void om_gks_point(const double *sL, const double *sR, double G, double dt, doubl
         Wb[k] = br.Wb[k];
         Wbt[k] = br.Wbt[k];
     }
+}
+
+void om_gks_point(const double *sL, const double *sR, double G, double dt, double eps,
+                  double eps_num, double *F0, double *Ft, double *Wb, double *Wbt)
+{
+    om_gks_point_mode(sL, sR, G, dt, eps, eps_num, 0, F0, Ft, Wb, Wbt);
 }
 
 /* ----------------------------------------------------------------------------------------- */
@@ -1256,7 +1307,8 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
             }
             for (int layer = 0; layer < 2; layer++) {
                 double F0[3], Ft[3], Wb[3], Wbt[3];
-                om_gks_point(side[layer][0], side[layer][1], G, dt, p->eps, p->eps_num, F0, Ft, Wb, Wbt);
+                om_gks_point_mode(side[layer][0], side[layer][1], G, dt, p->eps, p->eps_num, p->alpha_mode, F0,
+                                  Ft, Wb, Wbt);
                 if (R < 0 && !m->free_bc) { /* reflecting wall: no mass crosses */
                     F0[0] = 0;
                     Ft[0] = 0;

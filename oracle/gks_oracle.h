@@ -32,6 +32,12 @@ typedef struct {
     int per_side_gb; /* test only: 1 gives each side of an interface its own cell's bottom slope
                         in the evolution instead of the single-valued mean (shows what the
                         single-valued slope is for); 0 in every real use */
+    int alpha_mode;  /* the constants alpha_{k,m} of the evolution solution (Sec. 2.2): 0 the
+                        well-balance weights read here (3/4 on the state moment of mass, 5/4 on
+                        the momentum flux moments, on the jump of the sides' accelerations in the
+                        equilibrium part), 1 the paper's printed (1, 3/4, 1/4) on the flux moments
+                        of the acceleration term in both the equilibrium and the initial parts,
+                        1 on the state moments */
 } om_params;
 
 /* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
@@ -84,6 +90,9 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
  * 3/4 on the mass state moment and 5/4 on the momentum flux moments. */
 void om_gks_point(const double *sideL, const double *sideR, double G, double dt, double eps,
                   double eps_num, double *F0, double *Ft, double *Wb, double *Wbt);
+/* Same with the choice of the constants alpha_{k,m} (alpha_mode as in om_params). */
+void om_gks_point_mode(const double *sideL, const double *sideR, double G, double dt, double eps,
+                       double eps_num, int alpha_mode, double *F0, double *Ft, double *Wb, double *Wbt);
 /* Same, returning the time-integrated flux F(delta) for one delta (for the closed-form pins). */
 void om_gks_point_integrated(const double *sideL, const double *sideR, double G, double delta,
                              double tau, double *F);

@@ -208,8 +208,12 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
         const int b = s->bs[GKS_KERNEL_FLUX];
-        hipLaunchKernelGGL(gks::k_flux<R>, dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
-                           recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+        if (s->p.alpha_mode == 0)
+            hipLaunchKernelGGL((gks::k_flux<R, 0>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+                               recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+        else
+            hipLaunchKernelGGL((gks::k_flux<R, 1>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+                               recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
         const int b = s->bs[GKS_KERNEL_UPDATE];
@@ -498,9 +502,11 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                 return fail(GKS_EUNSUPPORTED, "unknown precision");
             if (!(q.G > 0) || !(q.cfl > 0) || !(q.chi > 0) || !(q.eps > 0) || !(q.eps_num >= 0))
                 return fail(GKS_EINVAL, "bad physical parameters");
+            if (q.alpha_mode != 0 && q.alpha_mode != 1) return fail(GKS_EINVAL, "unknown alpha_mode");
             if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
-                q.precision != prm[0].precision || q.linear != prm[0].linear)
-                return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision and linear");
+                q.precision != prm[0].precision || q.linear != prm[0].linear || q.alpha_mode != prm[0].alpha_mode)
+                return fail(GKS_EINVAL,
+                            "scenarios of a batch share G, cfl, eps, eps_num, precision, linear and alpha_mode");
         }
         *out = nullptr;
         const int prec = prm[0].precision;
@@ -562,6 +568,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         s->p.eps_num = prm[0].eps_num;
         s->p.cfl = prm[0].cfl;
         s->p.linear = prm[0].linear;
+        s->p.alpha_mode = prm[0].alpha_mode;
         s->p.chi = s->chi;
         s->p.t_end = s->tend;
         s->p.scal = s->scal;

@@ -49,6 +49,7 @@ struct MeshDev {
 struct Phys {
     double G, eps, eps_num, cfl;
     int linear;
+    int alpha_mode;       // 0: the well-balance weights read here, 1: the paper's printed constants
     const double *chi;    // [S] density ratio
     const double *t_end;  // [S]
     double *scal;         // [2S] per scenario: dt of the current step, time at its end
@@ -787,7 +788,11 @@ __host__ __device__ inline double sqrt_(double x) { return sqrt(x); }
 // Outputs (local frame): F0 with the hydrostatic term 1/2 G hb^2 removed from its normal-momentum
 // component, Ft, Wb (hb_dev = hb - (hL + hR)/2 in slot 0), Wbt.  hbase = (hL + hR)/2 in FP64; the
 // interface thickness is hbase + hb_dev.
-template <typename R>
+// AM selects the constants alpha_{k,m} of the acceleration term (Sec. 2.2, Eq. SWE-2nd-order):
+// AM = 0 the weights read for these slopes (below), AM = 1 the paper's printed (1, 3/4, 1/4) on the
+// flux moments of the acceleration term in both the equilibrium and the initial distributions'
+// parts, 1 on the state moments.
+template <typename R, int AM = 0>
 __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr, double hbase, R gBn, R gBt, R G, R eps,
                                  R eps_num, R dt, R *F0, R *Ft, R *Wb, R *Wbt)
 {
@@ -842,6 +847,16 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
         }
 #pragma unroll
         for (int i = 0; i < 3; i++) B5[i] = t1[i] + t2[i];
+        if constexpr (AM == 1) {
+            // the paper's constants on the initial distributions' acceleration moments: (3/4 - 1) on
+            // <u u>, (1/4 - 1) on <u v>; the moments are -2 Phi_n N1_2 / G and
+            // -2 (V Phi_n N1_1 + th Phi_t M_1) / G over each side's own half Maxwellian
+            const R pLn = sl.pn - G * gBn, pLt = sl.pt - G * gBt, pRn = sr.pn - G * gBn, pRt = sr.pt - G * gBt;
+            const R L1 = ML[2] - sl.U * ML[1], L2 = ML[3] - sl.U * ML[2];
+            const R R1 = MR[2] - sr.U * MR[1], R2 = MR[3] - sr.U * MR[2];
+            B5[1] += R(0.5) * iG * sum_products(pLn, L2, pRn, R2);
+            B5[2] += R(1.5) * iG * (sl.V * pLn * L1 + thL * pLt * ML[1] + sr.V * pRn * R1 + thR * pRt * MR[1]);
+        }
     }
     const R ihb = div_(R(1), hb);
     const R Ub = wb1 * ihb, Vb = wb2 * ihb;
@@ -872,11 +887,11 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     // -2 Phi_n N1_e / G (mass), -2 Phi_n N1_{e+1} / G, -2 (V Phi_n N1_e + th Phi_t M_e) / G.
     const R aLn = sl.pn - G * gBn, aLt = sl.pt - G * gBt, aRn = sr.pn - G * gBn, aRt = sr.pt - G * gBt;
     const R N1p0 = Mp[1] - Ub * Mp[0], N1m0 = Mm[1] - Ub * Mm[0];
-    // mass, state moment: weight 3/4 (the full-space moment is zero)
-    const R dA0 = sum_products(aLn, N1p0, aRn, N1m0) * (R(0.5) * iG);
+    // mass, state moment: weight 3/4 (the full-space moment is zero); the paper's constants leave
+    // the state moments unweighted
 #pragma unroll
     for (int i = 0; i < 3; i++) wt[i] = -(t1[i] + t2[i]);
-    wt[0] -= dA0;
+    if constexpr (AM == 0) wt[0] -= sum_products(aLn, N1p0, aRn, N1m0) * (R(0.5) * iG);
     // brackets multiplying the five time coefficients; B1 and B4 split into a hydrostatic part
     // and the rest.  B1 = (hb Ub, hb Ub^2 + P, hb Ub Vb)
     R B1[3], B2[3], B3[3];
@@ -892,14 +907,20 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 #pragma unroll
     for (int i = 0; i < 3; i++) B2[i] = t1[i] + t2[i];
     {
-        // flux moments: weight 5/4 on the two momentum components; full-space parts from
-        // N1_1 = th, N1_2 = 2 U th, M_1 = U
         const R N1p1 = Mp[2] - Ub * Mp[1], N1m1 = Mm[2] - Ub * Mm[1];
         const R N1p2 = Mp[3] - Ub * Mp[2], N1m2 = Mm[3] - Ub * Mm[2];
-        const R sn = aLn + aRn, st = aLt + aRt, q = R(-0.5) * iG;  // (5/4 - 1) (-2 / G)
-        B2[1] += q * (sum_products(aLn, N1p2, aRn, N1m2) - sn * Ub * thb);
-        B2[2] += q * (Vb * sum_products(aLn, N1p1, aRn, N1m1) + thb * sum_products(aLt, Mp[1], aRt, Mm[1]) -
-                      R(0.5) * thb * (sn * Vb + st * Ub));
+        if constexpr (AM == 0) {
+            // flux moments: weight 5/4 on the two momentum components; full-space parts from
+            // N1_1 = th, N1_2 = 2 U th, M_1 = U
+            const R sn = aLn + aRn, st = aLt + aRt, q = R(-0.5) * iG;  // (5/4 - 1) (-2 / G)
+            B2[1] += q * (sum_products(aLn, N1p2, aRn, N1m2) - sn * Ub * thb);
+            B2[2] += q * (Vb * sum_products(aLn, N1p1, aRn, N1m1) + thb * sum_products(aLt, Mp[1], aRt, Mm[1]) -
+                          R(0.5) * thb * (sn * Vb + st * Ub));
+        } else {
+            // the paper's constants: (3/4 - 1) on <u u>, (1/4 - 1) on <u v> of the whole term
+            B2[1] += R(0.5) * iG * sum_products(aLn, N1p2, aRn, N1m2);
+            B2[2] += R(1.5) * iG * (Vb * sum_products(aLn, N1p1, aRn, N1m1) + thb * sum_products(aLt, Mp[1], aRt, Mm[1]));
+        }
     }
     {
         const R aA = lamb * wt[0] * ihb;
@@ -938,7 +959,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 }
 
 // one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
-template <typename R>
+template <typename R, int AM>
 __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
                                               const R *__restrict__ r0, const double *__restrict__ gP1,
                                               double *__restrict__ eoh, R *__restrict__ eom)
@@ -1048,7 +1069,7 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     // single-valued bottom slope in the local frame (zero normal part at walls by construction)
     const R gBn = lay == 0 ? gBx * nx + gBy * ny : R(0), gBt = lay == 0 ? gBx * tx + gBy * ty : R(0);
     R F0[3], Ft[3], Wb[3], Wbt[3];
-    gks_point<R>(side[0], side[1], hbase, gBn, gBt, G, (R)p.eps, (R)p.eps_num, dt, F0, Ft, Wb, Wbt);
+    gks_point<R, AM>(side[0], side[1], hbase, gBn, gBt, G, (R)p.eps, (R)p.eps_num, dt, F0, Ft, Wb, Wbt);
     if (Rc == -1) {  // no mass crosses a wall
         F0[0] = 0;
         Ft[0] = 0;

@@ -53,7 +53,10 @@ class GksError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("t_end", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("linear", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("linear", ctypes.c_int32), ("alpha_mode", ctypes.c_int32)]
+
+
+ALPHA_MODES = {"reading": 0, "paper": 1}
 
 
 def load():
@@ -196,8 +199,9 @@ class Mesh:
         self.close()
 
 
-def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False):
-    return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear))
+def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False,
+                alpha_mode="reading"):
+    return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear), ALPHA_MODES[alpha_mode])
 
 
 class State:
@@ -223,8 +227,9 @@ class State:
         self._h = h
 
     @classmethod
-    def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, **kw):
-        p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear)
+    def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, alpha_mode="reading", **kw):
+        p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear,
+                        alpha_mode=alpha_mode)
         return cls(mesh, sc.W0, sc.gradW0, params=p, **kw)
 
     @classmethod

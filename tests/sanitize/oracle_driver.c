@@ -63,7 +63,7 @@ static int run(int periodic)
         W[3 * nt + c] = 0.8 + 0.02 * sin(3 * cx[c]);
         W[4 * nt + c] = 0.01 * cos(2 * cy[c]);
     }
-    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0};
+    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0, periodic ? 1 : 0};
     for (int k = 0; k < 3; k++) {
         double dt = om_dt(m, &p, W);
         om_step(m, &p, dt, 2, W, gW, W2, gW2);

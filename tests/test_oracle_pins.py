@@ -812,3 +812,38 @@ def test_free_boundary_accuracy_problem_matches_the_periodic_one():
         ex = a.exact(ra[2])
         ea, eb = np.abs(ra[0][3] - ex[3]).mean(), np.abs(rb[0][3] - ex[3]).mean()
         assert abs(ea - eb) < 1e-3 * eb
+
+
+# ------------------------------------------------------------------------------------------
+# the constants alpha_{k,m} of the acceleration term (Sec. 2.2): the paper's printed values as a
+# second mode beside the reading used by default
+
+def test_alpha_modes_differ_only_through_the_acceleration():
+    """Both modes weight only the acceleration term -2 lam Phi . (u - U): without acceleration
+    (Phi = 0 on both sides) the evolution is the same bit for bit, with one it is not."""
+    rng = np.random.default_rng(21)
+    for _ in range(5):
+        sL = np.array([1.0, 0.3, -0.2, 0.1, -0.05, 0.2, 0.1, -0.1, 0.3, 0.0, 0.0]) + 0.1 * rng.standard_normal(11) * [0, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0]
+        sR = np.array([0.8, 0.1, 0.1, -0.2, 0.1, 0.0, -0.1, 0.2, 0.1, 0.0, 0.0]) + 0.1 * rng.standard_normal(11) * [0, 1, 1, 1, 1, 1, 1, 1, 1, 0, 0]
+        a = o.gks_point(sL, sR, G, 0.01, alpha_mode="reading")
+        b = o.gks_point(sL, sR, G, 0.01, alpha_mode="paper")
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+        sL[9:], sR[9:] = (0.4, -0.3), (-0.2, 0.5)
+        a = o.gks_point(sL, sR, G, 0.01, alpha_mode="reading")
+        b = o.gks_point(sL, sR, G, 0.01, alpha_mode="paper")
+        assert not np.array_equal(a[0], b[0])
+
+
+def test_paper_alpha_mode_keeps_the_lake_at_rest():
+    """With the paper's constants the scheme is well balanced as well: a lake at rest over a bump on
+    a jittered mesh stays at rest to round-off (the momentum flux moments of a balanced pair vanish
+    by left-right symmetry for any weights, and the mass and state moments are unweighted)."""
+    sc = w.lake_at_rest(10, seed=31)
+    mesh = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, alpha_mode="paper")
+    W, gW = sc.W0, sc.gradW0
+    for _ in range(20):
+        W, gW = o.step(mesh, p, o.dt(mesh, p, W), W, gW)
+    assert np.abs(W[[1, 2, 4, 5]]).max() < 1e-13
+    assert np.abs(W[[0, 3]] - sc.W0[[0, 3]]).max() < 1e-13

@@ -243,9 +243,10 @@ gks_status gks_profile_read(gks_state *st, int32_t kernel, double *total_ms, int
 #define GKS_MLP_PARAMS 7105
 #define GKS_MLP_FEATURES 44
 
-/* Switch the indicator on for every later stage of `st` (params: host [7105], copied) with the
- * given logit threshold, or off (params = NULL).  A HIP graph captured by gks_batch_step before
- * the call is discarded and captured again. */
+/* Switch the indicator on for every later step of `st` (params: host [7105], copied) with the
+ * given logit threshold, or off (params = NULL).  The network runs in the first stage of a step,
+ * on the step's initial state; the second stage reuses its decisions.  A HIP graph captured by
+ * gks_batch_step before the call is discarded and captured again. */
 gks_status gks_indicator_set(gks_state *st, const float *params, float threshold);
 /* Evaluate the indicator on the latest state (synchronising): logits [n_tri] and mask [n_tri]
  * (1 = skip the nonlinear weights) to host memory, either may be NULL; n_skip (may be NULL) the

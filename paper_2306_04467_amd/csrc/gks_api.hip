@@ -188,12 +188,16 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         });
     timed(s, st, GKS_KERNEL_RECON, [&] {
         const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
-        if (s->ind_on)
-            hipLaunchKernelGGL((gks::k_recon<R, true>), g, t, 0, st, m, s->p, Whin, Wmin, gWin,
-                               gks::IndArgs{s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth},
-                               recs_of<R>(s->rec, m.T), (R *)s->r0);
-        else
-            hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, gks::IndArgs{},
+        if (s->ind_on) {
+            const gks::IndArgs ia{s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth};
+            if (stage == 1)  // the second stage reuses the decisions of the step's first stage
+                hipLaunchKernelGGL((gks::k_recon<R, 2>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
+                                   recs_of<R>(s->rec, m.T), (R *)s->r0);
+            else
+                hipLaunchKernelGGL((gks::k_recon<R, 1>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
+                                   recs_of<R>(s->rec, m.T), (R *)s->r0);
+        } else
+            hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, gks::IndArgs{},
                                recs_of<R>(s->rec, m.T), (R *)s->r0);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
@@ -990,9 +994,9 @@ void launch_labels(gks_state *s, double tol)
     pn.linear = 0;
     pl.linear = 1;
     const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
-    hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
+    hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
                        (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->rec, m.T), (R *)s->r0);
-    hipLaunchKernelGGL((gks::k_recon<R, false>), g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
+    hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
                        (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0);
     hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
                        (const gks::GpHead<R> *)s->rec, (const gks::GpHead<R> *)s->lab_rec, s->lab_y);

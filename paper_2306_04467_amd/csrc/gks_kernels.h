@@ -422,9 +422,11 @@ struct IndArgs {
 };
 
 // IND: the learned indicator decides per cell whether the smoothness indicators are computed.
-// Its 44 features come from the right-hand sides the block has gathered anyway; one wave
-// evaluates the network for the block's 32 cells on the matrix cores.
-template <typename R, bool IND>
+// IND = 1: its 44 features come from the right-hand sides the block has gathered anyway; one wave
+// evaluates the network for the block's 32 cells on the matrix cores and the decisions go to
+// ind.mask.  IND = 2: the decisions are read from ind.mask (the network ran on the step's first
+// stage, the second reuses them).
+template <typename R, int IND>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
                                                const R *__restrict__ Wm, const R *__restrict__ gW, IndArgs ind,
                                                GpRecs<R> rec, R *__restrict__ r0)
@@ -439,7 +441,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     constexpr int ROWS1 = 5 * 17, ROWS2 = 153 - ROWS1;
     constexpr int MBYTES = ROWS1 * RECON_CELLS * (int)sizeof(R);
     constexpr int OBYTES = NR * (int)(sizeof(GpHead<R>) + sizeof(GpTail<R>));
-    constexpr int IBYTES = IND ? RECON_CELLS * (FB + HB) * 2 + 4 * RECON_CELLS * 8 + RECON_CELLS : 0;
+    constexpr int IBYTES = IND == 1 ? RECON_CELLS * (FB + HB) * 2 + 4 * RECON_CELLS * 8 + RECON_CELLS : 0;
     constexpr int B1 = MBYTES > OBYTES ? MBYTES : OBYTES, LBYTES = B1 > IBYTES ? B1 : IBYTES;
     __shared__ uint4 lds[(LBYTES + 15) / 16];
     R *Ms = reinterpret_cast<R *>(lds);
@@ -483,7 +485,8 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         if (valid) recon_coeffs<5, 9, R>(q, Ms + lane, a);
     }
     bool lin = false;
-    if constexpr (IND) {
+    if constexpr (IND == 2) lin = valid && ind.mask[c] != 0;
+    if constexpr (IND == 1) {
         __syncthreads();  // the operators are no longer needed: the space holds the network's data
         short(*feat)[FB] = reinterpret_cast<short(*)[FB]>(lds);
         short(*hid)[HB] = reinterpret_cast<short(*)[HB]>(&feat[RECON_CELLS][0]);

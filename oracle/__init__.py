@@ -25,7 +25,7 @@ _ip = ctypes.POINTER(ctypes.c_int)
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int),
-                ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int)]
+                ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int), ("src_order", ctypes.c_int)]
 
 
 def build() -> str:
@@ -62,6 +62,10 @@ def load():
     lib.om_dt.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp]
     lib.om_operator.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, _dp, _dp,
                                 _dp, _dp, _dp, _dp]
+    lib.om_operator_src.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, _dp, _dp,
+                                    _dp, _dp, _dp, _dp, _dp, _dp]
+    lib.om_coupling_correction.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp, ctypes.c_int,
+                                           ctypes.c_double, _dp]
     lib.om_step.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, ctypes.c_int,
                             _dp, _dp, _dp, _dp]
     lib.om_mass.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -191,13 +195,19 @@ class Mesh:
 ALPHA_MODES = {"reading": 0, "paper": 1}
 
 
+SRC_ORDERS = (2, 4)
+
+
 def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False,
-           alpha_mode="reading") -> Params:
-    return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb), ALPHA_MODES[alpha_mode])
+           alpha_mode="reading", src_order=2) -> Params:
+    if src_order not in SRC_ORDERS:
+        raise ValueError(f"src_order must be one of {SRC_ORDERS}")
+    return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb), ALPHA_MODES[alpha_mode],
+                  int(src_order))
 
 
-def params_of(sc, linear=False, alpha_mode="reading") -> Params:
-    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode)
+def params_of(sc, linear=False, alpha_mode="reading", src_order=2) -> Params:
+    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode, src_order=src_order)
 
 
 def dt(mesh: Mesh, p: Params, W) -> float:
@@ -211,6 +221,24 @@ def operator(mesh: Mesh, p: Params, dt_: float, W, gW):
     load().om_operator(mesh._h, ctypes.byref(p), float(dt_), _d(_f64(W)), _d(_f64(gW)),
                        _d(L), _d(Lt), _d(G), _d(Gt))
     return L, Lt, G, Gt
+
+
+def coupling_source(mesh: Mesh, p: Params, dt_: float, W, gW):
+    """Layer-coupling part of the operator: (S, St), each [4, T] = lower layer x, y, upper x, y."""
+    T = mesh.n_tri
+    L, Lt = np.zeros((6, T)), np.zeros((6, T))
+    G, Gt = np.zeros((6, 2, T)), np.zeros((6, 2, T))
+    S, St = np.zeros((4, T)), np.zeros((4, T))
+    load().om_operator_src(mesh._h, ctypes.byref(p), float(dt_), _d(_f64(W)), _d(_f64(gW)),
+                           _d(L), _d(Lt), _d(G), _d(Gt), _d(S), _d(St))
+    return S, St
+
+
+def coupling_correction(mesh: Mesh, c: int, W, gW, linear=False, G=9.81):
+    """Interior correction [8] of the higher-order layer coupling in cell c (om_coupling_correction)."""
+    out = np.zeros(8)
+    load().om_coupling_correction(mesh._h, int(c), _d(_f64(W)), _d(_f64(gW)), int(linear), float(G), _d(out))
+    return out
 
 
 def step(mesh: Mesh, p: Params, dt_: float, W, gW, nstages: int = 2):

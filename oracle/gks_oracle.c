@@ -683,10 +683,101 @@ static double beta_cubic(const double *a, const double v0[3][2], const double *x
     return area * s1 + area * area * s2 + area * area * area * s3;
 }
 
-void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
-                         double *val, double *grad, double *r0)
+/* One variable's reconstruction in a cell as a function of position (offset d from the centroid):
+ * R(d) = Q0 + theta (ratio (P(d) - Q0) + sum_s c_s (P_s(d) - Q0)), P the P^3 fit, P_s the plane
+ * candidates, c_s = omega_s - ratio d_s (the nonlinear combination, Sec. 3.4), theta the positivity
+ * safeguard's factor.  Kept for the interior quadrature of the higher-order layer coupling. */
+typedef struct {
+    double Q0, ratio, theta, a[NDOF], off[NDOF], cs[4], b[4][2];
+} rfun;
+
+/* value, first and second derivatives (R, R_x, R_y, R_xx, R_xy, R_yy) of a reconstruction at d */
+static void rfun_eval(const rfun *r, double dx, double dy, double *o)
+{
+    double mm[9], mx[9], my[9];
+    mono(dx, dy, mm);
+    mono_dx(dx, dy, mx);
+    mono_dy(dx, dy, my);
+    double P = 0, Px = 0, Py = 0;
+    for (int k = 0; k < 9; k++) {
+        P += r->a[k] * (mm[k] - r->off[k]);
+        Px += r->a[k] * mx[k];
+        Py += r->a[k] * my[k];
+    }
+    /* second derivatives of the Taylor monomials dx^2/2, dx dy, dy^2/2, dx^3/6, dx^2 dy/2,
+     * dx dy^2/2, dy^3/6 */
+    double Pxx = r->a[2] + r->a[5] * dx + r->a[6] * dy;
+    double Pxy = r->a[3] + r->a[6] * dx + r->a[7] * dy;
+    double Pyy = r->a[4] + r->a[7] * dx + r->a[8] * dy;
+    double dev = r->ratio * P, gx = r->ratio * Px, gy = r->ratio * Py;
+    for (int s = 0; s < 4; s++) {
+        dev += r->cs[s] * (r->b[s][0] * dx + r->b[s][1] * dy);
+        gx += r->cs[s] * r->b[s][0];
+        gy += r->cs[s] * r->b[s][1];
+    }
+    const double th = r->theta;
+    o[0] = r->Q0 + th * dev;
+    o[1] = th * gx;
+    o[2] = th * gy;
+    o[3] = th * r->ratio * Pxx;
+    o[4] = th * r->ratio * Pxy;
+    o[5] = th * r->ratio * Pyy;
+}
+
+/* Higher-order layer coupling (Sec. 3.2, Eq. SWE-source-discretization and the remark after it
+ * that more integration points raise its order).  The cell average of h_a grad h_b splits
+ * exactly into  mean(h_a) mean(grad h_b) + mean((h_a - mean h_a) grad h_b);  the first product is
+ * the paper's form with the exact cell average in place of the Gauss-point mean, the second is the
+ * correction integrated here over the cell's own reconstructions, with the oracle's 25-point rule
+ * (exact for these degree-5 products).  The time derivative follows by the product rule with the
+ * thickness rate h_t = -div(h U) of the reconstructed momenta.  corr[8]:
+ *   0,1  mean((h1 - mean h1) grad h2)      2,3  mean((h2 - mean h2) grad h1)
+ *   4,5  its time derivative (lower)       6,7  its time derivative (upper)
+ * (h1 = eta1 - B with the cell's linear bottom). */
+static void coupling_correction(const om_mesh *m, int c, const rfun *rf, double *corr)
+{
+    quad_init();
+    double v0[3][2], px[25], py[25];
+    amap I = map_id();
+    image_vertices(m, c, &I, v0);
+    quad_points(v0[0], v0[1], v0[2], px, py);
+    const double x0 = m->cx[c], y0 = m->cy[c], Bx = m->Bx[c], By = m->By[c];
+    double f1[25], f2[25], g1[25][2], g2[25][2], t1[25], t2[25], gt1[25][2], gt2[25][2];
+    double t1m = 0, t2m = 0;
+    for (int q = 0; q < 25; q++) {
+        double dx = px[q] - x0, dy = py[q] - y0, e[NV][6];
+        for (int v = 0; v < NV; v++) rfun_eval(&rf[v], dx, dy, e[v]);
+        f2[q] = e[0][0] - rf[0].Q0;
+        g2[q][0] = e[0][1];
+        g2[q][1] = e[0][2];
+        f1[q] = (e[3][0] - rf[3].Q0) - (Bx * dx + By * dy);
+        g1[q][0] = e[3][1] - Bx;
+        g1[q][1] = e[3][2] - By;
+        /* thickness rates -div(h U) and their gradients, from the momentum reconstructions */
+        t2[q] = -(e[1][1] + e[2][2]);
+        gt2[q][0] = -(e[1][3] + e[2][4]);
+        gt2[q][1] = -(e[1][4] + e[2][5]);
+        t1[q] = -(e[4][1] + e[5][2]);
+        gt1[q][0] = -(e[4][3] + e[5][4]);
+        gt1[q][1] = -(e[4][4] + e[5][5]);
+        t1m += QW[q] * t1[q];
+        t2m += QW[q] * t2[q];
+    }
+    for (int k = 0; k < 8; k++) corr[k] = 0;
+    for (int q = 0; q < 25; q++)
+        for (int d = 0; d < 2; d++) {
+            corr[d] += QW[q] * f1[q] * g2[q][d];
+            corr[2 + d] += QW[q] * f2[q] * g1[q][d];
+            corr[4 + d] += QW[q] * ((t1[q] - t1m) * g2[q][d] + f1[q] * gt2[q][d]);
+            corr[6 + d] += QW[q] * ((t2[q] - t2m) * g1[q][d] + f2[q] * gt1[q][d]);
+        }
+}
+
+static void reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
+                             double *val, double *grad, double *r0, double *corr)
 {
     const double dlin = 0.05; /* reading: linear weight of each lower-order candidate */
+    rfun rf[NV];
     double x0[2] = {m->cx[c], m->cy[c]};
     double area = m->area[c];
     double h = sqrt(2.0 * area);
@@ -821,8 +912,36 @@ void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double 
                     grad[(p * NV + v) * 2] *= theta;
                     grad[(p * NV + v) * 2 + 1] *= theta;
                 }
+            rf[v].theta = theta;
+        } else {
+            rf[v].theta = 1.0;
+        }
+        rf[v].Q0 = Q0;
+        rf[v].ratio = w0 / d0;
+        for (int k = 0; k < NDOF; k++) {
+            rf[v].a[k] = a[k];
+            rf[v].off[k] = off[k];
+        }
+        for (int s = 0; s < 4; s++) {
+            rf[v].cs[s] = wm[s] - (w0 / d0) * dm[s];
+            rf[v].b[s][0] = b[s][0];
+            rf[v].b[s][1] = b[s][1];
         }
     }
+    if (corr) coupling_correction(m, c, rf, corr);
+}
+
+void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
+                         double *val, double *grad, double *r0)
+{
+    reconstruct_cell(m, c, W, gW, linear, G, val, grad, r0, NULL);
+}
+
+void om_coupling_correction(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
+                            double *corr)
+{
+    double val[36], grad[72], r0[6];
+    reconstruct_cell(m, c, W, gW, linear, G, val, grad, r0, corr);
 }
 
 /* ----------------------------------------------------------------------------------------- */
@@ -1155,18 +1274,22 @@ static void mirror_record(const double *n, int vec, const double *val, const dou
     }
 }
 
-int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
-                double *Lo, double *Lto, double *GWo, double *GWto)
+int om_operator_src(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
+                    double *Lo, double *Lto, double *GWo, double *GWto, double *So, double *Sto)
 {
     int T = m->nt, E = m->ne;
     const double G = p->G, chi = p->chi;
-    /* 1. reconstruction at the Gauss points of every cell */
+    const int src4 = p->src_order == 4;
+    /* 1. reconstruction at the Gauss points of every cell (and, for the higher-order coupling,
+     *    the interior correction of each cell) */
     double *val = (double *)malloc(sizeof(double) * (size_t)T * 36);
     double *grd = (double *)malloc(sizeof(double) * (size_t)T * 72);
     double *r0 = (double *)malloc(sizeof(double) * (size_t)T * 6);
+    double *corr = src4 ? (double *)malloc(sizeof(double) * (size_t)T * 8) : NULL;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int c = 0; c < T; c++)
-        om_reconstruct_cell(m, c, W, gW, p->linear, p->G, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6);
+        reconstruct_cell(m, c, W, gW, p->linear, p->G, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6,
+                         src4 ? corr + (size_t)c * 8 : NULL);
 
     /* side records of edge e, Gauss point g (edge orientation), side s: pointers or mirrors */
 #define REC_VAL(c, k, g) (val + (size_t)(c) * 36 + (2 * (k) + (g)) * 6)
@@ -1391,13 +1514,34 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
         }
         /* layer coupling (Sec. 3.2, Eq. SWE-source-discretization): Gauss-point mean thickness of
          * one layer times the Green-Gauss derivative of the other, from the central Gauss-point
-         * thicknesses; its time derivative by the product rule */
+         * thicknesses; its time derivative by the product rule.  Higher order (the paper's remark
+         * on more integration points): the cell average of the thickness in place of the
+         * Gauss-point mean, its rate from the cell's mass flux, plus the interior correction. */
+        double S[4], St[4];
         for (int d = 0; d < 2; d++) {
-            L[4 + d] += -chi * G * hsum[3] * GGc[0][d];
-            Lt[4 + d] += -chi * G * (htsum[3] * GGc[0][d] + hsum[3] * GGct[0][d]);
-            L[1 + d] += -G * hsum[0] * GGc[3][d];
-            Lt[1 + d] += -G * (htsum[0] * GGc[3][d] + hsum[0] * GGct[3][d]);
+            if (src4) {
+                const double *cc = corr + (size_t)c * 8;
+                double h1 = W[3 * T + c], h2 = W[0 * T + c]; /* cell-average thicknesses */
+                S[d] = -chi * G * (h1 * GGc[0][d] + cc[d]);
+                St[d] = -chi * G * (LF[3] * GGc[0][d] + h1 * GGct[0][d] + cc[4 + d]);
+                S[2 + d] = -G * (h2 * GGc[3][d] + cc[2 + d]);
+                St[2 + d] = -G * (LF[0] * GGc[3][d] + h2 * GGct[3][d] + cc[6 + d]);
+            } else {
+                S[d] = -chi * G * hsum[3] * GGc[0][d];
+                St[d] = -chi * G * (htsum[3] * GGc[0][d] + hsum[3] * GGct[0][d]);
+                S[2 + d] = -G * hsum[0] * GGc[3][d];
+                St[2 + d] = -G * (htsum[0] * GGc[3][d] + hsum[0] * GGct[3][d]);
+            }
+            L[4 + d] += S[d];
+            Lt[4 + d] += St[d];
+            L[1 + d] += S[2 + d];
+            Lt[1 + d] += St[2 + d];
         }
+        if (So)
+            for (int k = 0; k < 4; k++) {
+                So[(size_t)k * T + c] = S[k];
+                Sto[(size_t)k * T + c] = St[k];
+            }
         for (int v = 0; v < 6; v++) {
             Lo[v * T + c] = L[v];
             Lto[v * T + c] = Lt[v];
@@ -1410,10 +1554,17 @@ int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W
     free(val);
     free(grd);
     free(r0);
+    free(corr);
     free(hmid);
     free(gP1);
     free(eo);
     return 0;
+}
+
+int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
+                double *Lo, double *Lto, double *GWo, double *GWto)
+{
+    return om_operator_src(m, p, dt, W, gW, Lo, Lto, GWo, GWto, NULL, NULL);
 }
 
 /* ----------------------------------------------------------------------------------------- */

@@ -38,6 +38,12 @@ typedef struct {
                         equilibrium part), 1 the paper's printed (1, 3/4, 1/4) on the flux moments
                         of the acceleration term in both the equilibrium and the initial parts,
                         1 on the state moments */
+    int src_order;   /* layer coupling (Sec. 3.2, Eq. SWE-source-discretization): 2 (or 0) the
+                        paper's second-order form, Gauss-point mean thickness times the
+                        Green-Gauss derivative of the other layer; 4 the higher-order form its
+                        closing remark allows: the cell average in place of the Gauss-point mean
+                        plus the interior integral of (h_a - mean h_a) grad h_b over the cell's
+                        reconstructions */
 } om_params;
 
 /* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
@@ -47,13 +53,14 @@ void om_s2o4_stage(int n, double dt, const double *W, const double *L, const dou
 void om_s2o4_final(int n, double dt, const double *W, const double *L, const double *Lt, const double *Lt2,
                    double *out);
 
-/* Mesh: node coordinates [nn][2], counter-clockwise triangles [nt][3], bottom at the nodes
- * (piecewise linear), periodic != 0 pairs the boundary edges of [0,Lx]x[0,Ly] by translation,
- * otherwise every boundary edge is a reflecting wall.  Returns NULL on a malformed mesh. */
 /* Threads used by the per-cell and per-edge loops (OpenMP); results do not depend on it. */
 void om_set_threads(int n);
 int om_max_threads(void);
 
+/* Mesh: node coordinates [nn][2], counter-clockwise triangles [nt][3], bottom at the nodes
+ * (piecewise linear).  bc (passed as `periodic`): 1 pairs the boundary edges of [0,Lx]x[0,Ly] by
+ * translation, 2 makes every boundary edge free (zero-gradient), 0 a reflecting wall.  Returns
+ * NULL on a malformed mesh. */
 om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, const double *node_B,
                      int periodic, double Lx, double Ly);
 void om_mesh_free(om_mesh *m);
@@ -111,6 +118,14 @@ double om_dt(const om_mesh *m, const om_params *p, const double *W);
  * Gauss-point thicknesses as the mean of the two sides' reconstructed values (Sec. 3.2). */
 int om_operator(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
                 double *L, double *Lt, double *GW, double *GWt);
+/* Same, also returning the layer-coupling part of L and Lt (S[4][T], St[4][T]: lower layer x, y,
+ * upper layer x, y; NULL to skip). */
+int om_operator_src(const om_mesh *m, const om_params *p, double dt, const double *W, const double *gW,
+                    double *L, double *Lt, double *GW, double *GWt, double *S, double *St);
+/* The interior correction of the higher-order layer coupling in cell c (corr[8], see src_order):
+ * mean((h1 - mean h1) grad h2), mean((h2 - mean h2) grad h1), then their time derivatives. */
+void om_coupling_correction(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
+                            double *corr);
 
 /* One S2O4 step (Sec. 3.3, Eq. SWE-fully-discrete and the two-stage interface update).
  * nstages = 1 stops after the first stage and returns W^{n+1/2}. */

@@ -63,7 +63,9 @@ static int run(int periodic)
         W[3 * nt + c] = 0.8 + 0.02 * sin(3 * cx[c]);
         W[4 * nt + c] = 0.01 * cos(2 * cy[c]);
     }
-    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0, periodic ? 1 : 0};
+    /* both alpha modes and both layer-coupling orders: the periodic run takes the paper's
+     * constants and the higher-order coupling */
+    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0, periodic ? 1 : 0, periodic ? 4 : 2};
     for (int k = 0; k < 3; k++) {
         double dt = om_dt(m, &p, W);
         om_step(m, &p, dt, 2, W, gW, W2, gW2);
@@ -77,6 +79,8 @@ static int run(int periodic)
     om_plane_gradient(m, 0, hk, g2);
     double val[36], grad[72], r0[6];
     om_reconstruct_cell(m, nt / 2, W, gW, 0, 9.81, val, grad, r0);
+    double corr[8];
+    om_coupling_correction(m, nt / 2, W, gW, 0, 9.81, corr);
     double *X = calloc((size_t)44 * nt, sizeof(double));
     om_features(m, 9.81, W, gW, X);
     double *P = calloc(7105, sizeof(double)), *gr = calloc(7105, sizeof(double)), *y = calloc(nt, sizeof(double)),
@@ -86,7 +90,7 @@ static int run(int periodic)
     om_mlp_forward(P, X, nt, z);
     om_mlp_forward_bf16(P, X, nt, z);
     ok = ok && isfinite(loss) && finite_all(X, 44L * nt) && finite_all(gr, 7105) && isfinite(mass[0]) &&
-         finite_all(val, 36) && finite_all(g2, 2);
+         finite_all(val, 36) && finite_all(g2, 2) && finite_all(corr, 8);
     om_mesh_free(m);
     free(xy); free(B); free(tri); free(W); free(gW); free(W2); free(gW2); free(area); free(cx); free(cy);
     free(X); free(P); free(gr); free(y); free(z);

@@ -249,13 +249,13 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_run(sc, n_steps):
+def oracle_run(sc, n_steps, src_order=2):
     """The FP64 oracle on all host cores for n_steps CFL steps: (states after step 1 and after the
     last step, the step sizes, wall seconds, threads)."""
     import oracle
 
     om = oracle.Mesh.from_scenario(sc)
-    p = oracle.params_of(sc)
+    p = oracle.params_of(sc, src_order=src_order)
     threads = oracle.load().om_max_threads()
     W, gW = sc.W0, sc.gradW0
     dts, first = [], None
@@ -269,12 +269,12 @@ def oracle_run(sc, n_steps):
     return first, W, dts, time.time() - tc, threads, om, p
 
 
-def gpu_errors(mesh, sc, prec, dts, W1, Wn, indicator=None):
+def gpu_errors(mesh, sc, prec, dts, W1, Wn, indicator=None, src_order=2):
     """rel-L1 of the GPU path after the first and after all steps, stepping with the oracle's step
     sizes (explicit stage-0 steps)."""
     from paper_2306_04467_amd import State
 
-    st = State.from_scenario(mesh, sc, precision=prec)
+    st = State.from_scenario(mesh, sc, precision=prec, src_order=src_order)
     if indicator is not None:
         st.indicator(*indicator)
     a = sc_area(sc)
@@ -412,6 +412,30 @@ def run_c3(steps, warmup, with_error):
     return out
 
 
+def run_src4(sc, mesh, res, steps, warmup, with_error):
+    """The higher-order layer coupling (src_order 4) on the headline workload: both precisions timed
+    beside the paper's form, and the FP64 error after 20 steps against the oracle in the same mode."""
+    from paper_2306_04467_amd import State
+
+    out = {"workload": "the headline workload with the higher-order layer coupling"}
+    for prec in ("fp64", "fp32"):
+        st = State.from_scenario(mesh, sc, precision=prec, src_order=4)
+        tune(st)
+        ms = timed_steps(st, steps, warmup)
+        v = sc.n_tri * 2 * steps / (ms / 1e3)
+        out[prec] = {"value": round(v, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5)}
+        if prec in res:
+            out[prec]["relative_to_paper_form"] = round(v / res[prec][1], 4)
+        st.close()
+        log(f"src4 {prec}: {v / 1e9:.3f} G tri-stage/s {json.dumps(out[prec])}")
+    if with_error:
+        W1, Wn, dts, tc, threads, _, _ = oracle_run(sc, 20, src_order=4)
+        out["errors_vs_oracle"] = {"fp64": gpu_errors(mesh, sc, "fp64", dts, W1, Wn, src_order=4),
+                                   "oracle_s": round(tc, 1), "oracle_threads": threads}
+        log(f"src4 errors: {json.dumps(out['errors_vs_oracle'])}")
+    return out
+
+
 def he_init(seed, n_in=44, n_h=64):
     """Initial indicator parameters: He-normal weights, zero biases (seeded)."""
     import numpy as np
@@ -519,6 +543,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c3", dest="c3", action="store_false",
                     help="skip the 999,698-triangle dam break (timed in both precisions)")
+    ap.add_argument("--no-src4", dest="src4", action="store_false",
+                    help="skip the higher-order layer coupling leg on the headline workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -583,6 +609,8 @@ def main():
         extra["fp32_mixed"] = {"value": round(v32, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms32, 5),
                                "speedup_vs_fp64": round(v32 / value, 3), "errors_vs_oracle": errs.get("fp32"),
                                "roofline": r32, "kernels": k32}
+    if args.src4:
+        extra["higher_order_coupling"] = run_src4(sc, mesh, res, args.steps, args.warmup, not args.no_cpu_baseline)
     if args.c3:
         extra["dam_break_1M"] = run_c3(args.steps, args.warmup, not args.no_cpu_baseline)
     trained = train_indicator() if (args.ensemble > 0 or args.indicator_n > 0) else None

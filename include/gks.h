@@ -88,6 +88,14 @@ typedef struct {
                            moments (mass, normal, tangential momentum) of the whole term in both
                            the equilibrium and the initial distributions' parts, 1 on the state
                            moments */
+    int32_t src_order;  /* layer coupling (Sec. 3.2, Eq. SWE-source-discretization): 2 (or 0) the
+                           paper's second-order form, the Gauss-point mean thickness of one layer
+                           times the Green-Gauss derivative of the other's Gauss-point thickness;
+                           4 the higher-order form its closing remark allows: the cell-average
+                           thickness in place of the Gauss-point mean plus the cell average of
+                           (h_a - mean h_a) grad h_b over the cell's reconstructions (Radon's
+                           7-point rule), its time derivative with h_t = -div(h U).  Must agree
+                           across the scenarios of a batch; other values give GKS_EINVAL */
 } gks_params;
 
 /* Build a mesh on the current HIP device.
@@ -193,7 +201,10 @@ typedef enum {
                           then the mean of the two sides' thickness rates -div(h U) (upper, lower) */
     GKS_BUF_SKIP = 5,  /* uint8 [n_tri]: the learned indicator's decisions of the last stage that ran
                           with it (1 = linear weights); unspecified before the first such stage */
-    GKS_BUF_COUNT = 6
+    GKS_BUF_SRC = 6,   /* real [8][n_tri]: interior correction of the higher-order layer coupling
+                          (src_order 4 only, else GKS_EINVAL): mean((h1 - mean h1) grad h2) x, y,
+                          mean((h2 - mean h2) grad h1) x, y, then the time derivatives of both */
+    GKS_BUF_COUNT = 7
 } gks_buffer;
 /* Copy one intermediate array to host memory `dst` of `bytes` bytes (synchronising); "real" is
  * double for GKS_FP64 states and float for GKS_FP32_MIXED.  GKS_EINVAL if bytes is too small. */

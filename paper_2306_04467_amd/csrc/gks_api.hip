@@ -113,6 +113,8 @@ struct gks_state {
     uint8_t *smooth = nullptr;  // skip mask of the reconstruction (learned indicator)
     uint8_t *need = nullptr;    // cells whose plane gradient of the force model is used
     unsigned long long *bad = nullptr;  // first cell updated to a non-finite / non-positive state
+    bool src4 = false;          // higher-order layer coupling
+    void *src = nullptr;        // its interior correction [8][T] (real), written by the reconstruction
     // threads per block of the edge and cell kernels (per kernel class), chosen by gks_autotune
     int bs[GKS_KERNEL_COUNT] = {256, 192, 256, 256, 256, 256, 256, 256};
     int nparts = 0;
@@ -172,6 +174,40 @@ void timed(gks_state *s, hipStream_t st, int kernel, F &&launch)
     }
 }
 
+template <typename R, int SRC>
+void launch_recon(gks_state *s, int stage, hipStream_t st, const double *Whin, const R *Wmin, const R *gWin)
+{
+    const gks::MeshDev &m = s->md;
+    const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
+    R *src = SRC ? (R *)s->src : nullptr;
+    if (s->ind_on) {
+        const gks::IndArgs ia{s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth};
+        if (stage == 1)  // the second stage reuses the decisions of the step's first stage
+            hipLaunchKernelGGL((gks::k_recon<R, 2, SRC>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
+                               recs_of<R>(s->rec, m.T), (R *)s->r0, src);
+        else
+            hipLaunchKernelGGL((gks::k_recon<R, 1, SRC>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
+                               recs_of<R>(s->rec, m.T), (R *)s->r0, src);
+    } else
+        hipLaunchKernelGGL((gks::k_recon<R, 0, SRC>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, gks::IndArgs{},
+                           recs_of<R>(s->rec, m.T), (R *)s->r0, src);
+}
+
+template <typename R, int SRC>
+void launch_update(gks_state *s, int stage, hipStream_t st, const double *Whin, const R *Wmin, const R *gWin,
+                   double *Whout, R *Wmout, R *gWout)
+{
+    const gks::MeshDev &m = s->md;
+    const int b = s->bs[GKS_KERNEL_UPDATE];
+    const R *src = SRC ? (const R *)s->src : nullptr;
+    if (stage == 0)
+        hipLaunchKernelGGL((gks::k_update<R, 0, SRC>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
+    else
+        hipLaunchKernelGGL((gks::k_update<R, 1, SRC>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
+}
+
 template <typename R>
 void launch_stage(gks_state *s, int stage, hipStream_t st)
 {
@@ -187,18 +223,10 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
             hipLaunchKernelGGL(gks::k_ghost_fill<R>, dim3(blocks(m.NG, b)), dim3(b), 0, st, m, Whin, Wmin, gWin);
         });
     timed(s, st, GKS_KERNEL_RECON, [&] {
-        const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
-        if (s->ind_on) {
-            const gks::IndArgs ia{s->ind_W1b, s->ind_W2b, s->ind_P, s->ind_thr, s->smooth};
-            if (stage == 1)  // the second stage reuses the decisions of the step's first stage
-                hipLaunchKernelGGL((gks::k_recon<R, 2>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
-                                   recs_of<R>(s->rec, m.T), (R *)s->r0);
-            else
-                hipLaunchKernelGGL((gks::k_recon<R, 1>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, ia,
-                                   recs_of<R>(s->rec, m.T), (R *)s->r0);
-        } else
-            hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, st, m, s->p, Whin, Wmin, gWin, gks::IndArgs{},
-                               recs_of<R>(s->rec, m.T), (R *)s->r0);
+        if (s->src4)
+            launch_recon<R, 1>(s, stage, st, Whin, Wmin, gWin);
+        else
+            launch_recon<R, 0>(s, stage, st, Whin, Wmin, gWin);
     });
     timed(s, st, GKS_KERNEL_HHAT, [&] {
         const int b = s->bs[GKS_KERNEL_HHAT];
@@ -220,13 +248,10 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
                                recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
-        const int b = s->bs[GKS_KERNEL_UPDATE];
-        if (stage == 0)
-            hipLaunchKernelGGL((gks::k_update<R, 0>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
-                               (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+        if (s->src4)
+            launch_update<R, 1>(s, stage, st, Whin, Wmin, gWin, Whout, Wmout, gWout);
         else
-            hipLaunchKernelGGL((gks::k_update<R, 1>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
-                               (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc);
+            launch_update<R, 0>(s, stage, st, Whin, Wmin, gWin, Whout, Wmout, gWout);
     });
 }
 
@@ -507,10 +532,13 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
             if (!(q.G > 0) || !(q.cfl > 0) || !(q.chi > 0) || !(q.eps > 0) || !(q.eps_num >= 0))
                 return fail(GKS_EINVAL, "bad physical parameters");
             if (q.alpha_mode != 0 && q.alpha_mode != 1) return fail(GKS_EINVAL, "unknown alpha_mode");
+            if (q.src_order != 0 && q.src_order != 2 && q.src_order != 4)
+                return fail(GKS_EINVAL, "src_order must be 2 (or 0) or 4");
             if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
-                q.precision != prm[0].precision || q.linear != prm[0].linear || q.alpha_mode != prm[0].alpha_mode)
-                return fail(GKS_EINVAL,
-                            "scenarios of a batch share G, cfl, eps, eps_num, precision, linear and alpha_mode");
+                q.precision != prm[0].precision || q.linear != prm[0].linear || q.alpha_mode != prm[0].alpha_mode ||
+                (q.src_order == 4) != (prm[0].src_order == 4))
+                return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision, linear, "
+                                        "alpha_mode and src_order");
         }
         *out = nullptr;
         const int prec = prm[0].precision;
@@ -539,6 +567,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         gks_state *s = new gks_state();
         s->mesh = mesh;
         s->prec = prec;
+        s->src4 = prm[0].src_order == 4;
         s->md = prec == GKS_FP64 ? mesh->d64 : mesh->d32;
         s->stream = (hipStream_t)stream;
         s->nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (T + gks::DT_BLOCK - 1) / gks::DT_BLOCK));
@@ -553,7 +582,8 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                     {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
                     {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 6 * uE * 8}, {&s->eom, 24 * uE * rs},
                     {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
-                    {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}, {(void **)&s->bad, 8}};
+                    {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}, {(void **)&s->bad, 8},
+                    {&s->src, s->src4 ? 8 * uT * rs : 8}};
         for (auto &b : bufs) {
             hipError_t e = hipMalloc(b.p, std::max<size_t>(b.bytes, 8));
             if (e != hipSuccess) {
@@ -935,10 +965,16 @@ extern "C" gks_status gks_state_buffer(const gks_state *s, int32_t which, void *
         case GKS_BUF_R0: need = 2 * T * rs; break;
         case GKS_BUF_EOH: need = 6 * E * 8; break;
         case GKS_BUF_SKIP: need = T; break;
+        case GKS_BUF_SRC: need = 8 * T * rs; break;
         default: need = 24 * E * rs; break;
         }
         if (bytes < need) return fail(GKS_EINVAL, "buffer too small: " + std::to_string(need) + " bytes needed");
         HIP_OK(hipStreamSynchronize(s->stream));
+        if (which == GKS_BUF_SRC) {
+            if (!s->src4) return fail(GKS_EINVAL, "the state uses the second-order layer coupling (src_order 2)");
+            HIP_OK(hipMemcpy(dst, s->src, (size_t)need, hipMemcpyDeviceToHost));
+            return GKS_OK;
+        }
         if (which == GKS_BUF_SKIP) {
             if (!s->smooth) return fail(GKS_EINVAL, "the indicator has never been switched on");
             HIP_OK(hipMemcpy(dst, s->smooth, (size_t)T, hipMemcpyDeviceToHost));
@@ -995,9 +1031,9 @@ void launch_labels(gks_state *s, double tol)
     pl.linear = 1;
     const dim3 g(blocks(m.T, gks::RECON_CELLS)), t(192);
     hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, s->stream, m, pn, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->rec, m.T), (R *)s->r0);
+                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->rec, m.T), (R *)s->r0, nullptr);
     hipLaunchKernelGGL((gks::k_recon<R, 0>), g, t, 0, s->stream, m, pl, s->Wh[b], (const R *)s->Wm[b],
-                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0);
+                       (const R *)s->gW[b], gks::IndArgs{}, recs_of<R>(s->lab_rec, m.T), (R *)s->lab_r0, nullptr);
     hipLaunchKernelGGL(gks::k_label<R>, dim3(blocks(m.T, 256)), dim3(256), 0, s->stream, m, s->p.G, tol, s->Wh[b],
                        (const gks::GpHead<R> *)s->rec, (const gks::GpHead<R> *)s->lab_rec, s->lab_y);
 }

@@ -242,9 +242,17 @@ __device__ inline void recon_coeffs(const ReconRhs<R> &q, const R *Ms, R a[9])
 
 // the reconstruction from the P^3 coefficients a; lin: take the linear weights (no smoothness
 // indicators)
+// the combination that recon_cell settled on, for evaluations away from the Gauss points:
+// R(x) = Q0 + theta (ratio P(x) + sbx x + sby y) in scaled coordinates (P the zero-mean P^3 part)
+template <typename R>
+struct ReconComb {
+    R ratio, sbx, sby, theta;
+};
+
 template <typename R>
 __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *__restrict__ r0, int v, bool thick,
-                                  int64_t c, const ReconRhs<R> &q, const R a[9], ReconOut<R> &out)
+                                  int64_t c, const ReconRhs<R> &q, const R a[9], ReconOut<R> &out,
+                                  ReconComb<R> &comb)
 {
     const int64_t T = m.T;
     const R *rhs = q.rhs;
@@ -410,6 +418,81 @@ __device__ inline void recon_cell(const MeshDev &m, const Phys &p, bool lin, R *
             out.gy[slot] *= theta;
         }
     }
+    comb.ratio = ratio;
+    comb.sbx = sbx;
+    comb.sby = sby;
+    comb.theta = theta;
+}
+
+// Higher-order layer coupling (Sec. 3.2, Eq. SWE-source-discretization, and its remark that more
+// integration points raise the order): the part of the cell average of h_a grad h_b that the
+// product of averages misses, mean((h_a - mean h_a) grad h_b), and its time derivative with the
+// thickness rate h_t = -div(h U), from the cell's own reconstructions.  Each variable thread
+// evaluates three numbers per interior point: a thickness its deviation from the cell average and
+// its gradient (the lower layer's thickness is eta1 minus the linear bottom), a momentum its
+// derivative along its own direction and that derivative's gradient (so the two momentum threads
+// of a layer sum to div(h U)).  Radon's 7-point rule is exact for these degree-5 products.
+// cell geometry for the interior evaluations: scaled vertices and the cell mean of P^3's
+// non-constant part (as in recon_cell)
+template <typename R>
+struct SrcGeo {
+    R vx[3], vy[3], mean_const, ihs;
+};
+
+template <typename R>
+__device__ inline void src_geo(const MeshDev &m, int64_t c, const R a[9], R hs, SrcGeo<R> &g)
+{
+    const R *vt = tab<R>(m.vtx);
+    R mxx = 0, mxy = 0, myy = 0, mx3 = 0, mx2y = 0, mxy2 = 0, my3 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const R vx = vt[(2 * k) * m.T + c], vy = vt[(2 * k + 1) * m.T + c];
+        g.vx[k] = vx;
+        g.vy[k] = vy;
+        mxx += vx * vx;
+        mxy += vx * vy;
+        myy += vy * vy;
+        mx3 += vx * vx * vx;
+        mx2y += vx * vx * vy;
+        mxy2 += vx * vy * vy;
+        my3 += vy * vy * vy;
+    }
+    const R c12 = R(1) / R(12), c30 = R(1) / R(30);
+    g.mean_const = a[2] * mxx * c12 + a[3] * mxy * c12 + a[4] * myy * c12 + a[5] * mx3 * c30 +
+                   a[6] * mx2y * c30 + a[7] * mxy2 * c30 + a[8] * my3 * c30;
+    g.ihs = div_(R(1), hs);
+}
+
+// three numbers of variable v at the scaled point (x, y), see the block comment above
+template <typename R>
+__device__ inline void src_point(const MeshDev &m, int v, bool thick, int64_t c, const R a[9],
+                                 const ReconComb<R> &cb, const SrcGeo<R> &g, R hs, R x, R y, R o[3])
+{
+    const R ihs = g.ihs;
+    const R Px = a[0] + 2 * a[2] * x + a[3] * y + 3 * a[5] * x * x + 2 * a[6] * x * y + a[7] * y * y;
+    const R Py = a[1] + a[3] * x + 2 * a[4] * y + a[6] * x * x + 2 * a[7] * x * y + 3 * a[8] * y * y;
+    if (thick) {
+        const R P = a[0] * x + a[1] * y + a[2] * x * x + a[3] * x * y + a[4] * y * y + a[5] * x * x * x +
+                    a[6] * x * x * y + a[7] * x * y * y + a[8] * y * y * y - g.mean_const;
+        o[0] = cb.theta * (cb.ratio * P + cb.sbx * x + cb.sby * y);
+        o[1] = cb.theta * (cb.ratio * Px + cb.sbx) * ihs;
+        o[2] = cb.theta * (cb.ratio * Py + cb.sby) * ihs;
+        if (v == 3) {  // h1 = eta1 - B: remove the linear bottom's deviation and slope
+            const R gBx = (R)m.gB[c], gBy = (R)m.gB[m.T + c];
+            o[0] -= hs * (gBx * x + gBy * y);
+            o[1] -= gBx;
+            o[2] -= gBy;
+        }
+    } else {
+        const R Pxx = 2 * a[2] + 6 * a[5] * x + 2 * a[6] * y;
+        const R Pxy = a[3] + 2 * a[6] * x + 2 * a[7] * y;
+        const R Pyy = 2 * a[4] + 2 * a[7] * x + 6 * a[8] * y;
+        const bool dx = (v == 1 || v == 4);  // x-momentum: d/dx; y-momentum: d/dy
+        const R i2 = ihs * ihs;
+        o[0] = dx ? (cb.ratio * Px + cb.sbx) * ihs : (cb.ratio * Py + cb.sby) * ihs;
+        o[1] = cb.ratio * (dx ? Pxx : Pxy) * i2;
+        o[2] = cb.ratio * (dx ? Pxy : Pyy) * i2;
+    }
 }
 
 // the learned indicator inside the reconstruction: bf16 weight matrices, FP32 parameters, logit
@@ -426,10 +509,12 @@ struct IndArgs {
 // evaluates the network for the block's 32 cells on the matrix cores and the decisions go to
 // ind.mask.  IND = 2: the decisions are read from ind.mask (the network ran on the step's first
 // stage, the second reuses them).
-template <typename R, int IND>
+// SRC = 1: the block then also forms the interior correction of the higher-order layer coupling
+// (src[8][T], see src_point) in the LDS space the records used.
+template <typename R, int IND, int SRC = 0>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
                                                const R *__restrict__ Wm, const R *__restrict__ gW, IndArgs ind,
-                                               GpRecs<R> rec, R *__restrict__ r0)
+                                               GpRecs<R> rec, R *__restrict__ r0, R *__restrict__ src)
 {
     // LDS: first the block's 32 least-squares operators, loaded once with coalesced reads and
     // shared by the six variable threads of each cell; then, in the same space, the indicator's
@@ -553,7 +638,8 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         if (threadIdx.x < 32 && valid && ind.mask) ind.mask[c] = lin ? 1 : 0;
     }
     ReconOut<R> out;
-    if (valid) recon_cell<R>(m, p, lin, r0, v, thick, c, q, a, out);
+    ReconComb<R> comb;
+    if (valid) recon_cell<R>(m, p, lin, r0, v, thick, c, q, a, out, comb);
     __syncthreads();  // the space becomes the record tile
     if (valid) {
 #pragma unroll
@@ -574,6 +660,82 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     uint4 *dh = reinterpret_cast<uint4 *>(rec.head + 6 * c0), *dtl = reinterpret_cast<uint4 *>(rec.tail + 6 * c0);
     for (int i = threadIdx.x; i < nh; i += blockDim.x) dh[i] = sh[i];
     for (int i = threadIdx.x; i < nt; i += blockDim.x) dtl[i] = st[i];
+    if constexpr (SRC == 1) {
+        // Radon's 7-point rule (degree 5): the centroid, then two orbits (b, a, a) of barycentrics
+        const R A1 = R(0.101286507323456338800987361915), B1 = R(0.797426985353087322398025276170);
+        const R A2 = R(0.470142064105115089770441209513), B2 = R(0.059715871789769820459117580973);
+        const R W0 = R(0.225), W1 = R(0.125939180544827152595683945500), W2 = R(0.132394152788506180737649387833);
+        // [point of the batch][variable][3][cell]: four points, then three
+        static_assert(4 * 6 * 3 * RECON_CELLS * (int)sizeof(R) <= LBYTES, "interior values exceed the LDS tile");
+        R *sv = reinterpret_cast<R *>(lds);
+        SrcGeo<R> geo;
+        if (valid) src_geo<R>(m, c, a, q.hs, geo);
+        // group 0: lower (h1 - mean) grad h2; 1: upper (h2 - mean) grad h1; 2 and 3: their rates
+        const int gq = wv;
+        const int ha = (gq == 0 || gq == 2) ? 3 : 0, hb = 3 - ha;  // deviation of h_a, gradient of h_b
+        const int ta = ha == 3 ? 4 : 1, tb = ha == 3 ? 1 : 4;      // momenta of layer a, of layer b
+        R acc[7] = {0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const int q0 = 4 * b, nq = b == 0 ? 4 : 3;
+            __syncthreads();  // the previous contents of the space have been read
+            if (valid) {
+#pragma unroll
+                for (int j = 0; j < nq; j++) {
+                    const int qi = q0 + j;
+                    R l0, l1, l2;
+                    if (qi == 0) {
+                        l0 = l1 = l2 = R(1) / R(3);
+                    } else if (qi <= 3) {
+                        l0 = qi == 1 ? B1 : A1;
+                        l1 = qi == 2 ? B1 : A1;
+                        l2 = qi == 3 ? B1 : A1;
+                    } else {
+                        l0 = qi == 4 ? B2 : A2;
+                        l1 = qi == 5 ? B2 : A2;
+                        l2 = qi == 6 ? B2 : A2;
+                    }
+                    const R x = l0 * geo.vx[0] + l1 * geo.vx[1] + l2 * geo.vx[2];
+                    const R y = l0 * geo.vy[0] + l1 * geo.vy[1] + l2 * geo.vy[2];
+                    R o3[3];
+                    src_point<R>(m, v, thick, c, a, comb, geo, q.hs, x, y, o3);
+#pragma unroll
+                    for (int k = 0; k < 3; k++) sv[((j * 6 + v) * 3 + k) * RECON_CELLS + lane] = o3[k];
+                }
+            }
+            __syncthreads();
+            if (valid && gq < 4) {
+#pragma unroll
+                for (int j = 0; j < nq; j++) {
+                    const int qi = q0 + j;
+                    const R wq = qi == 0 ? W0 : qi <= 3 ? W1 : W2;
+                    auto at = [&](int vv, int k) { return sv[((j * 6 + vv) * 3 + k) * RECON_CELLS + lane]; };
+                    const R f = at(ha, 0), gx = at(hb, 1), gy = at(hb, 2);
+                    if (gq < 2) {
+                        acc[0] += wq * f * gx;
+                        acc[1] += wq * f * gy;
+                    } else {
+                        const R tau = -(at(ta, 0) + at(ta + 1, 0));
+                        const R gtx = -(at(tb, 1) + at(tb + 1, 1)), gty = -(at(tb, 2) + at(tb + 1, 2));
+                        acc[0] += wq * tau * gx;  // sum w tau_a grad h_b
+                        acc[1] += wq * tau * gy;
+                        acc[2] += wq * gx;        // sum w grad h_b
+                        acc[3] += wq * gy;
+                        acc[4] += wq * tau;       // mean of tau_a
+                        acc[5] += wq * f * gtx;   // sum w (h_a - mean) grad tau_b
+                        acc[6] += wq * f * gty;
+                    }
+                }
+            }
+        }
+        if (valid && gq < 4) {
+            // rates: sum w (tau_a - mean tau_a) grad h_b + sum w (h_a - mean) grad tau_b
+            const R o0 = gq < 2 ? acc[0] : acc[0] - acc[4] * acc[2] + acc[5];
+            const R o1 = gq < 2 ? acc[1] : acc[1] - acc[4] * acc[3] + acc[6];
+            src[(2 * gq) * T + c] = o0;
+            src[(2 * gq + 1) * T + c] = o1;
+        }
+    }
 }
 
 // --------------------------------------------------------------------------------------------
@@ -1129,12 +1291,15 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 // STAGE is a template argument: the second stage needs only the time derivatives, the thickness
 // fluxes and the interface thicknesses, so it neither loads nor sums the momentum fluxes, the
 // hydrostatic terms and the interface momenta
-template <typename R, int STAGE>
+// SRC = 1: the higher-order layer coupling: the cell-average thickness in place of the Gauss-point
+// mean, its rate from the cell's mass flux, plus the interior correction src[8][T] of k_recon.
+template <typename R, int STAGE, int SRC = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(MeshDev m, Phys p, const double *__restrict__ eoh,
                                                 const R *__restrict__ eom, const double *__restrict__ Whin,
                                                 const R *__restrict__ Wmin, const R *__restrict__ gWin,
                                                 double *__restrict__ Whout, R *__restrict__ Wmout,
-                                                R *__restrict__ gWout, double *__restrict__ Wc, R *__restrict__ Gc)
+                                                R *__restrict__ gWout, double *__restrict__ Wc, R *__restrict__ Gc,
+                                                const R *__restrict__ src)
 {
     constexpr int stage = STAGE;
     int64_t c = xcd_block() * blockDim.x + threadIdx.x;
@@ -1228,10 +1393,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     Lt[2] += LF[0] * (-G * gBy);
     Lt[4] += LF[3] * (-G * gBx);
     Lt[5] += LF[3] * (-G * gBy);
-    Lt[4] += -chi * G * (hts[0] * GC[1][0] + hs[0] * GCt[1][0]);
-    Lt[5] += -chi * G * (hts[0] * GC[1][1] + hs[0] * GCt[1][1]);
-    Lt[1] += -G * (hts[1] * GC[0][0] + hs[1] * GCt[0][0]);
-    Lt[2] += -G * (hts[1] * GC[0][1] + hs[1] * GCt[0][1]);
+    if constexpr (SRC == 1) {
+        // higher order: cell-average thicknesses, their rates from the mass fluxes
+        const double h2a = Whin[c], h1a = Whin[TG + c] - m.Bbar[c];
+        Lt[4] += -chi * G * (LF[3] * GC[1][0] + h1a * GCt[1][0] + (double)src[4 * T + c]);
+        Lt[5] += -chi * G * (LF[3] * GC[1][1] + h1a * GCt[1][1] + (double)src[5 * T + c]);
+        Lt[1] += -G * (LF[0] * GC[0][0] + h2a * GCt[0][0] + (double)src[6 * T + c]);
+        Lt[2] += -G * (LF[0] * GC[0][1] + h2a * GCt[0][1] + (double)src[7 * T + c]);
+    } else {
+        Lt[4] += -chi * G * (hts[0] * GC[1][0] + hs[0] * GCt[1][0]);
+        Lt[5] += -chi * G * (hts[0] * GC[1][1] + hs[0] * GCt[1][1]);
+        Lt[1] += -G * (hts[1] * GC[0][0] + hs[1] * GCt[0][0]);
+        Lt[2] += -G * (hts[1] * GC[0][1] + hs[1] * GCt[0][1]);
+    }
     if constexpr (stage == 0) {
         double L[6];
 #pragma unroll
@@ -1239,11 +1413,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const double h2 = Whin[c], h1 = Whin[TG + c] - m.Bbar[c];
         // bottom source h_j (0, -G B_x, -G B_y) (Sec. 3.2) and layer coupling
         // (Eq. SWE-source-discretization) from the Gauss-point mean thickness and the Green-Gauss
-        // derivative of the other layer's Gauss-point thickness (central values)
-        L[1] += h2 * (-G * gBx) - G * hs[1] * GC[0][0];
-        L[2] += h2 * (-G * gBy) - G * hs[1] * GC[0][1];
-        L[4] += h1 * (-G * gBx) - chi * G * hs[0] * GC[1][0];
-        L[5] += h1 * (-G * gBy) - chi * G * hs[0] * GC[1][1];
+        // derivative of the other layer's Gauss-point thickness (central values); the higher-order
+        // form takes the cell average and adds the interior correction
+        if constexpr (SRC == 1) {
+            L[1] += h2 * (-G * gBx) - G * (h2 * GC[0][0] + (double)src[2 * T + c]);
+            L[2] += h2 * (-G * gBy) - G * (h2 * GC[0][1] + (double)src[3 * T + c]);
+            L[4] += h1 * (-G * gBx) - chi * G * (h1 * GC[1][0] + (double)src[c]);
+            L[5] += h1 * (-G * gBy) - chi * G * (h1 * GC[1][1] + (double)src[T + c]);
+        } else {
+            L[1] += h2 * (-G * gBx) - G * hs[1] * GC[0][0];
+            L[2] += h2 * (-G * gBy) - G * hs[1] * GC[0][1];
+            L[4] += h1 * (-G * gBx) - chi * G * hs[0] * GC[1][0];
+            L[5] += h1 * (-G * gBy) - chi * G * hs[0] * GC[1][1];
+        }
         // the state carries grad(eta1) = grad(h1) + grad(B)
         GG[3][0] += gBx;
         GG[3][1] += gBy;

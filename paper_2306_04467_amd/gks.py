@@ -40,7 +40,7 @@ SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_in
 _VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
 MLP_PARAMS, MLP_FEATURES = 7105, 44
 BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 6, True),
-           "eom": (4, 24, False), "skip": (5, 1, None)}
+           "eom": (4, 24, False), "skip": (5, 1, None), "src": (6, 8, False)}
 KERNELS = ("ghost", "recon", "hhat", "plane", "flux", "update", "dt", "indicator")
 
 
@@ -53,10 +53,12 @@ class GksError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("t_end", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("linear", ctypes.c_int32), ("alpha_mode", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("linear", ctypes.c_int32), ("alpha_mode", ctypes.c_int32),
+                ("src_order", ctypes.c_int32)]
 
 
 ALPHA_MODES = {"reading": 0, "paper": 1}
+SRC_ORDERS = (2, 4)
 
 
 def load():
@@ -200,8 +202,9 @@ class Mesh:
 
 
 def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False,
-                alpha_mode="reading"):
-    return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear), ALPHA_MODES[alpha_mode])
+                alpha_mode="reading", src_order=2):
+    return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear), ALPHA_MODES[alpha_mode],
+                  int(src_order))
 
 
 class State:
@@ -227,15 +230,16 @@ class State:
         self._h = h
 
     @classmethod
-    def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, alpha_mode="reading", **kw):
+    def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, alpha_mode="reading",
+                      src_order=2, **kw):
         p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear,
-                        alpha_mode=alpha_mode)
+                        alpha_mode=alpha_mode, src_order=src_order)
         return cls(mesh, sc.W0, sc.gradW0, params=p, **kw)
 
     @classmethod
-    def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, **kw):
+    def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, src_order=2, **kw):
         ps = [make_params(G=s.G, chi=s.chi, cfl=s.cfl, t_end=s.t_end if s.t_end < 1e8 else 0.0,
-                          precision=precision, linear=linear) for s in scs]
+                          precision=precision, linear=linear, src_order=src_order) for s in scs]
         W0 = np.concatenate([s.W0 for s in scs], axis=1)
         gW0 = np.concatenate([s.gradW0 for s in scs], axis=2)
         return cls(batch_mesh, W0, gW0, params=ps, **kw)

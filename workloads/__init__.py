@@ -13,6 +13,7 @@ from .scenarios import (  # noqa: F401
     accuracy_e1_free,
     uniform_stream,
     free_outflow,
+    smooth_jittered,
     lake_at_rest,
     well_balance_bump,
     dam_break,

@@ -206,6 +206,45 @@ def free_outflow(n: int, seed: int = 20230622, chi: float = 0.95, cfl: float = 0
     return Scenario(f"free_outflow_n{n}", xy, tri, node_B, "free", None, G, chi, cfl, t_end, W0, gW0)
 
 
+def smooth_jittered(n: int, seed: int = 20230623, chi: float = 0.95, cfl: float = 0.3, t_end: float = 1e9,
+                    G: float = 9.81) -> Scenario:
+    """Both layers varying smoothly on a jittered wall mesh of [0,1]^2 over the bump bottom
+    0.1 exp(-30 |x - (0.5, 0.5)|^2): lower level 1 + 0.05 sin(2 pi x) cos(2 pi y), upper thickness
+    0.5 + 0.04 cos(2 pi x + 0.4) sin(2 pi y), velocities (0.2 + 0.1 sin(2 pi y), -0.1 cos(2 pi x))
+    below and (0.1 cos(2 pi (x + y)), 0.15) above."""
+    xy, tri = jittered_square(n, seed)
+    node_B = _bump(xy, amp=0.1, k=30.0)
+    Bm, Bx, By = _p1_bottom(xy, tri, node_B)
+    tp = 2.0 * np.pi
+
+    def prim(x, y):
+        eta = 1.0 + 0.05 * np.sin(tp * x) * np.cos(tp * y)
+        h2 = 0.5 + 0.04 * np.cos(tp * x + 0.4) * np.sin(tp * y)
+        one = np.ones_like(x)
+        return (h2, 0.1 * np.cos(tp * (x + y)), 0.15 * one, eta, 0.2 + 0.1 * np.sin(tp * y), -0.1 * np.cos(tp * x))
+
+    def cons(x, y):
+        h2, U2, V2, eta, U1, V1 = prim(x, y)
+        return np.stack([h2, h2 * U2, h2 * V2, eta, eta * U1, eta * V1])
+
+    W0 = cell_average(xy, tri, cons)
+    gW0 = cell_gradient(xy, tri, cons)
+    # the lower layer's thickness is the level minus the piecewise-linear bottom; its momentum is
+    # that thickness times the level's mean velocity, and the momentum gradient drops the bottom's
+    # share U grad B (smooth synthetic data, not an exact solution)
+    U1 = W0[4] / W0[3]
+    V1 = W0[5] / W0[3]
+    W0[3] -= Bm
+    gW0[3, 0] -= Bx
+    gW0[3, 1] -= By
+    W0[4], W0[5] = U1 * W0[3], V1 * W0[3]
+    gW0[4, 0] -= U1 * Bx
+    gW0[4, 1] -= U1 * By
+    gW0[5, 0] -= V1 * Bx
+    gW0[5, 1] -= V1 * By
+    return Scenario(f"smooth_jittered_n{n}", xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0)
+
+
 def _bump(xy, amp=0.5, cx=0.5, cy=0.5, k=50.0):
     return amp * np.exp(-k * ((xy[:, 0] - cx) ** 2 + (xy[:, 1] - cy) ** 2))
 

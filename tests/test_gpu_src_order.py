@@ -135,3 +135,23 @@ def test_bad_src_order_is_rejected(gks):
     st.stage(0)
     with pytest.raises(gks.GksError):
         st.buffer("src")  # only a state with the higher-order coupling has the correction
+
+
+def test_full_size_dam_break_step_parity_higher_order_coupling(gks):
+    """The 999,698-triangle two-layer dam break at full size with the higher-order coupling: one
+    S2O4 step with the CFL step, every cell against the oracle's step in the same mode (in the
+    second stage the front's new gradients make the interior correction non-zero)."""
+    sc = w.dam_break(707, seed=20230605)
+    print(f"[src4] full size dam break T={sc.n_tri}", flush=True)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, src_order=4)
+    dt = st.step(1, want_dt=True)
+    W, gW, _ = st.read()
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, src_order=4)
+    dref = o.dt(om, p, sc.W0)
+    assert abs(dt - dref) <= 4e-16 * dref
+    Wr, gWr = o.step(om, p, dref, sc.W0, sc.gradW0)
+    e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
+    print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
+    assert e.max() < TOL_FP64 and g.max() < TOL_FP64, (e, g)

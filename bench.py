@@ -426,6 +426,11 @@ def run_src4(sc, mesh, res, steps, warmup, with_error):
         out[prec] = {"value": round(v, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5)}
         if prec in res:
             out[prec]["relative_to_paper_form"] = round(v / res[prec][1], 4)
+        st.profile(True)
+        st.step(2)
+        prof = st.profile_read()
+        st.profile(False)
+        out[prec]["kernel_ms"] = {kk: round(pv[0] / pv[1], 5) for kk, pv in prof.items() if pv[1]}
         st.close()
         log(f"src4 {prec}: {v / 1e9:.3f} G tri-stage/s {json.dumps(out[prec])}")
     if with_error:

@@ -675,12 +675,13 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         const int ha = (gq == 0 || gq == 2) ? 3 : 0, hb = 3 - ha;  // deviation of h_a, gradient of h_b
         const int ta = ha == 3 ? 4 : 1, tb = ha == 3 ? 1 : 4;      // momenta of layer a, of layer b
         R acc[7] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
+        // loops kept rolled: the reconstruction's register budget (4 waves per SIMD) is the limit
+#pragma unroll 1
         for (int b = 0; b < 2; b++) {
             const int q0 = 4 * b, nq = b == 0 ? 4 : 3;
             __syncthreads();  // the previous contents of the space have been read
             if (valid) {
-#pragma unroll
+#pragma unroll 1
                 for (int j = 0; j < nq; j++) {
                     const int qi = q0 + j;
                     R l0, l1, l2;
@@ -705,7 +706,7 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
             }
             __syncthreads();
             if (valid && gq < 4) {
-#pragma unroll
+#pragma unroll 1
                 for (int j = 0; j < nq; j++) {
                     const int qi = q0 + j;
                     const R wq = qi == 0 ? W0 : qi <= 3 ? W1 : W2;

@@ -155,3 +155,28 @@ def test_full_size_dam_break_step_parity_higher_order_coupling(gks):
     e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
     print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
     assert e.max() < TOL_FP64 and g.max() < TOL_FP64, (e, g)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_higher_order_coupling_with_the_fused_indicator(gks, precision):
+    """The reconstruction variants that fuse the learned indicator also form the interior correction:
+    a network whose logit is a constant 1 (all weights zero, output bias 1) skips every cell at
+    threshold 0 and none at threshold 2, so three steps must equal, bit for bit, the linear
+    reconstruction and the full one, each with the higher-order coupling."""
+    sc = _case("jittered")
+    m = gks.Mesh.from_scenario(sc)
+    from paper_2306_04467_amd.gks import MLP_PARAMS
+
+    P = np.zeros(MLP_PARAMS, dtype=np.float32)
+    P[-1] = 1.0
+    out = {}
+    for name, kw, thr in (("skip_all", {}, 0.0), ("linear", {"linear": True}, None),
+                          ("skip_none", {}, 2.0), ("full", {}, None)):
+        st = gks.State.from_scenario(m, sc, precision=precision, src_order=4, **kw)
+        if thr is not None:
+            st.indicator(P, thr)
+        st.step(3)
+        out[name] = st.read()[0]
+    assert np.array_equal(out["skip_all"], out["linear"])
+    assert np.array_equal(out["skip_none"], out["full"])
+    assert not np.array_equal(out["linear"], out["full"])

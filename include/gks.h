@@ -164,6 +164,15 @@ gks_status gks_state_mass(const gks_state *st, int32_t s, double mass[2]);
  * streams) share that array and race; calls on one stream are ordered and do not. */
 gks_status gks_state_mass_noalloc(const gks_state *st, int32_t s, double mass[2]);
 
+/* Per-step diagnostics of scenario s (0 <= s < n_scenarios; synchronising), from device
+ * reductions over its cells: out[0] time t, out[1] last step size, out[2] and out[3] the layer
+ * masses as gks_state_mass (upper h2, lower h1), out[4] and out[5] the largest speed |hU|/h of the
+ * upper and the lower layer, out[6] and out[7] the spread (max - min) of the lower level
+ * eta1 = h1 + B and of the surface eta2 = eta1 + h2.  For a lake at rest (Sec. 3.2, the
+ * well-balance property) out[4..7] are its residual: zero up to rounding.  GKS_ENONFINITE as for
+ * the other synchronising queries (outputs filled first). */
+gks_status gks_state_diagnostics(const gks_state *st, int32_t s, double out[8]);
+
 /* Non-finite detection (a diagnostic of the cell update, Sec. 3.3): every cell update records on
  * the device, without a host round trip, the smallest cell index whose new state has a
  * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B).  gks_state_check

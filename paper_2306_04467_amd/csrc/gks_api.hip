@@ -837,6 +837,47 @@ gks_status gks_state_mass(const gks_state *s, int32_t scen, double mass[2])
     });
 }
 
+gks_status gks_state_diagnostics(const gks_state *s, int32_t scen, double out[8])
+{
+    return guarded([&]() -> gks_status {
+        if (!s || !out || scen < 0 || scen >= s->md.S) return fail(GKS_EINVAL, "bad diagnostics query");
+        const gks::HostMesh &h = s->mesh->host;
+        const int64_t c0 = h.scell[scen], c1 = h.scell[scen + 1];
+        const int nb = 256;  // 6 values per block: the state's part buffer holds at least 2048
+        const int b = s->half ? 1 : 0;
+        hipLaunchKernelGGL(gks::k_mass_partial, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[b], c0, c1, s->part);
+        HIP_OK(hipGetLastError());
+        std::vector<double> mpart(2 * nb), dpart(6 * nb);
+        HIP_OK(hipMemcpyAsync(mpart.data(), s->part, mpart.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        if (s->prec == GKS_FP64)
+            hipLaunchKernelGGL(gks::k_diag_partial<double>, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[b],
+                               (const double *)s->Wm[b], c0, c1, s->part);
+        else
+            hipLaunchKernelGGL(gks::k_diag_partial<float>, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[b],
+                               (const float *)s->Wm[b], c0, c1, s->part);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(dpart.data(), s->part, dpart.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        double sc[2];
+        HIP_OK(hipMemcpyAsync(sc, s->scal + 2 * scen, sizeof(sc), hipMemcpyDeviceToHost, s->stream));
+        HIP_OK(hipStreamSynchronize(s->stream));
+        out[0] = s->half ? sc[1] - 0.5 * sc[0] : sc[1];
+        out[1] = sc[0];
+        out[2] = out[3] = 0;
+        for (int k = 0; k < nb; k++) {
+            out[2] += mpart[2 * k];
+            out[3] += mpart[2 * k + 1];
+        }
+        double mx[6] = {0.0, 0.0, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL, -HUGE_VAL};
+        for (int k = 0; k < nb; k++)
+            for (int q = 0; q < 6; q++) mx[q] = std::max(mx[q], dpart[6 * k + q]);
+        out[4] = mx[0];
+        out[5] = mx[1];
+        out[6] = mx[2] + mx[3];  // max - min of eta1
+        out[7] = mx[4] + mx[5];  // max - min of eta2
+        return check_bad(s, nullptr);
+    });
+}
+
 gks_status gks_state_check(const gks_state *s, int64_t *first_bad)
 {
     return guarded([&]() -> gks_status {

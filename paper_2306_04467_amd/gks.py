@@ -6,6 +6,7 @@ raises if the shared object is missing; there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 import numpy as np
@@ -31,7 +32,7 @@ PRECISIONS = {"fp64": GKS_FP64, "fp32": GKS_FP32_MIXED}
 # every entry point declared in include/gks.h
 SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_info", "gks_mesh_scenario",
            "gks_state_init", "gks_state_destroy", "gks_stage", "gks_step", "gks_batch_step", "gks_state_read",
-           "gks_state_time", "gks_state_mass", "gks_state_mass_noalloc", "gks_state_check",
+           "gks_state_time", "gks_state_mass", "gks_state_mass_noalloc", "gks_state_diagnostics", "gks_state_check",
            "gks_state_checkpoint_size", "gks_state_save", "gks_state_load", "gks_state_buffer", "gks_profile", "gks_profile_read",
            "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
            "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
@@ -90,6 +91,7 @@ def load():
     lib.gks_state_time.argtypes = [_vp, ctypes.c_int32, _dp, _dp]
     lib.gks_state_mass.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_mass_noalloc.argtypes = [_vp, ctypes.c_int32, _dp]
+    lib.gks_state_diagnostics.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_check.argtypes = [_vp, _i64p]
     lib.gks_state_checkpoint_size.argtypes = [_vp, _i64p]
     lib.gks_state_save.argtypes = [_vp, _vp, ctypes.c_int64]
@@ -277,6 +279,32 @@ class State:
         _check(load().gks_state_mass(self._h, int(s), _d(m)))
         return m
 
+    DIAGNOSTICS = ("t", "dt", "mass_upper", "mass_lower", "max_speed_upper", "max_speed_lower",
+                   "spread_eta1", "spread_eta2")
+
+    def diagnostics(self, s=0):
+        """Per-step diagnostics of scenario s from device reductions (see gks_state_diagnostics):
+        time, last step, layer masses, largest layer speeds, spreads of the two levels."""
+        out = np.zeros(8)
+        _check(load().gks_state_diagnostics(self._h, int(s), _d(out)))
+        return dict(zip(self.DIAGNOSTICS, out.tolist()))
+
+    def run_logged(self, n_steps, out, every=1, s=0):
+        """Advance n_steps steps, writing every `every` steps one JSON line of diagnostics of
+        scenario s (plus the share of cells the learned indicator skipped, when it is on) to the
+        text stream `out`; returns the last record."""
+        rec = None
+        done = 0
+        while done < n_steps:
+            k = min(every, n_steps - done)
+            self.step(k)
+            done += k
+            rec = {"step": done, **self.diagnostics(s)}
+            if getattr(self, "_ind_params", None) is not None:
+                rec["skipped_fraction"] = self.indicator_eval()[2] / self.mesh.n_tri
+            out.write(json.dumps(rec) + "\n")
+        return rec
+
     def check(self):
         """First cell updated to a non-finite or non-positive-thickness state, or -1 (no raise)."""
         first = ctypes.c_int64(-1)
@@ -333,6 +361,7 @@ class State:
         """Switch the indicator on (params [7105]) or off (params None) for later stages."""
         if params is None:
             _check(load().gks_indicator_set(self._h, None, 0.0))
+            self._ind_params = None
             return
         self._ind_params = _f32(params)
         if self._ind_params.size != MLP_PARAMS:

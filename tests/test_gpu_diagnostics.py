@@ -6,7 +6,10 @@ checkpoint / restart.
   such cell, which the oracle's own half step with the same size identifies independently, and
   the synchronising calls must report GKS_ENONFINITE.
 * k steps, a checkpoint, a load into a fresh state and k more steps give the bits of 2k steps, in
-  both precisions; a checkpoint does not load into a state of another mesh."""
+  both precisions; a checkpoint does not load into a state of another mesh.
+* The per-step diagnostics (device reductions: masses, layer speeds, level spreads) equal the same
+  quantities computed on the host, are logged as JSON lines, and are at rounding for a lake at
+  rest."""
 import numpy as np
 import pytest
 
@@ -78,3 +81,46 @@ def test_checkpoint_restart_is_bitwise(gks, precision):
     c.stage(0)
     with pytest.raises(gks.GksError):
         c.save()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_device_diagnostics_match_the_state(gks, precision):
+    """gks_state_diagnostics against the same quantities computed on the host from the state it
+    reads back: time, step, masses, largest layer speeds, spreads of the two levels; and on a lake
+    at rest the speeds and spreads stay at rounding (the well-balance residual)."""
+    import io
+    import json
+
+    sc = w.lake_at_rest(20, perturb=1e-2, seed=21)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, precision=precision)
+    buf = io.StringIO()
+    rec = st.run_logged(6, buf, every=3)
+    lines = [json.loads(x) for x in buf.getvalue().splitlines()]
+    assert [x["step"] for x in lines] == [3, 6] and lines[-1] == rec
+    W, _, t = st.read()
+    om = o.Mesh.from_scenario(sc)
+    a, _, _ = om.geometry()
+    t_, dt_ = st.time()
+    eta1 = W[3] + om_bottom_means(sc)
+    eta2 = eta1 + W[0]
+    ref = {"t": t_, "dt": dt_, "mass_upper": float((a * W[0]).sum()), "mass_lower": float((a * W[3]).sum()),
+           "max_speed_upper": float((np.hypot(W[1], W[2]) / W[0]).max()),
+           "max_speed_lower": float((np.hypot(W[4], W[5]) / W[3]).max()),
+           "spread_eta1": float(eta1.max() - eta1.min()), "spread_eta2": float(eta2.max() - eta2.min())}
+    print(f"[diag] {precision}: {rec}", flush=True)
+    for k, v in ref.items():
+        assert abs(rec[k] - v) <= 1e-12 * max(1.0, abs(v)), (k, rec[k], v)
+    assert rec["max_speed_lower"] > 1e-4  # the perturbation moves
+    rest = gks.State.from_scenario(m, w.lake_at_rest(20, seed=21), precision=precision)
+    rest.step(50)
+    d = rest.diagnostics()
+    bound = 1e-13 if precision == "fp64" else 1e-10
+    assert max(d["max_speed_upper"], d["max_speed_lower"], d["spread_eta1"], d["spread_eta2"]) < bound, d
+    with pytest.raises(gks.GksError):
+        st.diagnostics(1)  # a single mesh has scenario 0 only
+
+
+def om_bottom_means(sc):
+    """Cell means of the piecewise-linear bottom (the mean of the three node values)."""
+    return sc.node_B[sc.tri].mean(axis=1)

@@ -173,6 +173,15 @@ gks_status gks_state_mass_noalloc(const gks_state *st, int32_t s, double mass[2]
  * the other synchronising queries (outputs filled first). */
 gks_status gks_state_diagnostics(const gks_state *st, int32_t s, double out[8]);
 
+/* Checked build (compiled with GKS_CHECKED, libgks_checked.so): every index the kernels read from
+ * a mesh table (stencil cells, ghost sources, edge cells and slots, cell edges, scenario and chunk
+ * ranges) is tested against the size of the array it indexes; a miss sets a device flag and the
+ * access falls back to element 0.  gks_debug_bounds synchronises the device and returns the flag
+ * in *violations (1 after any miss, else 0), clearing it if reset != 0.  In the ordinary build it
+ * returns GKS_EUNSUPPORTED with *violations = -1.  A debugging aid for the hot path (the flag is
+ * shared by every state on the device). */
+gks_status gks_debug_bounds(int32_t reset, int32_t *violations);
+
 /* Non-finite detection (a diagnostic of the cell update, Sec. 3.3): every cell update records on
  * the device, without a host round trip, the smallest cell index whose new state has a
  * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B).  gks_state_check

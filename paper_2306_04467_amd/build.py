@@ -20,15 +20,26 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# the checked build: every index the kernels read from a mesh table is tested (gks_debug_bounds)
+LIB_CHECKED = os.path.join(HERE, "libgks_checked.so")
+
+
+def _compile(out: str, extra, verbose: bool):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", LIB + ".tmp", *[os.path.join(CSRC, s) for s in SOURCES]]
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-o", out + ".tmp", *[os.path.join(CSRC, s) for s in SOURCES]]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stderr)
-    os.replace(LIB + ".tmp", LIB)
+    return cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the library and its checked build (in parallel); returns the library's path."""
+    jobs = [(LIB, _compile(LIB, [], verbose)), (LIB_CHECKED, _compile(LIB_CHECKED, ["-DGKS_CHECKED"], verbose))]
+    for out, (cmd, proc) in jobs:
+        _, err = proc.communicate()
+        if proc.returncode != 0:
+            raise RuntimeError("hipcc failed:\n" + err)
+        os.replace(out + ".tmp", out)
     return LIB
 
 

@@ -878,6 +878,27 @@ gks_status gks_state_diagnostics(const gks_state *s, int32_t scen, double out[8]
     });
 }
 
+gks_status gks_debug_bounds(int32_t reset, int32_t *violations)
+{
+    return guarded([&]() -> gks_status {
+#ifdef GKS_CHECKED
+        unsigned int v = 0;
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMemcpyFromSymbol(&v, HIP_SYMBOL(gks::oob_flag), sizeof(v)));
+        if (violations) *violations = (int32_t)v;
+        if (reset) {
+            const unsigned int zero = 0;
+            HIP_OK(hipMemcpyToSymbol(HIP_SYMBOL(gks::oob_flag), &zero, sizeof(zero)));
+        }
+        return GKS_OK;
+#else
+        (void)reset;
+        if (violations) *violations = -1;
+        return fail(GKS_EUNSUPPORTED, "index checks are compiled into the checked build only");
+#endif
+    });
+}
+
 gks_status gks_state_check(const gks_state *s, int64_t *first_bad)
 {
     return guarded([&]() -> gks_status {

@@ -76,6 +76,24 @@ __device__ inline const R *tab(const void *p)
     return static_cast<const R *>(p);
 }
 
+// Checked build (GKS_CHECKED): every index read from a mesh table is tested against the size of
+// the array it indexes before it is used; a miss sets oob_flag and the access falls back to
+// element 0, so the kernel itself stays in bounds.  Other builds take the index as it is.
+#ifdef GKS_CHECKED
+__device__ unsigned int oob_flag;
+__device__ inline int64_t checked_index(int64_t i, int64_t n)
+{
+    if (i < 0 || i >= n) {
+        atomicOr(&oob_flag, 1u);
+        return 0;
+    }
+    return i;
+}
+#define GKS_IX(i, n) ::gks::checked_index((int64_t)(i), (int64_t)(n))
+#else
+#define GKS_IX(i, n) (i)
+#endif
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Cells and edges
 // are numbered with spatial locality, so give each XCD one contiguous range of blocks: neighbour
 // gathers then hit the same L2 instead of being fetched from HBM by several XCDs.
@@ -130,7 +148,7 @@ __global__ void k_ghost_fill(MeshDev m, double *__restrict__ Wh, R *__restrict__
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= m.NG) return;
-    const int64_t TG = m.T + m.NG, s = m.gsrc[g], d = m.T + g, NG = m.NG;
+    const int64_t TG = m.T + m.NG, s = GKS_IX(m.gsrc[g], m.T), d = m.T + g, NG = m.NG;
     // R (a b; c e) maps gradient directions, V (va vb; vc ve) momentum vectors: V = R across a
     // wall, V = I across a free boundary (each component extended evenly)
     const double a = m.gR[g], b = m.gR[NG + g], c = m.gR[2 * NG + g], e = m.gR[3 * NG + g];
@@ -194,7 +212,7 @@ __device__ inline void recon_rhs(const MeshDev &m, const double *__restrict__ Wh
     R *rhs = q.rhs;
     int32_t nb[9];
 #pragma unroll
-    for (int s = 0; s < 9; s++) nb[s] = m.sten[s * T + c];
+    for (int s = 0; s < 9; s++) nb[s] = GKS_IX(m.sten[s * T + c], T + m.NG);
     // the level of the variable's layer (h2, or eta1 for the lower layer), loaded outside the
     // branch so that a wave holding a thickness and a momentum issues it once: a thickness
     // differences it, a momentum takes its layer's thickness from it
@@ -756,7 +774,7 @@ __global__ void k_need(MeshDev m, const R *__restrict__ r0, uint8_t *__restrict_
     bool bad = (double)r0[c] < W_ONE || (double)r0[T + c] < W_ONE;
 #pragma unroll
     for (int l = 0; l < 3; l++) {
-        const int32_t i = m.sten[l * T + c];
+        const int32_t i = GKS_IX(m.sten[l * T + c], T + m.NG);
         if (i < T) bad = bad || (double)r0[i] < W_ONE || (double)r0[T + i] < W_ONE;
     }
     need[c] = bad ? 1 : 0;
@@ -769,9 +787,10 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, co
     int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
     const int64_t T = m.T, E = m.E;
-    const int32_t L = m.eL[e], Rc = m.eR[e], sl = m.eslot[e];
+    const int32_t L = GKS_IX(m.eL[e], m.T), Rc = m.eR[e] >= 0 ? GKS_IX(m.eR[e], m.T) : m.eR[e],
+                  sl = m.eslot[e];
     if (!need[L] && (Rc < 0 || !need[Rc])) return;  // no plane gradient uses this edge
-    const int kL = sl & 3, kR = sl >> 2;
+    const int kL = GKS_IX(sl & 3, 3), kR = GKS_IX(sl >> 2, 3);
     const R *en = tab<R>(m.en);
     const double nx = en[e], ny = en[E + e];
     double acc0 = 0, acc1 = 0;
@@ -821,7 +840,7 @@ __global__ void k_plane(MeshDev m, const uint8_t *__restrict__ need, const doubl
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         const int32_t code = m.cedge[k * T + c];
-        const int64_t e = code >= 0 ? code : ~code;
+        const int64_t e = GKS_IX(code >= 0 ? code : ~code, m.E);
         const double gx = m.gg[(2 * k) * T + c], gy = m.gg[(2 * k + 1) * T + c];
         const double h0 = hmid[e], h1 = hmid[E + e];
         s[0] += gx * h0;
@@ -1135,14 +1154,15 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     const int g = idx & 1, lay = (idx >> 1) & 1;  // lay 0: lower layer (h1), 1: upper (h2)
     if (e >= m.E) return;
     const int64_t T = m.T, E = m.E;
-    const int sc = m.escen ? m.escen[e] : 0;
+    const int sc = m.escen ? (int)GKS_IX(m.escen[e], m.S) : 0;
     const R dt = (R)p.scal[2 * sc];
     // a scenario that has reached its end time takes zero-length steps: nothing to evolve (both
     // lanes of a Gauss-point pair belong to the same edge and leave together)
     if (p.scal[2 * sc] == 0.0) return;
     const R chi = (R)p.chi[sc], G = (R)p.G;
-    const int32_t L = m.eL[e], Rc = m.eR[e], sl = m.eslot[e];
-    const int kL = sl & 3, kR = sl >> 2;
+    const int32_t L = GKS_IX(m.eL[e], m.T), Rc = m.eR[e] >= 0 ? GKS_IX(m.eR[e], m.T) : m.eR[e],
+                  sl = m.eslot[e];
+    const int kL = GKS_IX(sl & 3, 3), kR = GKS_IX(sl >> 2, 3);
     const int sL = 2 * kL + g, sR = 2 * kR + 1 - g;
     const R *en = tab<R>(m.en), *egB = tab<R>(m.egB);
     const R nx = en[e], ny = en[E + e], tx = -ny, ty = nx;
@@ -1306,7 +1326,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     int64_t c = xcd_block() * blockDim.x + threadIdx.x;
     if (c >= m.T) return;
     const int64_t T = m.T, E = m.E, TG = m.T + m.NG;
-    const int sc = m.cscen ? m.cscen[c] : 0;
+    const int sc = m.cscen ? (int)GKS_IX(m.cscen[c], m.S) : 0;
     const double dt = p.scal[2 * sc], G = p.G, chi = p.chi[sc];
     if (dt == 0.0) {
         // the scenario has reached its end time: the state stays as it is (the stage's output is
@@ -1334,7 +1354,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 #pragma unroll
     for (int k = 0; k < 3; k++) {
         const int32_t code = m.cedge[k * T + c];
-        const int64_t e = code >= 0 ? code : ~code;
+        const int64_t e = GKS_IX(code >= 0 ? code : ~code, m.E);
         const double f = m.fl[k * T + c], gx = m.gg[(2 * k) * T + c], gy = m.gg[(2 * k + 1) * T + c];
         const double Hu = eoh[2 * E + e], Hl = eoh[3 * E + e];
         double Wb[6];
@@ -1548,7 +1568,8 @@ __global__ void __launch_bounds__(DT_BLOCK) k_dt_chunk(MeshDev m, Phys p, const 
     __shared__ double sh[DT_BLOCK / 64];
     const int ch = blockIdx.x;
     double smax = 0;
-    for (int64_t c = m.cb[ch] + threadIdx.x; c < m.cb[ch + 1]; c += blockDim.x)
+    const int64_t c0 = GKS_IX(m.cb[ch], m.T + 1), c1 = GKS_IX(m.cb[ch + 1], m.T + 1);
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x)
         smax = fmax(smax, wave_speed(m, p, Wh, Wm, c));
     smax = block_max(smax, sh);
     if (threadIdx.x == 0) part[ch] = smax;
@@ -1558,7 +1579,8 @@ __global__ void __launch_bounds__(64) k_dt_scenario(MeshDev m, Phys p, const dou
 {
     const int s = blockIdx.x;
     double v = 0;
-    for (int i = m.sc0[s] + threadIdx.x; i < m.sc0[s + 1]; i += 64) v = fmax(v, part[i]);
+    const int i0 = (int)GKS_IX(m.sc0[s], m.NCH + 1), i1 = (int)GKS_IX(m.sc0[s + 1], m.NCH + 1);
+    for (int i = i0 + threadIdx.x; i < i1; i += 64) v = fmax(v, part[i]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
     if (threadIdx.x == 0) set_step(m, p, s, v);

@@ -37,7 +37,7 @@ SYMBOLS = ("gks_mesh_create", "gks_mesh_batch", "gks_mesh_destroy", "gks_mesh_in
            "gks_indicator_set", "gks_indicator_eval", "gks_state_features", "gks_state_labels",
            "gks_trainer_create", "gks_trainer_destroy", "gks_trainer_add", "gks_trainer_add_state",
            "gks_trainer_info", "gks_trainer_grad", "gks_trainer_fit", "gks_trainer_params", "gks_trainer_logits",
-           "gks_trainer_threshold", "gks_autotune", "gks_last_error")
+           "gks_trainer_threshold", "gks_autotune", "gks_debug_bounds", "gks_last_error")
 _VOID = ("gks_mesh_destroy", "gks_state_destroy", "gks_trainer_destroy", "gks_last_error")
 MLP_PARAMS, MLP_FEATURES = 7105, 44
 BUFFERS = {"rech": (0, 12, True), "recm": (1, 96, False), "r0": (2, 2, False), "eoh": (3, 6, True),
@@ -93,6 +93,7 @@ def load():
     lib.gks_state_mass_noalloc.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_diagnostics.argtypes = [_vp, ctypes.c_int32, _dp]
     lib.gks_state_check.argtypes = [_vp, _i64p]
+    lib.gks_debug_bounds.argtypes = [ctypes.c_int32, _i32p]
     lib.gks_state_checkpoint_size.argtypes = [_vp, _i64p]
     lib.gks_state_save.argtypes = [_vp, _vp, ctypes.c_int64]
     lib.gks_state_load.argtypes = [_vp, _vp, ctypes.c_int64]
@@ -120,6 +121,14 @@ def load():
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def debug_bounds(reset=False):
+    """Index checks of the checked build (see gks_debug_bounds): 1 after an out-of-range index,
+    else 0; raises GksError(GKS_EUNSUPPORTED) in the ordinary build."""
+    v = ctypes.c_int32()
+    _check(load().gks_debug_bounds(int(bool(reset)), ctypes.byref(v)))
+    return v.value
 
 
 def _check(code):

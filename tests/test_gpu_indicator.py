@@ -339,3 +339,43 @@ def test_indicator_gain_case(gks):
     assert ef <= TOL_FP32_REL_L1, ef
     assert ei <= TOL_FP32_REL_L1, (ei, ef)
     assert np.mean(skipped) > 0.3, skipped
+
+
+def test_indicator_at_full_size(gks):
+    """The gain workload at its full size (2,000,000 triangles, dam break over a bump, FP32): a
+    network trained as in the gain case above, fused into the reconstruction (its first stage
+    infers, the second reuses the decisions), for one step with the oracle's step size; with and
+    without it the state stays within the FP32 bound of the FP64 oracle's step, and the network
+    skips most cells."""
+    P0 = _random_params(21)
+    train = [w.dam_break(24, seed=111), w.lake_at_rest(24, perturb=1e-2, seed=112),
+             w.dam_break(24, seed=113, left=(0.8, 0.6), right=(0.6, 0.8), bump_amp=0.2)]
+    tr = gks.Trainer(sum(sc.n_tri for sc in train) * 6, P0, max_batch=512)
+    for sc in train:
+        st = gks.State.from_scenario(gks.Mesh.from_scenario(sc), sc, precision="fp64")
+        for k in range(6):
+            tr.add_state(st, LABEL_TOL)
+            st.step(5)
+    tr.fit(30, batch=512, lr=2e-3, seed=7)
+    thr, P = tr.threshold(1e-4), tr.params()
+
+    sc = w.dam_break(1000, seed=20230608, sin_amp=0.1, bump_amp=0.2)
+    print(f"[indicator] full size T={sc.n_tri}", flush=True)
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    a, _, _ = om.geometry()
+    m = gks.Mesh.from_scenario(sc)
+    full = gks.State.from_scenario(m, sc, precision="fp32")
+    ind = gks.State.from_scenario(m, sc, precision="fp32")
+    ind.indicator(P, thr)
+    dt = o.dt(om, p, sc.W0)
+    for st in (full, ind):
+        st.stage(0, dt)
+        st.stage(1)
+    W, _ = o.step(om, p, dt, sc.W0, sc.gradW0)
+    _, _, k = ind.indicator_eval()
+    ef = _rel_l1(full.read()[0], W, a).max()
+    ei = _rel_l1(ind.read()[0], W, a).max()
+    print(f"   rel-L1 full {ef:.2e} indicator {ei:.2e} skipped {k / sc.n_tri:.3f}", flush=True)
+    assert ef <= TOL_FP32_REL_L1 and ei <= TOL_FP32_REL_L1, (ef, ei)
+    assert k > 0.5 * sc.n_tri

@@ -105,13 +105,16 @@ typedef struct {
  *   bc, periodic_L[2]     boundary kind; periodic_L = (Lx, Ly) for GKS_BC_PERIODIC, else ignored
  * Setup runs on the host in FP64 (edges, compact stencils of Sec. 3.4 Eq. Recons-stencil with
  * mirror ghost cells at walls, least-squares matrices of Eq. Recons-system) and uploads the
- * result.  Returns GKS_EMESH for a malformed mesh. */
+ * result.  Returns GKS_EMESH for a malformed mesh (bad node index, clockwise or zero-area
+ * triangle, an edge shared by more than two triangles or twice in one direction, unpaired
+ * periodic edges) and GKS_EINVAL for n_tri above 2^29 (cell, edge and Gauss-point record indices
+ * are 32-bit); these checks run on the host before any device call. */
 gks_status gks_mesh_create(const double *node_xy, int64_t n_nodes, const int32_t *tri, int64_t n_tri,
                            const double *node_B, int32_t bc, const double *periodic_L,
                            gks_mesh **out);
 /* Concatenate n independent single meshes into one batch mesh of n scenarios (an ensemble
  * advanced together, each scenario with its own time step).  The inputs stay valid and owned by
- * the caller. */
+ * the caller.  GKS_EINVAL above 2^30 cells and ghost cells in all. */
 gks_status gks_mesh_batch(const gks_mesh *const *meshes, int32_t n, gks_mesh **out);
 void gks_mesh_destroy(gks_mesh *mesh);
 /* sizes: triangles, edges, ghost mirror cells (kept for wall stencils), scenarios; any may be NULL */

@@ -239,6 +239,7 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
     std::unordered_map<uint64_t, int64_t> emap;
     emap.reserve(3 * nt);
     std::vector<int32_t> eL, eR, ekL, ekR;
+    std::vector<uint8_t> eup;  // direction of the edge in its left cell: from the smaller node id
     std::vector<int32_t> cedge(3 * nt);
     for (int64_t c = 0; c < nt; c++)
         for (int k = 0; k < 3; k++) {
@@ -252,6 +253,7 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
             if (it == emap.end()) {
                 int64_t e = (int64_t)eL.size();
                 emap.emplace(key, e);
+                eup.push_back(a < b ? 1 : 0);
                 eL.push_back((int32_t)c);
                 ekL.push_back(k);
                 eR.push_back(-1);
@@ -261,6 +263,11 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
                 int64_t e = it->second;
                 if (eR[e] >= 0) {
                     err = "edge shared by more than two triangles";
+                    return 1;
+                }
+                if ((a < b ? 1 : 0) == eup[e]) {
+                    err = "edge traversed in the same direction by two triangles (overlapping or "
+                          "inconsistently oriented triangles)";
                     return 1;
                 }
                 eR[e] = (int32_t)c;
@@ -304,7 +311,7 @@ int build_host_mesh(const double *xy, int64_t nn, const int32_t *tri, int64_t nt
             eshift[e] = aff_shift(px - rx, py - ry);
             if (std::fabs(rqx + (px - rx) - qx) > 1e-9 * (1 + std::fabs(qx)) ||
                 std::fabs(rqy + (py - ry) - qy) > 1e-9 * (1 + std::fabs(qy))) {
-                err = "periodic edge pair does not match by translation";
+                err = "the two cells of an edge do not share its end points (up to the periodic shift)";
                 return 1;
             }
             gRx = m.gB[eR[e]];

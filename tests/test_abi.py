@@ -56,3 +56,37 @@ def test_null_handles_are_rejected_on_the_host():
     assert lib.gks_stage(vp(), 0, None) == 1
     assert lib.gks_mesh_scenario(vp(), 0, None, None) == 1
     assert lib.gks_trainer_info(vp(), None, None) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_mesh_checks_run_on_the_host():
+    """gks_mesh_create checks its sizes and builds the host mesh before it touches a device: a size
+    above the 32-bit index limit, an unknown boundary kind, clockwise, degenerate and non-manifold
+    triangles are all rejected here, without a GPU (the size check reads no array)."""
+    import numpy as np
+
+    lib = ctypes.CDLL(LIB)
+    lib.gks_last_error.restype = ctypes.c_char_p
+    dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+    lib.gks_mesh_create.argtypes = [dp, ctypes.c_int64, ip, ctypes.c_int64, dp, ctypes.c_int32, dp,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    xy = np.array([[0, 0], [1, 0], [1, 1], [0, 1], [0.5, 0.5]], dtype=np.float64)
+    tri = np.array([[0, 1, 4], [1, 2, 4], [2, 3, 4], [3, 0, 4]], dtype=np.int32)
+    out = ctypes.c_void_p()
+
+    def create(xy_, tri_, n_tri=None, bc=0):
+        return lib.gks_mesh_create(xy_.ctypes.data_as(dp), xy_.shape[0], tri_.ctypes.data_as(ip),
+                                   tri_.shape[0] if n_tri is None else n_tri, None, bc, None, ctypes.byref(out))
+
+    assert create(xy, tri, n_tri=(1 << 29) + 1) == 1 and b"32-bit" in lib.gks_last_error()
+    assert create(xy, tri, bc=7) == 1 and b"boundary" in lib.gks_last_error()
+    assert create(xy, np.ascontiguousarray(tri[:, ::-1])) == 4          # clockwise: GKS_EMESH
+    flat = xy.copy()
+    flat[4] = [0.5, 0.0]
+    assert create(flat, tri) == 4                                        # zero-area triangle
+    over = np.concatenate([tri, [[0, 1, 2]]]).astype(np.int32)
+    assert create(xy, over) == 4 and b"same direction" in lib.gks_last_error()  # overlapping triangles
+    xy3 = np.concatenate([xy, [[0.5, -0.5], [0.5, 0.2]]])
+    three = np.concatenate([tri, [[1, 0, 5], [0, 1, 6]]]).astype(np.int32)
+    assert create(xy3, three) == 4 and b"more than two" in lib.gks_last_error()  # edge 0-1 in three
+    assert not out.value

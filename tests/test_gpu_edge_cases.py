@@ -45,7 +45,7 @@ def test_rejects_malformed_meshes(gks):
     with pytest.raises(gks.GksError) as ei:
         gks.Mesh(xy, tri[:, ::-1].copy())               # clockwise triangles
     assert ei.value.code == GKS_EMESH
-    fan = np.concatenate([tri, [[0, 1, 2]]]).astype(np.int32)  # edge 0-1 shared by three triangles
+    fan = np.concatenate([tri, [[0, 1, 2]]]).astype(np.int32)  # overlaps: edge 0-1 twice in one direction
     with pytest.raises(gks.GksError) as ei:
         gks.Mesh(xy, fan)
     assert ei.value.code == GKS_EMESH

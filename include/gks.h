@@ -207,7 +207,10 @@ gks_status gks_state_checkpoint_size(const gks_state *st, int64_t *bytes);
 gks_status gks_state_save(const gks_state *st, void *blob, int64_t bytes);
 gks_status gks_state_load(gks_state *st, const void *blob, int64_t bytes);
 
-/* Intermediate arrays of the last stage, for tests and inspection tools. */
+/* Intermediate arrays of the last stage, for tests and inspection tools.  After a second stage the
+ * edge arrays hold its mass fluxes, time derivatives, interface thicknesses and coupling values;
+ * the momentum fluxes, hydrostatic terms and interface momenta, which the second update does not
+ * read, are still the first stage's. */
 typedef enum {
     GKS_BUF_RECH = 0,  /* double [6 slots][2][n_tri]: h2 and h1 + B at the cells' Gauss points
                           (slot = 2 * local edge + point, in the cell's counter-clockwise order) */

@@ -193,6 +193,15 @@ void launch_recon(gks_state *s, int stage, hipStream_t st, const double *Whin, c
                            recs_of<R>(s->rec, m.T), (R *)s->r0, src);
 }
 
+template <typename R, int AM, int STAGE>
+void launch_flux(gks_state *s, hipStream_t st)
+{
+    const gks::MeshDev &m = s->md;
+    const int b = s->bs[GKS_KERNEL_FLUX];
+    hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+                       recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+}
+
 template <typename R, int SRC>
 void launch_update(gks_state *s, int stage, hipStream_t st, const double *Whin, const R *Wmin, const R *gWin,
                    double *Whout, R *Wmout, R *gWout)
@@ -239,13 +248,17 @@ void launch_stage(gks_state *s, int stage, hipStream_t st)
         hipLaunchKernelGGL(gks::k_plane, dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->need, s->hmid, s->gP1);
     });
     timed(s, st, GKS_KERNEL_FLUX, [&] {
-        const int b = s->bs[GKS_KERNEL_FLUX];
-        if (s->p.alpha_mode == 0)
-            hipLaunchKernelGGL((gks::k_flux<R, 0>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
-                               recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
-        else
-            hipLaunchKernelGGL((gks::k_flux<R, 1>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
-                               recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+        if (s->p.alpha_mode == 0) {
+            if (stage == 0)
+                launch_flux<R, 0, 0>(s, st);
+            else
+                launch_flux<R, 0, 1>(s, st);
+        } else {
+            if (stage == 0)
+                launch_flux<R, 1, 0>(s, st);
+            else
+                launch_flux<R, 1, 1>(s, st);
+        }
     });
     timed(s, st, GKS_KERNEL_UPDATE, [&] {
         if (s->src4)

@@ -1144,7 +1144,10 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 }
 
 // one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
-template <typename R, int AM>
+// STAGE 1 (the second stage) writes only what the second update reads: the mass fluxes, the time
+// derivatives, the interface thicknesses and the coupling's Gauss-point thicknesses and rates; the
+// momentum fluxes, the hydrostatic terms and the interface momenta keep the first stage's values.
+template <typename R, int AM, int STAGE>
 __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
                                               const R *__restrict__ r0, const double *__restrict__ gP1,
                                               double *__restrict__ eoh, R *__restrict__ eom)
@@ -1287,17 +1290,20 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     for (int i = 0; i < 11; i++) out[i] = R(0.5) * (out[i] + __shfl_xor(out[i], 1));
     const int o = lay == 0 ? 3 : 0;  // paper component offset of this layer
     if (g == 0) {
-        eoh[(int64_t)(lay == 0 ? 1 : 0) * E + e] = P;
+        if constexpr (STAGE == 0) eoh[(int64_t)(lay == 0 ? 1 : 0) * E + e] = P;
         eoh[(int64_t)(lay == 0 ? 3 : 2) * E + e] = H;
         eoh[(int64_t)(lay == 0 ? 5 : 4) * E + e] = Hc;
 #pragma unroll
-        for (int i = 0; i < 3; i++) eom[(int64_t)(o + i) * E + e] = out[i];        // F0
+        for (int i = 0; i < 3; i++)
+            if (STAGE == 0 || i == 0) eom[(int64_t)(o + i) * E + e] = out[i];      // F0
 #pragma unroll
         for (int i = 0; i < 3; i++) eom[(int64_t)(6 + o + i) * E + e] = out[3 + i];  // Ft
     } else {
         const int mo = lay == 0 ? 2 : 0;
-        eom[(int64_t)(12 + mo) * E + e] = out[6];   // Wb momenta
-        eom[(int64_t)(13 + mo) * E + e] = out[7];
+        if constexpr (STAGE == 0) {
+            eom[(int64_t)(12 + mo) * E + e] = out[6];  // Wb momenta
+            eom[(int64_t)(13 + mo) * E + e] = out[7];
+        }
 #pragma unroll
         for (int i = 0; i < 3; i++) eom[(int64_t)(16 + o + i) * E + e] = out[8 + i];  // Wbt
         eom[(int64_t)(lay == 0 ? 23 : 22) * E + e] = Hct;

@@ -345,7 +345,7 @@ def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
     from paper_2306_04467_amd import Mesh, State
 
     t0 = time.time()
-    scs = workloads.ensemble(n_scen)
+    scs = workloads.build_config("C4", n_scen=n_scen)
     T = sum(s.n_tri for s in scs)
     log(f"ensemble: {n_scen} scenarios, {T} triangles built ({time.time() - t0:.1f}s)")
     t0 = time.time()
@@ -408,7 +408,7 @@ def run_c3(steps, warmup, with_error):
     from paper_2306_04467_amd import Mesh, State
 
     t0 = time.time()
-    sc = workloads.dam_break(707, seed=20230605)
+    sc = workloads.build_config("C3")
     mesh = Mesh.from_scenario(sc)
     log(f"dam break: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
     out = {"workload": f"two-layer dam break, jittered Delaunay [0,1]^2, {sc.n_tri} triangles, levels 1.0/0.5 -> "
@@ -511,7 +511,7 @@ def run_indicator(n, steps, warmup, err_n, with_error, trained=None):
 
     P, thr, info = trained if trained is not None else train_indicator()
     t0 = time.time()
-    sc = workloads.dam_break(n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
+    sc = workloads.build_config("C5", n=n)
     mesh = Mesh.from_scenario(sc)
     log(f"gain workload: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
     out = {"workload": f"dam break + bump, jittered Delaunay [0,1]^2, {sc.n_tri} triangles, FP32 mixed",
@@ -541,7 +541,7 @@ def run_indicator(n, steps, warmup, err_n, with_error, trained=None):
     if with_error:
         # the same workload shape on a 520,200-triangle mesh, 20 steps against the oracle on all
         # host cores
-        se = workloads.dam_break(err_n, seed=20230608, sin_amp=0.1, bump_amp=0.2)
+        se = workloads.build_config("C5", n=err_n)
         W1, Wn, dts, tc, threads, _, _ = oracle_run(se, 20)
         m2 = Mesh.from_scenario(se)
         full = gpu_errors(m2, se, "fp32", dts, W1, Wn)
@@ -606,7 +606,7 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    sc = workloads.lake_at_rest(args.n, seed=20230604, perturb=1e-3, disk=(0.3, 0.3, 0.1))
+    sc = workloads.build_config("C2", n=args.n)
     log(f"workload built: {sc.n_tri} triangles ({time.time() - t0:.1f}s)")
     precs = [args.precision] if args.precision else ["fp64", "fp32"]
     res = {}

@@ -973,3 +973,20 @@ def test_higher_order_coupling_source_converges_faster():
     assert min(o4) > 2.7, o4
     assert o4t[1] > 2.7, o4t
     assert e4[-1][0] < 0.3 * e2[-1][0], (e4, e2)
+
+
+def test_configuration_table_builds_the_benchmark_inputs():
+    """The named configurations (workloads.configs) are what the benchmark runs: C1 has the
+    survey's 800 triangles; the others' generators and sizes are fixed by their arguments (2 n^2
+    triangles on the jittered meshes), checked here without building the large meshes."""
+    import json
+
+    sc = w.build_config("C1")
+    assert sc.n_tri == 800 and sc.boundary == "periodic"
+    for name, n_tri in (("C2", 520_200), ("C3", 999_698), ("C5", 2_000_000)):
+        c = w.config_spec(name)
+        assert 2 * c["args"]["n"] ** 2 == n_tri
+    assert w.config_spec("C4")["args"]["n_scen"] == 256
+    json.dumps({k: w.config_spec(k) for k in w.CONFIGS})  # plain data
+    small = w.build_config("C2", n=8)
+    assert small.n_tri == 128 and small.boundary == "wall"

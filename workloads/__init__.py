@@ -23,3 +23,4 @@ from .scenarios import (  # noqa: F401
     circular_interface,
     COMPONENTS,
 )
+from .configs import CONFIGS, build as build_config, spec as config_spec  # noqa: F401,E402

@@ -190,8 +190,8 @@ gks_status gks_debug_bounds(int32_t reset, int32_t *violations);
  * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B).  gks_state_check
  * synchronises and returns GKS_ENONFINITE with *first_bad = that cell (index into the
  * concatenated cells of a batch), or GKS_OK with *first_bad = -1 (first_bad may be NULL).  The
- * synchronising calls gks_state_read, gks_state_time, gks_state_mass and gks_step with dt_last
- * return GKS_ENONFINITE too, after filling their outputs.  The flag stays set until a checkpoint
+ * synchronising calls gks_state_read, gks_state_time, gks_state_mass, gks_state_diagnostics and
+ * gks_step with dt_last return GKS_ENONFINITE too, after filling their outputs.  The flag stays set until a checkpoint
  * taken before the failure is loaded. */
 gks_status gks_state_check(const gks_state *st, int64_t *first_bad);
 

@@ -177,6 +177,11 @@ def kernel_roofline(st, mesh, steps, prec):
         kernels["flux"]["alu"] = {"bound": "alu", "achieved": round(tf, 2), "peak": peak, "unit": "TFLOP/s",
                                   "frac": round(tf / peak, 4), "flops_per_launch": fl,
                                   "source": "profiles/gks_flux_valu_flops_520k.md (SQ_INSTS_VALU_*_F64/F32 x 64)"}
+        if prec == "fp32":
+            # the library is built without packed FP32 instructions, so its FP32 vector peak is the
+            # unpacked rate, equal to the FP64 one
+            kernels["flux"]["alu"]["peak_unpacked"] = FP64_VALU_PEAK_TFLOPS
+            kernels["flux"]["alu"]["frac_unpacked"] = round(tf / FP64_VALU_PEAK_TFLOPS, 4)
     return kernels, roof
 
 

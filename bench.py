@@ -12,8 +12,8 @@ Also reported on the same JSON line: the mixed FP32/FP64 path on the same worklo
 ensemble of 256 independent scenarios (sizes log-uniform in 5k-200k triangles, FP32, steps replayed
 from a HIP graph), each with its relative L1 error against the FP64 oracle; the roofline of the
 dominant kernel (algorithmic bytes / duration measured with HIP events recorded by the library
-around each launch on its stream) and of the whole step (the survey's fused-ideal bytes per
-triangle-stage); the errors after 20 steps against the FP64 oracle run on all host cores, which
+around each launch on its stream) and of the whole step (the fused-ideal bytes per triangle-stage:
+every input and output once, no intermediate arrays); the errors after 20 steps against the FP64 oracle run on all host cores, which
 is also the CPU baseline (plus a single-core sample); the 999,698-triangle dam break timed in both
 precisions; and the FP64 arithmetic of the flux kernel against the vector ALU peak.
 """

@@ -51,7 +51,7 @@ typedef enum {
     GKS_EMESH = 4,        /* malformed mesh (index out of range, inverted or degenerate triangle,
                              edge shared by more than two triangles, unpaired periodic edge) */
     GKS_ENONFINITE = 5,   /* non-finite value or non-positive layer thickness in the state */
-    GKS_EUNSUPPORTED = 6  /* option not available in this build */
+    GKS_EUNSUPPORTED = 6  /* option not compiled into this library */
 } gks_status;
 
 typedef enum {

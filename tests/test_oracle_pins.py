@@ -976,9 +976,10 @@ def test_higher_order_coupling_source_converges_faster():
 
 
 def test_configuration_table_builds_the_benchmark_inputs():
-    """The named configurations (workloads.configs) are what the benchmark runs: C1 has the
-    800 triangles of the small periodic case; the others' generators and sizes are fixed by their arguments (2 n^2
-    triangles on the jittered meshes), checked here without building the large meshes."""
+    """The named configurations (workloads.configs) are what the benchmark runs: C1 has the 800
+    triangles of the small periodic case; the others' generators and sizes are fixed by their
+    arguments (2 n^2 triangles on the jittered meshes), checked here without building the large
+    meshes."""
     import json
 
     sc = w.build_config("C1")

@@ -51,3 +51,30 @@ def test_paper_alpha_mode_lake_at_rest(gks):
     st.step(200)
     W, _, _ = st.read()
     assert np.abs(W[[1, 2, 4, 5]]).max() < 1e-12 and np.abs(W[[0, 3]] - sc.W0[[0, 3]]).max() < 1e-12
+
+
+def test_paper_alpha_mode_mixed_precision(gks):
+    """The paper's constants in the mixed FP32/FP64 path: three steps of a dam break within the mixed
+    path's relative L1 bound of the FP64 oracle in the same mode."""
+    sc = w.dam_break(20, seed=44)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, precision="fp32", alpha_mode="paper")
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, alpha_mode="paper")
+    a, _, _ = om.geometry()
+    Wr, gWr = sc.W0, sc.gradW0
+    for _ in range(3):
+        dt = o.dt(om, p, Wr)
+        st.stage(0, dt)
+        st.stage(1)
+        Wr, gWr = o.step(om, p, dt, Wr, gWr)
+    W, _, _ = st.read()
+    err = []
+    for q in (0, 3):
+        h = Wr[q]
+        err.append((a * np.abs(W[q] - h)).sum() / (a * np.abs(h)).sum())
+        den = (a * h * np.sqrt(sc.G * h)).sum()
+        for v in (q + 1, q + 2):
+            err.append((a * np.abs(W[v] - Wr[v])).sum() / den)
+    print(f"[alpha] paper mode fp32 3 steps: rel-L1 {max(err):.2e}", flush=True)
+    assert max(err) <= 1e-5, err

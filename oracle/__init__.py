@@ -25,7 +25,8 @@ _ip = ctypes.POINTER(ctypes.c_int)
 class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int),
-                ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int), ("src_order", ctypes.c_int)]
+                ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int), ("src_order", ctypes.c_int),
+                ("grad_mode", ctypes.c_int)]
 
 
 def build() -> str:
@@ -58,6 +59,7 @@ def load():
     lib.om_gks_point_integrated.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp]
     lib.om_moments.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp]
     lib.om_time_integrals.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
+    lib.om_side_rate.argtypes = [_dp, ctypes.c_double, _dp]
     lib.om_dt.restype = ctypes.c_double
     lib.om_dt.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp]
     lib.om_operator.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, _dp, _dp,
@@ -196,18 +198,22 @@ ALPHA_MODES = {"reading": 0, "paper": 1}
 
 
 SRC_ORDERS = (2, 4)
+# interface values of the gradient update (Sec. 3.3): the continuous evolution solution (the
+# paper's choice) or each cell's own side of the interface
+GRAD_MODES = {"continuous": 0, "discontinuous": 1}
 
 
 def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False,
-           alpha_mode="reading", src_order=2) -> Params:
+           alpha_mode="reading", src_order=2, grad_mode="continuous") -> Params:
     if src_order not in SRC_ORDERS:
         raise ValueError(f"src_order must be one of {SRC_ORDERS}")
     return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb), ALPHA_MODES[alpha_mode],
-                  int(src_order))
+                  int(src_order), GRAD_MODES[grad_mode])
 
 
-def params_of(sc, linear=False, alpha_mode="reading", src_order=2) -> Params:
-    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode, src_order=src_order)
+def params_of(sc, linear=False, alpha_mode="reading", src_order=2, grad_mode="continuous") -> Params:
+    return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode, src_order=src_order,
+                  grad_mode=grad_mode)
 
 
 def dt(mesh: Mesh, p: Params, W) -> float:
@@ -306,6 +312,13 @@ def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0, alpha_mode="reading")
     load().om_gks_point_mode(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
                              ALPHA_MODES[alpha_mode], _d(F0), _d(Ft), _d(Wb), _d(Wbt))
     return F0, Ft, Wb, Wbt
+
+
+def side_rate(side, G):
+    """(h, hU_n, hU_t)_t of one side's own state from its Maxwellian (om_side_rate)."""
+    out = np.zeros(3)
+    load().om_side_rate(_d(_f64(side)), float(G), _d(out))
+    return out
 
 
 def gks_point_integrated(sideL, sideR, G, delta, tau):

@@ -1183,6 +1183,18 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, int 
     }
 }
 
+void om_side_rate(const double *sd, double G, double *Wt)
+{
+    double h = sd[0], U = sd[1], V = sd[2], lam = 1 / (G * h);
+    double mu[NM], nv[NM];
+    om_moments(U, lam, 0, NM, mu);
+    om_moments(V, lam, 0, NM, nv);
+    poly P;
+    p_micro(&P, lam, h, U, V, sd);
+    p_moment3(&P, 0, h, mu, nv, Wt);
+    for (int k = 0; k < 3; k++) Wt[k] = -Wt[k];
+}
+
 void om_gks_point_integrated(const double *sL, const double *sR, double G, double delta,
                              double tau, double *F)
 {
@@ -1336,8 +1348,8 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     }
 
     /* 3. gas-kinetic evolution at every Gauss point of every edge, both layers */
-    double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 14);
-#define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 14)
+    double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 26);
+#define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 26)
 #pragma omp parallel for schedule(dynamic, 256)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
@@ -1449,6 +1461,21 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
                 const double *a = side[layer][0], *b = side[layer][1];
                 out[12] = 0.5 * (a[0] + b[0]);
                 out[13] = -0.5 * ((a[5] + a[8]) + (b[5] + b[8]));
+                /* the discontinuous reading of the gradient update (Sec. 3.3, the values W^l, W^r
+                 * at the inner sides): each side's own state and its own time derivative, in the
+                 * global frame (14..19 left side, 20..25 right side) */
+                for (int s = 0; s < 2; s++) {
+                    const double *sd = side[layer][s];
+                    double Ws[3] = {sd[0], sd[0] * sd[1], sd[0] * sd[2]}, Wst[3];
+                    om_side_rate(sd, G, Wst);
+                    double *o6 = out + 14 + 6 * s;
+                    o6[0] = Ws[0];
+                    o6[1] = Ws[1] * n[0] + Ws[2] * t[0];
+                    o6[2] = Ws[1] * n[1] + Ws[2] * t[1];
+                    o6[3] = Wst[0];
+                    o6[4] = Wst[1] * n[0] + Wst[2] * t[0];
+                    o6[5] = Wst[1] * n[1] + Wst[2] * t[1];
+                }
             }
         }
     }
@@ -1469,12 +1496,15 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
                 int o = layer == 0 ? 3 : 0;
                 for (int v = 0; v < 3; v++) {
                     double F0 = 0, Ft = 0, Wb = 0, Wbt = 0;
+                    /* interface value of the gradient update: the evolution's W-bar, or the value
+                     * on this cell's own side of the edge */
+                    const int wo = p->grad_mode == 1 ? (sg > 0 ? 14 : 20) : 6;
                     for (int g = 0; g < 2; g++) {
                         const double *q = EO(e, g, layer);
                         F0 += 0.5 * q[v];
                         Ft += 0.5 * q[3 + v];
-                        Wb += 0.5 * q[6 + v];
-                        Wbt += 0.5 * q[9 + v];
+                        Wb += 0.5 * q[wo + v];
+                        Wbt += 0.5 * q[wo + 3 + v];
                     }
                     LF[o + v] -= sg * ln * F0 * inv;
                     LFt[o + v] -= sg * ln * Ft * inv;

@@ -44,6 +44,11 @@ typedef struct {
                         closing remark allows: the cell average in place of the Gauss-point mean
                         plus the interior integral of (h_a - mean h_a) grad h_b over the cell's
                         reconstructions */
+    int grad_mode;   /* interface values of the gradient update (Sec. 3.3, Eq. slope-1): 0 the
+                        continuous evolution solution W^l = W^r (the interface equilibrium's state
+                        and time slope, the paper's choice); 1 discontinuous values W^l != W^r:
+                        each cell takes the state on its own side of the interface, advanced by
+                        that side's own time derivative (om_side_rate) */
 } om_params;
 
 /* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
@@ -103,6 +108,11 @@ void om_gks_point_mode(const double *sideL, const double *sideR, double G, doubl
 /* Same, returning the time-integrated flux F(delta) for one delta (for the closed-form pins). */
 void om_gks_point_integrated(const double *sideL, const double *sideR, double G, double delta,
                              double tau, double *F);
+/* Time derivative (h, hU_n, hU_t)_t of one side's own state (side as in om_gks_point, local
+ * frame) from the compatibility condition on that side's Maxwellian: minus the full-space moments
+ * of its slope and acceleration polynomial (Sec. 2.2).  The inner-side value of the discontinuous
+ * reading of the gradient update (grad_mode 1) evolves with it. */
+void om_side_rate(const double *side, double G, double *Wt);
 /* Normalised moments <u^k>, k = 0..K-1, of the Gaussian with mean U and variance 1/(2 lambda):
  * half = 0 full space, +1 over u > 0, -1 over u < 0. */
 void om_moments(double U, double lam, int half, int K, double *out);

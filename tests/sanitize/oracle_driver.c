@@ -63,9 +63,10 @@ static int run(int periodic)
         W[3 * nt + c] = 0.8 + 0.02 * sin(3 * cx[c]);
         W[4 * nt + c] = 0.01 * cos(2 * cy[c]);
     }
-    /* both alpha modes and both layer-coupling orders: the periodic run takes the paper's
-     * constants and the higher-order coupling */
-    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0, periodic ? 1 : 0, periodic ? 4 : 2};
+    /* both alpha modes, both layer-coupling orders and both gradient-update readings: the
+     * periodic run takes the paper's constants and the higher-order coupling, the wall run the
+     * discontinuous interface values */
+    om_params p = {9.81, 0.95, 0.3, 0.05, 5.0, 0, 0, periodic ? 1 : 0, periodic ? 4 : 2, periodic ? 0 : 1};
     for (int k = 0; k < 3; k++) {
         double dt = om_dt(m, &p, W);
         om_step(m, &p, dt, 2, W, gW, W2, gW2);
@@ -79,6 +80,8 @@ static int run(int periodic)
     om_plane_gradient(m, 0, hk, g2);
     double val[36], grad[72], r0[6];
     om_reconstruct_cell(m, nt / 2, W, gW, 0, 9.81, val, grad, r0);
+    double side[11] = {0.7, 0.2, -0.1, 0.05, -0.02, 0.01, 0.03, -0.04, 0.02, -0.3, 0.1}, st[3];
+    om_side_rate(side, 9.81, st);
     double corr[8];
     om_coupling_correction(m, nt / 2, W, gW, 0, 9.81, corr);
     double *X = calloc((size_t)44 * nt, sizeof(double));
@@ -90,7 +93,7 @@ static int run(int periodic)
     om_mlp_forward(P, X, nt, z);
     om_mlp_forward_bf16(P, X, nt, z);
     ok = ok && isfinite(loss) && finite_all(X, 44L * nt) && finite_all(gr, 7105) && isfinite(mass[0]) &&
-         finite_all(val, 36) && finite_all(g2, 2) && finite_all(corr, 8);
+         finite_all(val, 36) && finite_all(g2, 2) && finite_all(corr, 8) && finite_all(st, 3);
     om_mesh_free(m);
     free(xy); free(B); free(tri); free(W); free(gW); free(W2); free(gW2); free(area); free(cx); free(cy);
     free(X); free(P); free(gr); free(y); free(z);

@@ -96,6 +96,13 @@ typedef struct {
                            (h_a - mean h_a) grad h_b over the cell's reconstructions (Radon's
                            7-point rule), its time derivative with h_t = -div(h U).  Must agree
                            across the scenarios of a batch; other values give GKS_EINVAL */
+    int32_t grad_mode;  /* interface values of the gradient update (Sec. 3.3, Eq. slope-1): 0
+                           (default) the continuous evolution solution W^l = W^r, the interface
+                           equilibrium's state and time slope (the paper's choice); 1 discontinuous
+                           values W^l != W^r: each cell takes the reconstructed state on its own
+                           side of the edge, advanced in time by that side's own rate from the
+                           shallow-water equations (half again as many edge outputs).  Must agree
+                           across a batch; other values give GKS_EINVAL */
 } gks_params;
 
 /* Build a mesh on the current HIP device.

@@ -2,4 +2,4 @@
 water equations on triangular meshes: HIP kernels behind a C ABI (include/gks.h) and a thin
 Python binding."""
 from .gks import (GKS_EINVAL, GKS_ENONFINITE, GKS_EUNSUPPORTED, GKS_OK, GksError, Mesh, State,  # noqa: F401
-                  Trainer, debug_bounds, load)
+                  Trainer, debug_bounds, load, make_params)

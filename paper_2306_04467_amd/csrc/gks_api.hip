@@ -114,6 +114,7 @@ struct gks_state {
     uint8_t *need = nullptr;    // cells whose plane gradient of the force model is used
     unsigned long long *bad = nullptr;  // first cell updated to a non-finite / non-positive state
     bool src4 = false;          // higher-order layer coupling
+    bool gm1 = false;           // discontinuous interface values in the gradient update
     void *src = nullptr;        // its interior correction [8][T] (real), written by the reconstruction
     // threads per block of the edge and cell kernels (per kernel class), chosen by gks_autotune
     int bs[GKS_KERNEL_COUNT] = {256, 192, 256, 256, 256, 256, 256, 256};
@@ -193,28 +194,47 @@ void launch_recon(gks_state *s, int stage, hipStream_t st, const double *Whin, c
                            recs_of<R>(s->rec, m.T), (R *)s->r0, src);
 }
 
-template <typename R, int AM, int STAGE>
-void launch_flux(gks_state *s, hipStream_t st)
+template <typename R, int AM, int STAGE, int GM>
+void launch_flux_gm(gks_state *s, hipStream_t st)
 {
     const gks::MeshDev &m = s->md;
     const int b = s->bs[GKS_KERNEL_FLUX];
-    hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+    hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE, GM>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
                        recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+}
+
+template <typename R, int AM, int STAGE>
+void launch_flux(gks_state *s, hipStream_t st)
+{
+    if (s->gm1)
+        launch_flux_gm<R, AM, STAGE, 1>(s, st);
+    else
+        launch_flux_gm<R, AM, STAGE, 0>(s, st);
+}
+
+template <typename R, int SRC, int GM>
+void launch_update_gm(gks_state *s, int stage, hipStream_t st, const double *Whin, const R *Wmin, const R *gWin,
+                      double *Whout, R *Wmout, R *gWout)
+{
+    const gks::MeshDev &m = s->md;
+    const int b = s->bs[GKS_KERNEL_UPDATE];
+    const R *src = SRC ? (const R *)s->src : nullptr;
+    if (stage == 0)
+        hipLaunchKernelGGL((gks::k_update<R, 0, SRC, GM>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
+    else
+        hipLaunchKernelGGL((gks::k_update<R, 1, SRC, GM>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
+                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
 }
 
 template <typename R, int SRC>
 void launch_update(gks_state *s, int stage, hipStream_t st, const double *Whin, const R *Wmin, const R *gWin,
                    double *Whout, R *Wmout, R *gWout)
 {
-    const gks::MeshDev &m = s->md;
-    const int b = s->bs[GKS_KERNEL_UPDATE];
-    const R *src = SRC ? (const R *)s->src : nullptr;
-    if (stage == 0)
-        hipLaunchKernelGGL((gks::k_update<R, 0, SRC>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
-                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
+    if (s->gm1)
+        launch_update_gm<R, SRC, 1>(s, stage, st, Whin, Wmin, gWin, Whout, Wmout, gWout);
     else
-        hipLaunchKernelGGL((gks::k_update<R, 1, SRC>), dim3(blocks(m.T, b)), dim3(b), 0, st, m, s->p, s->eoh,
-                           (const R *)s->eom, Whin, Wmin, gWin, Whout, Wmout, gWout, s->Wc, (R *)s->Gc, src);
+        launch_update_gm<R, SRC, 0>(s, stage, st, Whin, Wmin, gWin, Whout, Wmout, gWout);
 }
 
 template <typename R>
@@ -547,11 +567,12 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
             if (q.alpha_mode != 0 && q.alpha_mode != 1) return fail(GKS_EINVAL, "unknown alpha_mode");
             if (q.src_order != 0 && q.src_order != 2 && q.src_order != 4)
                 return fail(GKS_EINVAL, "src_order must be 2 (or 0) or 4");
+            if (q.grad_mode != 0 && q.grad_mode != 1) return fail(GKS_EINVAL, "grad_mode must be 0 or 1");
             if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
                 q.precision != prm[0].precision || q.linear != prm[0].linear || q.alpha_mode != prm[0].alpha_mode ||
-                (q.src_order == 4) != (prm[0].src_order == 4))
+                (q.src_order == 4) != (prm[0].src_order == 4) || q.grad_mode != prm[0].grad_mode)
                 return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision, linear, "
-                                        "alpha_mode and src_order");
+                                        "alpha_mode, src_order and grad_mode");
         }
         *out = nullptr;
         const int prec = prm[0].precision;
@@ -581,6 +602,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         s->mesh = mesh;
         s->prec = prec;
         s->src4 = prm[0].src_order == 4;
+        s->gm1 = prm[0].grad_mode == 1;
         s->md = prec == GKS_FP64 ? mesh->d64 : mesh->d32;
         s->stream = (hipStream_t)stream;
         s->nparts = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (T + gks::DT_BLOCK - 1) / gks::DT_BLOCK));
@@ -593,7 +615,8 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
                     {&s->Wm[1], 4 * uTG * rs}, {&s->gW[0], 12 * uTG * rs}, {&s->gW[1], 12 * uTG * rs},
                     {(void **)&s->Wc, 6 * uT * 8}, {&s->Gc, 12 * uT * rs}, {&s->rec, 6 * uT * rec_bytes(prec)},
                     {&s->r0, 2 * uT * rs}, {(void **)&s->hmid, 2 * uE * 8},
-                    {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, 6 * uE * 8}, {&s->eom, 24 * uE * rs},
+                    {(void **)&s->gP1, 4 * uT * 8}, {(void **)&s->need, uT}, {(void **)&s->eoh, (s->gm1 ? 8 : 6) * uE * 8},
+                    {&s->eom, (s->gm1 ? 34 : 24) * uE * rs},
                     {(void **)&s->scal, 2 * uS * 8}, {(void **)&s->part, 2 * (size_t)std::max<int64_t>(std::max(s->nparts, 1024), mesh->d64.NCH) * 8},
                     {(void **)&s->chi, uS * 8}, {(void **)&s->tend, uS * 8}, {(void **)&s->bad, 8},
                     {&s->src, s->src4 ? 8 * uT * rs : 8}};

@@ -1144,7 +1144,23 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
 // STAGE 1 (the second stage) writes only what the second update reads: the mass fluxes, the time
 // derivatives, the interface thicknesses and the coupling's Gauss-point thicknesses and rates; the
 // momentum fluxes, the hydrostatic terms and the interface momenta keep the first stage's values.
-template <typename R, int AM, int STAGE>
+// Time derivative of one side's own state (h, m.n, m.t in the local frame) from the shallow-water
+// equations on that side's data: minus the derivative of the normal and tangential fluxes plus
+// h times the acceleration; the pressure term takes the slope of the level (eta1 for the lower
+// layer, whose bottom slope it contains, h2 for the upper).
+template <typename R>
+__device__ inline void side_rate(const SideL<R> &q, R G, R *o)
+{
+    const R U = q.U, V = q.V, h = q.h;
+    o[0] = -(q.mnn + q.mtt);
+    o[1] = -(R(2) * U * q.mnn - U * U * q.hn + G * h * q.en) - (U * q.mtt + V * q.mnt - U * V * q.ht) + h * q.pn;
+    o[2] = -(U * q.mtn + V * q.mnn - U * V * q.hn) - (R(2) * V * q.mtt - V * V * q.ht + G * h * q.et) + h * q.pt;
+}
+
+// GM = 1: the discontinuous reading of the gradient update: besides the fluxes, each side's own
+// state and time derivative, averaged over the edge's two Gauss points (left side in the rows of
+// the interface state, right side in eoh rows 6-7 and eom rows 24-33)
+template <typename R, int AM, int STAGE, int GM = 0>
 __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
                                               const R *__restrict__ r0, const double *__restrict__ gP1,
                                               double *__restrict__ eoh, R *__restrict__ eom)
@@ -1278,11 +1294,34 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     out[3] = Ft[0];
     out[4] = Ft[1] * nx + Ft[2] * tx;
     out[5] = Ft[1] * ny + Ft[2] * ty;
-    out[6] = Wb[1] * nx + Wb[2] * tx;
-    out[7] = Wb[1] * ny + Wb[2] * ty;
-    out[8] = Wbt[0];
-    out[9] = Wbt[1] * nx + Wbt[2] * tx;
-    out[10] = Wbt[1] * ny + Wbt[2] * ty;
+    R side_out[5];  // GM = 1: the right side's momenta and rates (the left side's go in out[6..10])
+    if constexpr (GM == 1) {
+        H = h64[0];
+        double Hr = h64[1];
+#pragma unroll
+        for (int s = 0; s < 2; s++) {
+            R r[3];
+            side_rate(side[s], G, r);
+            R *o5 = s == 0 ? out + 6 : side_out;
+            const R mn = side[s].h * side[s].U, mt = side[s].h * side[s].V;
+            o5[0] = mn * nx + mt * tx;
+            o5[1] = mn * ny + mt * ty;
+            o5[2] = r[0];
+            o5[3] = r[1] * nx + r[2] * tx;
+            o5[4] = r[1] * ny + r[2] * ty;
+        }
+        H = 0.5 * (H + __shfl_xor(H, 1));
+        Hr = 0.5 * (Hr + __shfl_xor(Hr, 1));
+#pragma unroll
+        for (int i = 0; i < 5; i++) side_out[i] = R(0.5) * (side_out[i] + __shfl_xor(side_out[i], 1));
+        if (g == 0) eoh[(int64_t)(lay == 0 ? 7 : 6) * E + e] = Hr;
+    } else {
+        out[6] = Wb[1] * nx + Wb[2] * tx;
+        out[7] = Wb[1] * ny + Wb[2] * ty;
+        out[8] = Wbt[0];
+        out[9] = Wbt[1] * nx + Wbt[2] * tx;
+        out[10] = Wbt[1] * ny + Wbt[2] * ty;
+    }
 #pragma unroll
     for (int i = 0; i < 11; i++) out[i] = R(0.5) * (out[i] + __shfl_xor(out[i], 1));
     const int o = lay == 0 ? 3 : 0;  // paper component offset of this layer
@@ -1304,6 +1343,14 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 #pragma unroll
         for (int i = 0; i < 3; i++) eom[(int64_t)(16 + o + i) * E + e] = out[8 + i];  // Wbt
         eom[(int64_t)(lay == 0 ? 23 : 22) * E + e] = Hct;
+        if constexpr (GM == 1) {
+            if constexpr (STAGE == 0) {
+                eom[(int64_t)(24 + mo) * E + e] = side_out[0];
+                eom[(int64_t)(25 + mo) * E + e] = side_out[1];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; i++) eom[(int64_t)(28 + o + i) * E + e] = side_out[2 + i];
+        }
     }
 }
 
@@ -1317,7 +1364,9 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
 // hydrostatic terms and the interface momenta
 // SRC = 1: the higher-order layer coupling: the cell-average thickness in place of the Gauss-point
 // mean, its rate from the cell's mass flux, plus the interior correction src[8][T] of k_recon.
-template <typename R, int STAGE, int SRC = 0>
+// GM = 1: the discontinuous reading of the gradient update: a cell takes the interface values of
+// its own side of each edge (the right cell of an edge reads eoh rows 6-7 and eom rows 24-33).
+template <typename R, int STAGE, int SRC = 0, int GM = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_update(MeshDev m, Phys p, const double *__restrict__ eoh,
                                                 const R *__restrict__ eom, const double *__restrict__ Whin,
                                                 const R *__restrict__ Wmin, const R *__restrict__ gWin,
@@ -1359,15 +1408,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         const int32_t code = m.cedge[k * T + c];
         const int64_t e = GKS_IX(code >= 0 ? code : ~code, m.E);
         const double f = m.fl[k * T + c], gx = m.gg[(2 * k) * T + c], gy = m.gg[(2 * k + 1) * T + c];
-        const double Hu = eoh[2 * E + e], Hl = eoh[3 * E + e];
+        // rows of this cell's interface values: shared, or those of its own side (GM = 1)
+        const int64_t ho = (GM == 1 && code < 0) ? 4 * E : 0, mo = (GM == 1 && code < 0) ? 12 * E : 0;
+        const double Hu = eoh[2 * E + ho + e], Hl = eoh[3 * E + ho + e];
         double Wb[6];
         Wb[0] = Hu;
         Wb[3] = Hl;
         if constexpr (stage == 0) {
-            Wb[1] = eom[12 * E + e];
-            Wb[2] = eom[13 * E + e];
-            Wb[4] = eom[14 * E + e];
-            Wb[5] = eom[15 * E + e];
+            Wb[1] = eom[12 * E + mo + e];
+            Wb[2] = eom[13 * E + mo + e];
+            Wb[4] = eom[14 * E + mo + e];
+            Wb[5] = eom[15 * E + mo + e];
         }
 #pragma unroll
         for (int v = 0; v < 6; v++) {
@@ -1378,7 +1429,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 GG[v][1] += gy * Wb[v];
             }
             const double Ft = eom[(int64_t)(6 + v) * E + e];
-            const double Wbt = eom[(int64_t)(16 + v) * E + e];
+            const double Wbt = eom[(int64_t)(16 + v) * E + mo + e];
             LFt[v] -= f * Ft;
             GGt[v][0] += gx * Wbt;
             GGt[v][1] += gy * Wbt;

@@ -55,11 +55,12 @@ class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("t_end", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("linear", ctypes.c_int32), ("alpha_mode", ctypes.c_int32),
-                ("src_order", ctypes.c_int32)]
+                ("src_order", ctypes.c_int32), ("grad_mode", ctypes.c_int32)]
 
 
 ALPHA_MODES = {"reading": 0, "paper": 1}
 SRC_ORDERS = (2, 4)
+GRAD_MODES = {"continuous": 0, "discontinuous": 1}
 
 
 def load():
@@ -213,9 +214,9 @@ class Mesh:
 
 
 def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False,
-                alpha_mode="reading", src_order=2):
+                alpha_mode="reading", src_order=2, grad_mode="continuous"):
     return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear), ALPHA_MODES[alpha_mode],
-                  int(src_order))
+                  int(src_order), GRAD_MODES[grad_mode])
 
 
 class State:
@@ -242,15 +243,17 @@ class State:
 
     @classmethod
     def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, alpha_mode="reading",
-                      src_order=2, **kw):
+                      src_order=2, grad_mode="continuous", **kw):
         p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear,
-                        alpha_mode=alpha_mode, src_order=src_order)
+                        alpha_mode=alpha_mode, src_order=src_order, grad_mode=grad_mode)
         return cls(mesh, sc.W0, sc.gradW0, params=p, **kw)
 
     @classmethod
-    def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, src_order=2, **kw):
+    def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, src_order=2, grad_mode="continuous",
+                       **kw):
         ps = [make_params(G=s.G, chi=s.chi, cfl=s.cfl, t_end=s.t_end if s.t_end < 1e8 else 0.0,
-                          precision=precision, linear=linear, src_order=src_order) for s in scs]
+                          precision=precision, linear=linear, src_order=src_order, grad_mode=grad_mode)
+              for s in scs]
         W0 = np.concatenate([s.W0 for s in scs], axis=1)
         gW0 = np.concatenate([s.gradW0 for s in scs], axis=2)
         return cls(batch_mesh, W0, gW0, params=ps, **kw)

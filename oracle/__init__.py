@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("linear", ctypes.c_int),
                 ("per_side_gb", ctypes.c_int), ("alpha_mode", ctypes.c_int), ("src_order", ctypes.c_int),
-                ("grad_mode", ctypes.c_int)]
+                ("grad_mode", ctypes.c_int), ("h_dry", ctypes.c_double)]
 
 
 def build() -> str:
@@ -60,6 +60,10 @@ def load():
     lib.om_moments.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp]
     lib.om_time_integrals.argtypes = [ctypes.c_double, ctypes.c_double, _dp]
     lib.om_side_rate.argtypes = [_dp, ctypes.c_double, _dp]
+    lib.om_cell_velocity.restype = ctypes.c_double
+    lib.om_cell_velocity.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
+    lib.om_gks_point_wd.argtypes = [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp, _dp, _dp, _dp]
     lib.om_dt.restype = ctypes.c_double
     lib.om_dt.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), _dp]
     lib.om_operator.argtypes = [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_double, _dp, _dp,
@@ -204,16 +208,21 @@ GRAD_MODES = {"continuous": 0, "discontinuous": 1}
 
 
 def params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, linear=False, per_side_gb=False,
-           alpha_mode="reading", src_order=2, grad_mode="continuous") -> Params:
+           alpha_mode="reading", src_order=2, grad_mode="continuous", h_dry=0.0) -> Params:
     if src_order not in SRC_ORDERS:
         raise ValueError(f"src_order must be one of {SRC_ORDERS}")
+    if not h_dry >= 0:
+        raise ValueError("h_dry must be >= 0")
     return Params(G, chi, cfl, eps, eps_num, int(linear), int(per_side_gb), ALPHA_MODES[alpha_mode],
-                  int(src_order), GRAD_MODES[grad_mode])
+                  int(src_order), GRAD_MODES[grad_mode], float(h_dry))
 
 
-def params_of(sc, linear=False, alpha_mode="reading", src_order=2, grad_mode="continuous") -> Params:
+def params_of(sc, linear=False, alpha_mode="reading", src_order=2, grad_mode="continuous", h_dry=None) -> Params:
+    """Parameters of a scenario; h_dry defaults to the scenario's own (0 where it has none)."""
+    if h_dry is None:
+        h_dry = getattr(sc, "h_dry", 0.0)
     return params(G=sc.G, chi=sc.chi, cfl=sc.cfl, linear=linear, alpha_mode=alpha_mode, src_order=src_order,
-                  grad_mode=grad_mode)
+                  grad_mode=grad_mode, h_dry=h_dry)
 
 
 def dt(mesh: Mesh, p: Params, W) -> float:
@@ -311,6 +320,19 @@ def gks_point(sideL, sideR, G, dt_, eps=0.05, eps_num=5.0, alpha_mode="reading")
     F0, Ft, Wb, Wbt = (np.zeros(3) for _ in range(4))
     load().om_gks_point_mode(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
                              ALPHA_MODES[alpha_mode], _d(F0), _d(Ft), _d(Wb), _d(Wbt))
+    return F0, Ft, Wb, Wbt
+
+
+def cell_velocity(h, m, h_dry):
+    """Velocity of a layer cell (om_cell_velocity): m / h, desingularised below h_dry."""
+    return load().om_cell_velocity(float(h), float(m), float(h_dry))
+
+
+def gks_point_wd(sideL, sideR, G, dt_, h_dry, order1=False, eps=0.05, eps_num=5.0, alpha_mode="reading"):
+    sL, sR = _f64(sideL), _f64(sideR)
+    F0, Ft, Wb, Wbt = (np.zeros(3) for _ in range(4))
+    load().om_gks_point_wd(_d(sL), _d(sR), float(G), float(dt_), float(eps), float(eps_num),
+                           ALPHA_MODES[alpha_mode], float(h_dry), int(order1), _d(F0), _d(Ft), _d(Wb), _d(Wbt))
     return F0, Ft, Wb, Wbt
 
 

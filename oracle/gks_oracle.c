@@ -566,6 +566,7 @@ int om_max_threads(void) { return omp_get_max_threads(); }
  * side to the right one, 1/2 erfc(-sqrt(lambda) (unl + unr) / 2). */
 double om_edge_height(double zl, double zr, double hl, double hr, double unl, double unr, double G)
 {
+    if (!(hl + hr > 0)) return 0.5 * (zl + zr); /* both sides dry: no particles to weigh */
     double lamb = 2 / (G * (hl + hr));
     double xi = 0.5 * erfc(-sqrt(lamb) * 0.5 * (unl + unr));
     return xi * zl + (1 - xi) * zr;
@@ -773,8 +774,16 @@ static void coupling_correction(const om_mesh *m, int c, const rfun *rf, double 
         }
 }
 
+double om_cell_velocity(double h, double m, double h_dry)
+{
+    const double hs = OM_THIN * h_dry; /* desingularised below the thin-layer thickness */
+    if (!(h_dry > 0) || h >= hs) return m / h;
+    double h2 = h * h, d2 = hs * hs;
+    return sqrt(2.0) * h * m / sqrt(h2 * h2 + d2 * d2);
+}
+
 static void reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
-                             double *val, double *grad, double *r0, double *corr)
+                             double h_dry, double *val, double *grad, double *r0, double *corr)
 {
     const double dlin = 0.05; /* reading: linear weight of each lower-order candidate */
     rfun rf[NV];
@@ -928,20 +937,52 @@ static void reconstruct_cell(const om_mesh *m, int c, const double *W, const dou
             rf[v].b[s][1] = b[s][1];
         }
     }
+    /* wet/dry reading: in the front band of a layer -- the cell or one of its face neighbours has
+     * that layer thinner than OM_THIN h_dry -- the layer is reconstructed as its cell average,
+     * thickness constant (the lower layer's level then follows the bottom) and momentum the
+     * thickness times the cell's desingularised velocity, all gradients at the Gauss points those
+     * of these constant fields.  Its high-order weight ratio r0 is set to 0 (never 0 otherwise):
+     * the force model then takes the plane gradient at its edges, and the evolution there is of
+     * first order in space and time */
+    if (h_dry > 0)
+        for (int o = 0; o < NV; o += 3) {
+            double hbar = o == 0 ? q[0][0] : q[0][3] - m->Bbar[c];
+            double hk[4], hmax = 0;
+            for (int l = 0; l < 4; l++) {
+                int n = m->st_cell[NS * c + l];
+                hk[l] = o == 0 ? q[l][0] : q[l][3] - m->Bbar[n];
+                hmax = fmax(hmax, hk[l]);
+            }
+            int band = 0;
+            for (int l = 0; l < 4; l++) band |= hk[l] < OM_THIN * h_dry || hk[l] < OM_FRONT * hmax;
+            if (!band) continue;
+            double Uc = om_cell_velocity(hbar, q[0][o + 1], h_dry), Vc = om_cell_velocity(hbar, q[0][o + 2], h_dry);
+            for (int p = 0; p < 6; p++) {
+                double bdev = o == 3 ? m->Bx[c] * (gp[p][0] - x0[0]) + m->By[c] * (gp[p][1] - x0[1]) : 0.0;
+                val[p * NV + o] = q[0][o] + bdev;
+                val[p * NV + o + 1] = hbar * Uc;
+                val[p * NV + o + 2] = hbar * Vc;
+                grad[(p * NV + o) * 2] = o == 3 ? m->Bx[c] : 0.0;
+                grad[(p * NV + o) * 2 + 1] = o == 3 ? m->By[c] : 0.0;
+                for (int k = 2; k < 6; k++) grad[(p * NV + o) * 2 + k] = 0.0;
+            }
+            for (int v = o; v < o + 3; v++) rf[v].theta = 0.0;
+            r0[o] = 0.0;
+        }
     if (corr) coupling_correction(m, c, rf, corr);
 }
 
 void om_reconstruct_cell(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                          double *val, double *grad, double *r0)
 {
-    reconstruct_cell(m, c, W, gW, linear, G, val, grad, r0, NULL);
+    reconstruct_cell(m, c, W, gW, linear, G, 0.0, val, grad, r0, NULL);
 }
 
 void om_coupling_correction(const om_mesh *m, int c, const double *W, const double *gW, int linear, double G,
                             double *corr)
 {
     double val[36], grad[72], r0[6];
-    reconstruct_cell(m, c, W, gW, linear, G, val, grad, r0, corr);
+    reconstruct_cell(m, c, W, gW, linear, G, 0.0, val, grad, r0, corr);
 }
 
 /* ----------------------------------------------------------------------------------------- */
@@ -1107,16 +1148,21 @@ static void alpha_paper(const double *sL, const double *sR, double G, double lam
     p_moment3(&FR, 1, hb, mubm, nvb, rm);
     for (int k = 0; k < 3; k++) d2[k] = (ALPHA_PAPER[k] - 1) * (lp[k] + rm[k]);
     double hL = sL[0], UL = sL[1], VL = sL[2], hR = sR[0], UR = sR[1], VR = sR[2];
-    double lamL = 1 / (G * hL), lamR = 1 / (G * hR);
-    double muLp[NM], muRm[NM], nvL[NM], nvR[NM];
-    om_moments(UL, lamL, +1, NM, muLp);
-    om_moments(UR, lamR, -1, NM, muRm);
-    om_moments(VL, lamL, 0, NM, nvL);
-    om_moments(VR, lamR, 0, NM, nvR);
-    p_micro(&FL, lamL, hL, UL, VL, fL); /* acceleration over each side's own Maxwellian */
-    p_micro(&FR, lamR, hR, UR, VR, fR);
-    p_moment3(&FL, 1, hL, muLp, nvL, lp);
-    p_moment3(&FR, 1, hR, muRm, nvR, rm);
+    for (int k = 0; k < 3; k++) lp[k] = rm[k] = 0; /* a vacuum side has no particles */
+    if (hL > 0) {
+        double lamL = 1 / (G * hL), muLp[NM], nvL[NM];
+        om_moments(UL, lamL, +1, NM, muLp);
+        om_moments(VL, lamL, 0, NM, nvL);
+        p_micro(&FL, lamL, hL, UL, VL, fL); /* acceleration over each side's own Maxwellian */
+        p_moment3(&FL, 1, hL, muLp, nvL, lp);
+    }
+    if (hR > 0) {
+        double lamR = 1 / (G * hR), muRm[NM], nvR[NM];
+        om_moments(UR, lamR, -1, NM, muRm);
+        om_moments(VR, lamR, 0, NM, nvR);
+        p_micro(&FR, lamR, hR, UR, VR, fR);
+        p_moment3(&FR, 1, hR, muRm, nvR, rm);
+    }
     for (int k = 0; k < 3; k++) d5[k] = (ALPHA_PAPER[k] - 1) * (lp[k] + rm[k]);
 }
 
@@ -1124,17 +1170,27 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, int 
 {
     double hL = sL[0], UL = sL[1], VL = sL[2];
     double hR = sR[0], UR = sR[1], VR = sR[2];
-    double lamL = 1 / (G * hL), lamR = 1 / (G * hR);
-    double muLp[NM], muRm[NM], nvL[NM], nvR[NM];
-    om_moments(UL, lamL, +1, NM, muLp);
-    om_moments(UR, lamR, -1, NM, muRm);
-    om_moments(VL, lamL, 0, NM, nvL);
-    om_moments(VR, lamR, 0, NM, nvR);
+    /* a side at zero thickness is a vacuum: its moments are zero (its record is all zeros) */
+    const int wetL = hL > 0, wetR = hR > 0;
+    double lamL = wetL ? 1 / (G * hL) : 0, lamR = wetR ? 1 / (G * hR) : 0;
+    double muLp[NM] = {0}, muRm[NM] = {0}, nvL[NM] = {0}, nvR[NM] = {0};
+    if (wetL) {
+        om_moments(UL, lamL, +1, NM, muLp);
+        om_moments(VL, lamL, 0, NM, nvL);
+    }
+    if (wetR) {
+        om_moments(UR, lamR, -1, NM, muRm);
+        om_moments(VR, lamR, 0, NM, nvR);
+    }
     /* interface state: particles from the left moving right plus from the right moving left */
     double Wb[3];
     Wb[0] = hL * muLp[0] + hR * muRm[0];
     Wb[1] = hL * muLp[1] + hR * muRm[1];
     Wb[2] = hL * muLp[0] * VL + hR * muRm[0] * VR;
+    if (!(Wb[0] > 0)) { /* no particles at the interface */
+        memset(o, 0, sizeof(*o));
+        return;
+    }
     double hb = Wb[0], Ub = Wb[1] / hb, Vb = Wb[2] / hb, lamb = 1 / (G * hb);
     double mub[NM], mubp[NM], mubm[NM], nvb[NM];
     om_moments(Ub, lamb, 0, NM, mub);
@@ -1145,8 +1201,14 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, int 
     poly PbL, PbR, PL, PR, one;
     p_micro(&PbL, lamb, hb, Ub, Vb, sL);
     p_micro(&PbR, lamb, hb, Ub, Vb, sR);
-    p_micro(&PL, lamL, hL, UL, VL, sL);
-    p_micro(&PR, lamR, hR, UR, VR, sR);
+    if (wetL)
+        p_micro(&PL, lamL, hL, UL, VL, sL);
+    else
+        p_zero(&PL);
+    if (wetR)
+        p_micro(&PR, lamR, hR, UR, VR, sR);
+    else
+        p_zero(&PR);
     p_zero(&one);
     one.c[0][0] = 1;
     /* time slope of the interface equilibrium from compatibility */
@@ -1185,6 +1247,10 @@ static void gks_brackets_eval(const double *sL, const double *sR, double G, int 
 
 void om_side_rate(const double *sd, double G, double *Wt)
 {
+    if (!(sd[0] > 0)) { /* a vacuum side */
+        Wt[0] = Wt[1] = Wt[2] = 0;
+        return;
+    }
     double h = sd[0], U = sd[1], V = sd[2], lam = 1 / (G * h);
     double mu[NM], nv[NM];
     om_moments(U, lam, 0, NM, mu);
@@ -1211,8 +1277,19 @@ void om_gks_point_integrated(const double *sL, const double *sR, double G, doubl
 void om_gks_point_mode(const double *sL, const double *sR, double G, double dt, double eps,
                        double eps_num, int alpha_mode, double *F0, double *Ft, double *Wb, double *Wbt)
 {
+    om_gks_point_wd(sL, sR, G, dt, eps, eps_num, alpha_mode, 0.0, 0, F0, Ft, Wb, Wbt);
+}
+
+void om_gks_point_wd(const double *sL, const double *sR, double G, double dt, double eps,
+                     double eps_num, int alpha_mode, double h_dry, int order1, double *F0, double *Ft,
+                     double *Wb, double *Wbt)
+{
     gks_brackets br;
     gks_brackets_eval(sL, sR, G, alpha_mode, &br);
+    if (!(br.Wb[0] > h_dry)) { /* a dry interface passes nothing */
+        for (int k = 0; k < 3; k++) F0[k] = Ft[k] = Wb[k] = Wbt[k] = 0;
+        return;
+    }
     /* collision time with the pressure-jump term (Sec. 4) */
     double pl = sL[0] * sL[0], pr = sR[0] * sR[0];
     double tau = eps * dt + eps_num * fabs((pl - pr) / (pl + pr)) * dt;
@@ -1225,9 +1302,10 @@ void om_gks_point_mode(const double *sL, const double *sR, double G, double dt, 
             F1[k] += g1[i] * br.B[i][k];
             F2[k] += g2[i] * br.B[i][k];
         }
-        /* flux and its time derivative from F(dt) and F(dt/2) for a linear-in-time flux */
-        F0[k] = (4 * F2[k] - F1[k]) / dt;
-        Ft[k] = 4 * (F1[k] - 2 * F2[k]) / (dt * dt);
+        /* flux and its time derivative from F(dt) and F(dt/2) for a linear-in-time flux; at first
+         * order the step's mean flux with no time derivative */
+        F0[k] = order1 ? F1[k] / dt : (4 * F2[k] - F1[k]) / dt;
+        Ft[k] = order1 ? 0.0 : 4 * (F1[k] - 2 * F2[k]) / (dt * dt);
         Wb[k] = br.Wb[k];
         Wbt[k] = br.Wbt[k];
     }
@@ -1250,8 +1328,10 @@ double om_dt(const om_mesh *m, const om_params *p, const double *W)
         if (m->dX[c] < dxmin) dxmin = m->dX[c];
         for (int layer = 0; layer < 2; layer++) {
             int o = 3 * layer;
-            double h = W[o * T + c], U = W[(o + 1) * T + c] / h, V = W[(o + 2) * T + c] / h;
-            double s = sqrt(U * U + V * V) + sqrt(p->G * h);
+            double h = W[o * T + c];
+            double U = om_cell_velocity(h, W[(o + 1) * T + c], p->h_dry);
+            double V = om_cell_velocity(h, W[(o + 2) * T + c], p->h_dry);
+            double s = sqrt(U * U + V * V) + sqrt(p->G * fmax(h, 0.0)); /* a dry cell may hold -0 */
             if (s > smax) smax = s;
         }
     }
@@ -1300,7 +1380,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     double *corr = src4 ? (double *)malloc(sizeof(double) * (size_t)T * 8) : NULL;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int c = 0; c < T; c++)
-        reconstruct_cell(m, c, W, gW, p->linear, p->G, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6,
+        reconstruct_cell(m, c, W, gW, p->linear, p->G, p->h_dry, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6,
                          src4 ? corr + (size_t)c * 8 : NULL);
 
     /* side records of edge e, Gauss point g (edge orientation), side s: pointers or mirrors */
@@ -1328,8 +1408,9 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
             for (int f = 0; f < 2; f++) {
                 int o = f == 0 ? 3 : 0; /* eta1 lives in slot 3, h2 in slot 0 */
                 double hl = f == 0 ? vl[3] - Bg : vl[0], hr = f == 0 ? vr[3] - Bg : vr[0];
-                double unl = (vl[o + 1] * n[0] + vl[o + 2] * n[1]) / hl;
-                double unr = (vr[o + 1] * n[0] + vr[o + 2] * n[1]) / hr;
+                /* a dry side (wet/dry reading) has no velocity */
+                double unl = hl > p->h_dry && hl > 0 ? (vl[o + 1] * n[0] + vl[o + 2] * n[1]) / hl : 0.0;
+                double unr = hr > p->h_dry && hr > 0 ? (vr[o + 1] * n[0] + vr[o + 2] * n[1]) / hr : 0.0;
                 acc[f] += 0.5 * om_edge_height(vl[o], vr[o], hl, hr, unl, unr, G);
             }
         }
@@ -1424,6 +1505,10 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
                     const double *phi = layer == 0 ? phi1 : phi2;
                     double mx = vs[s][o + 1], my = vs[s][o + 2];
                     double *sd = side[layer][s];
+                    if (p->h_dry > 0 && !(h > p->h_dry)) { /* wet/dry reading: a dry side is a vacuum */
+                        for (int i = 0; i < 11; i++) sd[i] = 0.0;
+                        continue;
+                    }
                     sd[0] = h;
                     sd[1] = (mx * n[0] + my * n[1]) / h;
                     sd[2] = (mx * t[0] + my * t[1]) / h;
@@ -1441,9 +1526,16 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
                 }
             }
             for (int layer = 0; layer < 2; layer++) {
+                /* wet/dry reading: at an edge of the layer's front band (r0 = 0 on either side) the
+                 * evolution is of first order: the sides' states alone, no slopes, no acceleration,
+                 * and the step's mean flux */
+                const int order1 = p->h_dry > 0 && (rL[layer] == 0.0 || rR[layer] == 0.0);
+                if (order1)
+                    for (int s = 0; s < 2; s++)
+                        for (int i = 3; i < 11; i++) side[layer][s][i] = 0.0;
                 double F0[3], Ft[3], Wb[3], Wbt[3];
-                om_gks_point_mode(side[layer][0], side[layer][1], G, dt, p->eps, p->eps_num, p->alpha_mode, F0,
-                                  Ft, Wb, Wbt);
+                om_gks_point_wd(side[layer][0], side[layer][1], G, dt, p->eps, p->eps_num, p->alpha_mode,
+                                p->h_dry, order1, F0, Ft, Wb, Wbt);
                 if (R < 0 && !m->free_bc) { /* reflecting wall: no mass crosses */
                     F0[0] = 0;
                     Ft[0] = 0;

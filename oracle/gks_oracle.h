@@ -49,6 +49,13 @@ typedef struct {
                         and time slope, the paper's choice); 1 discontinuous values W^l != W^r:
                         each cell takes the state on its own side of the interface, advanced by
                         that side's own time derivative (om_side_rate) */
+    double h_dry;    /* wet/dry layers (a vanishing layer, Sec. 4's dam breaks over a dry bed; the
+                        paper gives no treatment, this is a reading): 0 (off) the scheme as above;
+                        > 0 a layer thickness at or below h_dry is dry.  A dry side of an interface
+                        carries no particles (vacuum), an interface whose equilibrium thickness is
+                        at or below h_dry passes nothing, and a layer thinner than OM_THIN h_dry in
+                        a cell is reconstructed as its constant cell average with the cell's
+                        desingularised velocity (om_cell_velocity), at first order */
 } om_params;
 
 /* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
@@ -86,6 +93,10 @@ void om_lsq_matrix(const om_mesh *m, int c, double *M);
 /* Smallest sine of the angle between the two centroid offsets of a plane candidate of the
  * nonlinear reconstruction (a sub-stencil {0, i, j}); flatter sub-stencils are not candidates. */
 #define OM_PLANE_SINE_MIN 0.2
+/* a layer thinner than OM_THIN h_dry in a cell is reconstructed at first order (h_dry > 0) */
+#define OM_THIN 1000.0
+/* ... or thinner than OM_FRONT times the thickest of the cell and its face neighbours */
+#define OM_FRONT 0.3
 
 /* Reconstruction of all six variables in cell c (with eta1 = h1 + B in place of h1) at the cell's
  * six Gauss points (local edge k, point g -> index 2k+g):
@@ -108,6 +119,18 @@ void om_gks_point_mode(const double *sideL, const double *sideR, double G, doubl
 /* Same, returning the time-integrated flux F(delta) for one delta (for the closed-form pins). */
 void om_gks_point_integrated(const double *sideL, const double *sideR, double G, double delta,
                              double tau, double *F);
+/* Velocity of a layer with cell-average thickness h and momentum component m: m / h where h is at
+ * least h_dry (or h_dry is 0); below it the desingularised form sqrt(2) h m / sqrt(h^4 + h_dry^4)
+ * (Kurganov and Petrova 2007), which tends to zero with h. */
+double om_cell_velocity(double h, double m, double h_dry);
+/* The evolution at one Gauss point with wet/dry sides (h_dry as in om_params): a side whose
+ * thickness is at or below zero is a vacuum (the caller zeroes a dry side's record), and an
+ * interface whose equilibrium thickness is at or below h_dry gives zero fluxes and interface values.
+ * order1 != 0: first order in time, F0 the step's mean flux F(dt) / dt and Ft = 0 (the caller
+ * zeroes the sides' slopes and accelerations for first order in space). */
+void om_gks_point_wd(const double *sideL, const double *sideR, double G, double dt, double eps,
+                     double eps_num, int alpha_mode, double h_dry, int order1, double *F0, double *Ft,
+                     double *Wb, double *Wbt);
 /* Time derivative (h, hU_n, hU_t)_t of one side's own state (side as in om_gks_point, local
  * frame) from the compatibility condition on that side's Maxwellian: minus the full-space moments
  * of its slope and acceleration polynomial (Sec. 2.2).  The inner-side value of the discontinuous

@@ -21,6 +21,9 @@ from .scenarios import (  # noqa: F401
     riemann_exchange,
     riemann_interface,
     circular_interface,
+    dam_break_dry,
+    ritter_channel,
+    dam_break_breach,
     COMPONENTS,
 )
 from .configs import CONFIGS, build as build_config, spec as config_spec  # noqa: F401,E402

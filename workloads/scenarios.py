@@ -35,6 +35,7 @@ class Scenario:
     W0: np.ndarray               # [6, T]
     gradW0: np.ndarray           # [6, 2, T]
     exact: Optional[Callable] = None  # exact(t) -> W cell averages [6, T] when known
+    h_dry: float = 0.0           # wet/dry threshold of the scheme (0: every layer wet everywhere)
 
     @property
     def n_tri(self) -> int:
@@ -292,7 +293,7 @@ def dam_break(n: int, seed: int = 20230605, chi: float = 0.95, x_dam: float = 0.
     return _level_state(f"dam_break_n{n}", xy, tri, node_B, chi, cfl, t_end, G, levels, 0.0, None)
 
 
-def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, disk):
+def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, disk, h_dry=0.0):
     T = tri.shape[0]
     Bm, Bx, By = _p1_bottom(xy, tri, node_B)
     c = xy[tri].mean(axis=1)
@@ -310,9 +311,92 @@ def _level_state(name, xy, tri, node_B, chi, cfl, t_end, G, levels, perturb, dis
     W0[3] = eta1 - Bm
     gW0[3, 0] = -Bx
     gW0[3, 1] = -By
-    if (W0[3] <= 0).any() or (W0[0] <= 0).any():
+    if h_dry > 0:
+        if (W0[3] < 0).any() or (W0[0] < 0).any():
+            raise ValueError("negative layer thickness in initial data")
+    elif (W0[3] <= 0).any() or (W0[0] <= 0).any():
         raise ValueError("non-positive layer thickness in initial data")
-    return Scenario(name, xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0)
+    return Scenario(name, xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0, gW0, h_dry=h_dry)
+
+
+# ---------------------------------------------------------------------------------------------
+# vanishing layers (wet/dry)
+
+def dam_break_dry(n: int = 100, seed: int = 20230607, chi: float = 1.0, h_dry: float = 1e-6, cfl: float = 0.3,
+                  t_end: float = 0.08, G: float = 9.81) -> Scenario:
+    """The paper's two-layer dam break (Sec. 4, dam-break problems at density ratios 1 and 0.2):
+    [0, 1] x [0, 0.5], flat bottom, walls, at rest; lower layer 0.357 everywhere, upper layer 1 for
+    x < 0.5 and dry (0) beyond; jittered Delaunay mesh of cell size 1/n."""
+    xy, tri = jittered_rect(n, max(n // 2, 2), 1.0, 0.5, seed)
+
+    def levels(cx, cy):
+        return np.full_like(cx, 0.357), np.where(cx < 0.5, 1.0, 0.0)
+
+    return _level_state(f"dam_break_dry_n{n}", xy, tri, np.zeros(xy.shape[0]), chi, cfl, t_end, G, levels,
+                        0.0, None, h_dry=h_dry)
+
+
+def _ritter(x, t, h0, x0, G):
+    """Ritter's dam break onto a dry bed: thickness and velocity of the single-layer equations."""
+    c0 = math.sqrt(G * h0)
+    xi = (np.asarray(x, dtype=np.float64) - x0) / t
+    h = np.where(xi <= -c0, h0, np.where(xi >= 2 * c0, 0.0, (2 * c0 - xi) ** 2 / (9 * G)))
+    u = np.where(xi <= -c0, 0.0, np.where(xi >= 2 * c0, 0.0, 2.0 / 3.0 * (c0 + xi)))
+    return h, u
+
+
+def ritter_channel(n: int = 200, layer: str = "lower", seed: int = 20230608, h0: float = 1.0, x0: float = 1.0,
+                   h_dry: float = 1e-6, chi: float = 0.98, cfl: float = 0.3, t_end: float = 0.1,
+                   G: float = 9.81) -> Scenario:
+    """A single-layer dam break onto a dry bed in the two-layer system: one layer (``layer``) is h0
+    for x < x0 and dry beyond, the other layer is dry everywhere, flat bottom, walls, channel
+    [0, 2] x [0, 0.2] (jittered mesh, cell size 2/n).  With the other layer absent the equations
+    are the single-layer ones, whose solution is Ritter's: exact(t) gives its cell averages."""
+    xy, tri = jittered_rect(n, max(n // 10, 2), 2.0, 0.2, seed)
+    T = tri.shape[0]
+    c = xy[tri].mean(axis=1)
+    o = 3 if layer == "lower" else 0
+    W0 = np.zeros((6, T))
+    W0[o] = np.where(c[:, 0] < x0, h0, 0.0)
+
+    def exact(t):
+        W = np.zeros((6, T))
+        if t <= 0:
+            W[o] = W0[o]
+            return W
+        W[o] = cell_average(xy, tri, lambda x, y: _ritter(x, t, h0, x0, G)[0], q=12)
+        W[o + 1] = cell_average(xy, tri, lambda x, y: np.prod(_ritter(x, t, h0, x0, G), axis=0), q=12)
+        return W
+
+    return Scenario(f"ritter_{layer}_n{n}", xy, tri, np.zeros(xy.shape[0]), "wall", None, G, chi, cfl, t_end,
+                    W0, np.zeros((6, 2, T)), exact=exact, h_dry=h_dry)
+
+
+def dam_break_breach(kind: str = "dry", n: int = 80, seed: int = 20230609, chi: float = 0.98, h_dry: float = 1e-6,
+                     cfl: float = 0.3, t_end: float = 7.2, G: float = 9.81) -> Scenario:
+    """A stand-in for the paper's 2-D dam break in an irregular domain (Sec. 4): a dam of width 10
+    whose left side is at x = 95, with a breach of length 75 starting at y = 95, in a flat-bottom
+    basin [0, 260] x [0, 200] (the far wall is beyond the reach of a dry-bed front, speed at most
+    2 sqrt(G 10), by t = 7.2); jittered mesh of cell size 200/n with the dam's triangles removed,
+    walls.  Lower / upper thicknesses (9, 1) for x < 95 and, beyond, (5, 0) for the wet bed or
+    (1e-3, 1e-3) for the dry one."""
+    xy, tri = jittered_rect(int(round(1.3 * n)), n, 260.0, 200.0, seed)
+    c = xy[tri].mean(axis=1)
+    dam = (c[:, 0] > 95.0) & (c[:, 0] < 105.0) & ~((c[:, 1] > 95.0) & (c[:, 1] < 170.0))
+    tri = tri[~dam]
+    used = np.unique(tri)
+    remap = np.full(xy.shape[0], -1, dtype=np.int64)
+    remap[used] = np.arange(used.size)
+    xy = xy[used]
+    tri = remap[tri].astype(np.int32)
+    right = (5.0, 0.0) if kind == "wet" else (1e-3, 1e-3)
+
+    def levels(cx, cy):
+        left = cx < 95.0
+        return np.where(left, 9.0, right[0]), np.where(left, 1.0, right[1])
+
+    return _level_state(f"dam_break_breach_{kind}_n{n}", xy, tri, np.zeros(xy.shape[0]), chi, cfl, t_end, G,
+                        levels, 0.0, None, h_dry=h_dry)
 
 
 def riemann_exchange(n: int = 100, chi: float = 0.98, cfl: float = 0.3, t_end: float = 0.1,

@@ -103,6 +103,17 @@ typedef struct {
                            side of the edge, advanced in time by that side's own rate from the
                            shallow-water equations (half again as many edge outputs).  Must agree
                            across a batch; other values give GKS_EINVAL */
+    double h_dry;       /* wet/dry layers (a layer that vanishes, as in the paper's dam breaks over
+                           a dry bed, Sec. 4; the paper gives no treatment, this is a reading): 0
+                           (default) every layer must stay wet (thickness > 0); > 0 a thickness may
+                           be 0.  A side of an interface at or below h_dry is a vacuum, an
+                           interface whose equilibrium thickness is at or below h_dry passes
+                           nothing, and in a layer's front band (the cell or a face neighbour
+                           thinner than 1000 h_dry or than 0.3 times the thickest of the four) the
+                           layer is reconstructed as its cell average with the cell's velocity
+                           desingularised below 1000 h_dry, and evolves at first order in space
+                           and time.  Must agree across a batch; needs src_order 2 and no learned
+                           indicator; negative or non-finite values give GKS_EINVAL */
 } gks_params;
 
 /* Build a mesh on the current HIP device.

@@ -199,8 +199,12 @@ void launch_flux_gm(gks_state *s, hipStream_t st)
 {
     const gks::MeshDev &m = s->md;
     const int b = s->bs[GKS_KERNEL_FLUX];
-    hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE, GM>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
-                       recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+    if (s->p.h_dry > 0)
+        hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE, GM, 1>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+                           recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
+    else
+        hipLaunchKernelGGL((gks::k_flux<R, AM, STAGE, GM, 0>), dim3(blocks(4 * m.E, b)), dim3(b), 0, st, m, s->p,
+                           recs_of<R>(s->rec, m.T), (const R *)s->r0, s->gP1, s->eoh, (R *)s->eom);
 }
 
 template <typename R, int AM, int STAGE>
@@ -568,11 +572,15 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
             if (q.src_order != 0 && q.src_order != 2 && q.src_order != 4)
                 return fail(GKS_EINVAL, "src_order must be 2 (or 0) or 4");
             if (q.grad_mode != 0 && q.grad_mode != 1) return fail(GKS_EINVAL, "grad_mode must be 0 or 1");
+            if (!(q.h_dry >= 0) || !std::isfinite(q.h_dry)) return fail(GKS_EINVAL, "h_dry must be finite and >= 0");
+            if (q.h_dry > 0 && q.src_order == 4)
+                return fail(GKS_EINVAL, "wet/dry layers (h_dry > 0) need the second-order layer coupling");
             if (q.G != prm[0].G || q.cfl != prm[0].cfl || q.eps != prm[0].eps || q.eps_num != prm[0].eps_num ||
                 q.precision != prm[0].precision || q.linear != prm[0].linear || q.alpha_mode != prm[0].alpha_mode ||
-                (q.src_order == 4) != (prm[0].src_order == 4) || q.grad_mode != prm[0].grad_mode)
+                (q.src_order == 4) != (prm[0].src_order == 4) || q.grad_mode != prm[0].grad_mode ||
+                q.h_dry != prm[0].h_dry)
                 return fail(GKS_EINVAL, "scenarios of a batch share G, cfl, eps, eps_num, precision, linear, "
-                                        "alpha_mode, src_order and grad_mode");
+                                        "alpha_mode, src_order, grad_mode and h_dry");
         }
         *out = nullptr;
         const int prec = prm[0].precision;
@@ -586,7 +594,8 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         for (int v = 0; v < 6; v++)
             for (int64_t c = 0; c < T; c++) {
                 double x = W0[v * T + c];
-                if (!std::isfinite(x) || ((v == 0 || v == 3) && !(x > 0)))
+                // a layer thickness must be positive, or >= 0 with wet/dry layers
+                if (!std::isfinite(x) || ((v == 0 || v == 3) && !(x > 0 || (prm[0].h_dry > 0 && x >= 0))))
                     return fail(GKS_ENONFINITE, "bad initial value at component " + std::to_string(v) + ", cell " +
                                                     std::to_string(c));
                 if (v == 0) wh[c] = x;
@@ -639,6 +648,7 @@ gks_status gks_state_init(const gks_mesh *mesh_c, const gks_params *prm, const d
         s->p.cfl = prm[0].cfl;
         s->p.linear = prm[0].linear;
         s->p.alpha_mode = prm[0].alpha_mode;
+        s->p.h_dry = prm[0].h_dry;
         s->p.chi = s->chi;
         s->p.t_end = s->tend;
         s->p.scal = s->scal;
@@ -1224,6 +1234,8 @@ gks_status gks_indicator_set(gks_state *s, const float *params, float threshold)
             return GKS_OK;
         }
         if (!std::isfinite(threshold)) return fail(GKS_EINVAL, "threshold must be finite");
+        if (s->p.h_dry > 0)
+            return fail(GKS_EINVAL, "the learned indicator is not trained for wet/dry layers (h_dry > 0)");
         for (int i = 0; i < gks::MLP_NP; i++)
             if (!std::isfinite(params[i])) return fail(GKS_ENONFINITE, "non-finite indicator parameter");
         const size_t T = (size_t)s->md.T;

@@ -48,6 +48,7 @@ struct MeshDev {
 
 struct Phys {
     double G, eps, eps_num, cfl;
+    double h_dry;         // wet/dry threshold (0: every layer is wet everywhere)
     int linear;
     int alpha_mode;       // 0: the well-balance weights read here, 1: the paper's printed constants
     const double *chi;    // [S] density ratio
@@ -60,6 +61,24 @@ struct Phys {
 // the force model's weight w is taken as 1 when it is within 1e-12 of 1: the blend would then
 // change the acceleration by less than its own FP64 rounding
 constexpr double W_ONE = 1.0 - 1e-12;
+
+// Wet/dry layers (Phys::h_dry > 0; the paper's dam breaks over a dry bed, with no treatment given
+// there): a side of an interface whose thickness is at or below h_dry is a vacuum, an interface
+// whose equilibrium thickness is at or below h_dry passes nothing, and the front band of a layer --
+// the cells where the layer, in the cell or in one of its face neighbours, is thinner than
+// WD_THIN h_dry or than WD_FRONT times the thickest of the four -- is reconstructed at first order
+// and evolves at first order in space and time.  Below WD_THIN h_dry a cell's velocity is
+// desingularised (Kurganov and Petrova 2007).
+constexpr double WD_THIN = 1000.0, WD_FRONT = 0.3;
+
+__host__ __device__ inline double wd_velocity(double h, double m, double h_dry)
+{
+    const double hs = WD_THIN * h_dry;
+    if (!(h_dry > 0) || h >= hs) return m / h;
+    const double h2 = h * h, d2 = hs * hs;
+    return 1.4142135623730950488 * h * m / sqrt(h2 * h2 + d2 * d2);
+}
+
 
 // relative floor of the smoothness indicators of the nonlinear reconstruction, above the
 // rounding of the bulk precision: the weights leave their linear values once a variable varies
@@ -529,6 +548,28 @@ struct IndArgs {
 // stage, the second reuses them).
 // SRC = 1: the block then also forms the interior correction of the higher-order layer coupling
 // (src[8][T], see src_point) in the LDS space the records used.
+// whether cell c lies in the front band of the layer of variable v (h2 for v < 3, the lower layer
+// eta1 - B for v >= 3); a wall ghost holds its cell's mirrored state and bottom
+__device__ inline bool wd_band(const MeshDev &m, const Phys &p, const double *__restrict__ Wh, int v, int64_t c)
+{
+    const int64_t T = m.T, TG = m.T + m.NG;
+    const bool lower = v >= 3;
+    const double *H = Wh + (lower ? TG : 0);
+    double hk[4];
+#pragma unroll
+    for (int l = 0; l < 4; l++) {
+        const int64_t i = l == 0 ? c : (int64_t)GKS_IX(m.sten[(l - 1) * T + c], TG);
+        double h = H[i];
+        if (lower) h -= m.Bbar[i < T ? i : (int64_t)GKS_IX(m.gsrc[i - T], T)];
+        hk[l] = h;
+    }
+    const double hmax = fmax(fmax(hk[0], hk[1]), fmax(hk[2], hk[3])), thin = WD_THIN * p.h_dry;
+    bool band = false;
+#pragma unroll
+    for (int l = 0; l < 4; l++) band = band || hk[l] < thin || hk[l] < WD_FRONT * hmax;
+    return band;
+}
+
 template <typename R, int IND, int SRC = 0>
 __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *__restrict__ Wh,
                                                const R *__restrict__ Wm, const R *__restrict__ gW, IndArgs ind,
@@ -658,6 +699,27 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     ReconOut<R> out;
     ReconComb<R> comb;
     if (valid) recon_cell<R>(m, p, lin, r0, v, thick, c, q, a, out, comb);
+    if (p.h_dry > 0 && valid && wd_band(m, p, Wh, v, c)) {
+        // front band: the layer's cell average, thickness constant (the lower layer's level follows
+        // the bottom), momentum the thickness times the desingularised velocity; r0 = 0 marks it
+        const R *vt = tab<R>(m.vtx);
+        const R gs[2] = {R(0.5 - 0.28867513459481288225), R(0.5 + 0.28867513459481288225)};
+        const double gBx = v == 3 ? m.gB[c] : 0.0, gBy = v == 3 ? m.gB[T + c] : 0.0;
+        const double mv = thick ? 0.0 : q.hl * wd_velocity(q.hl, (double)q.Q0, p.h_dry);
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+#pragma unroll
+            for (int g = 0; g < 2; g++) {
+                const int k1 = (k + 1) % 3, slot = 2 * k + g;
+                const R x = vt[(2 * k) * T + c] + gs[g] * (vt[(2 * k1) * T + c] - vt[(2 * k) * T + c]);
+                const R y = vt[(2 * k + 1) * T + c] + gs[g] * (vt[(2 * k1 + 1) * T + c] - vt[(2 * k + 1) * T + c]);
+                out.v[slot] = thick ? q.Q0h + (double)q.hs * (gBx * (double)x + gBy * (double)y) : mv;
+                out.gx[slot] = (R)gBx;
+                out.gy[slot] = (R)gBy;
+            }
+        if (v == 3) r0[c] = R(0);
+        if (v == 0) r0[T + c] = R(0);
+    }
     __syncthreads();  // the space becomes the record tile
     if (valid) {
 #pragma unroll
@@ -805,22 +867,24 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, co
         for (int f = 0; f < 2; f++) {
             // f = 0: eta1 with the lower layer's momentum; f = 1: h2 with the upper layer's
             const int hq = f == 0 ? 1 : 0, mq = f == 0 ? 2 : 0;
+            // a dry side (thickness at or below h_dry, or not positive) has no velocity
             const double zl = ql.h[hq];
             const double hl = f == 0 ? zl - Bg : zl;
-            const double unl = ((double)ql.q[mq] * nx + (double)ql.q[mq + 1] * ny) / hl;
+            const double unl = (hl > p.h_dry && hl > 0) ? ((double)ql.q[mq] * nx + (double)ql.q[mq + 1] * ny) / hl : 0.0;
             double zr, hr, unr;
             if (Rc >= 0) {
                 zr = qr.h[hq];
                 hr = f == 0 ? zr - Bg : zr;
-                unr = ((double)qr.q[mq] * nx + (double)qr.q[mq + 1] * ny) / hr;
+                unr = (hr > p.h_dry && hr > 0) ? ((double)qr.q[mq] * nx + (double)qr.q[mq + 1] * ny) / hr : 0.0;
             } else {  // mirror state across a wall; the same state across a free boundary
                 zr = zl;
                 hr = hl;
                 unr = Rc == -1 ? -unl : unl;
             }
-            // reading: xi is the kinetic fraction of particles moving from left to right
+            // reading: xi is the kinetic fraction of particles moving from left to right (one half
+            // when both sides are dry)
             const double lb = 2.0 / (p.G * (hl + hr));
-            const double xi = 0.5 * erfc(-sqrt(lb) * 0.5 * (unl + unr));
+            const double xi = (hl + hr > 0) ? 0.5 * erfc(-sqrt(lb) * 0.5 * (unl + unr)) : 0.5;
             const double hh = xi * zl + (1 - xi) * zr;
             if (f == 0) acc0 += 0.5 * hh; else acc1 += 0.5 * hh;
         }
@@ -977,9 +1041,14 @@ __host__ __device__ inline double sqrt_(double x) { return sqrt(x); }
 // AM = 0 the weights read for these slopes (below), AM = 1 the paper's printed (1, 3/4, 1/4) on the
 // flux moments of the acceleration term in both the equilibrium and the initial distributions'
 // parts, 1 on the state moments.
-template <typename R, int AM = 0>
-__host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr, double hbase, R gBn, R gBt, R G, R eps,
-                                 R eps_num, R dt, R *F0, R *Ft, R *Wb, R *Wbt)
+// Wet/dry (h_dry > 0): a vacuum side comes with h = 1/h = U = V = 0 and no slopes, so that each of
+// its terms is an exact zero; an interface whose equilibrium thickness hbase + hdev is at or below
+// h_dry gives zero outputs and returns true (dry).  order1: first order in time, F0 the step's mean
+// flux F(dt)/dt and Ft = 0 (the caller passes sides without slopes and accelerations).
+template <typename R, int AM = 0, int WD = 0>
+__host__ __device__ inline bool gks_point(const SideL<R> &sl, const SideL<R> &sr, double hbase, R gBn, R gBt, R G, R eps,
+                                 R eps_num, R dt, R *F0, R *Ft, R *Wb, R *Wbt, bool order1 = false,
+                                 double h_dry = 0.0)
 {
     // the bottom's moments are added unconditionally: for the upper layer (and a flat bottom) the
     // slope is zero and they add exact zeros.  A branch on the slope diverges inside every wave
@@ -1010,6 +1079,13 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     }
     // interface equilibrium state: thickness as an FP64 base plus a deviation that is 0 at rest
     const R hdev = R(0.5) * (sl.h * eL + sr.h * eR);
+    if constexpr (WD) {
+        if (!(hbase + (double)hdev > h_dry)) {  // no particles at the interface
+#pragma unroll
+            for (int i = 0; i < 3; i++) F0[i] = Ft[i] = Wb[i] = Wbt[i] = R(0);
+            return true;
+        }
+    }
     const R hb = (R)(hbase + (double)hdev);
     const R wb1 = sum_products(sl.h, ML[1], sr.h, MR[1]);
     const R wb2 = sum_products(sl.h * ML[0], sl.V, sr.h * MR[0], sr.V);
@@ -1119,8 +1195,10 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     const R pl = sl.h * sl.h, pr = sr.h * sr.h;
     const R r = eps + eps_num * fabs(div_(pl - pr, pl + pr));
     const R E2 = exp_(div_(R(-0.5), r)), E1 = E2 * E2, a1 = 1 - E1, a2 = 1 - E2;
-    const R c04 = r * (4 * a2 - a1), c01 = 1 - c04;
-    const R ct1 = 4 * r * (2 * a2 - a1), ct4 = -ct1;
+    // first order: the step's mean flux, c01 + c04 = 1 still, no time derivative
+    const bool o1 = WD && order1;
+    const R c04 = o1 ? r * a1 : r * (4 * a2 - a1), c01 = 1 - c04;
+    const R ct1 = o1 ? R(0) : 4 * r * (2 * a2 - a1), ct4 = -ct1;
     const R c02 = -r + r * r * (8 * a2 - 2 * a1) - 2 * r * E2 + r * E1;
     const R ct2 = 4 * (2 * r * r * (a1 - 2 * a2) + r * (E2 - E1));
     const R c03 = -r + r * r * (4 * a2 - a1), ct3 = 4 * (R(0.25) + r * r * (a1 - 2 * a2));
@@ -1138,6 +1216,7 @@ __host__ __device__ inline void gks_point(const SideL<R> &sl, const SideL<R> &sr
     Wbt[0] = wt[0];
     Wbt[1] = wt[1];
     Wbt[2] = wt[2];
+    return false;
 }
 
 // one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
@@ -1160,7 +1239,9 @@ __device__ inline void side_rate(const SideL<R> &q, R G, R *o)
 // GM = 1: the discontinuous reading of the gradient update: besides the fluxes, each side's own
 // state and time derivative, averaged over the edge's two Gauss points (left side in the rows of
 // the interface state, right side in eoh rows 6-7 and eom rows 24-33)
-template <typename R, int AM, int STAGE, int GM = 0>
+// WD = 1: wet/dry layers (Phys::h_dry > 0): vacuum sides, first-order band edges, dry interfaces;
+// a template argument so that the wet-only path carries none of it
+template <typename R, int AM, int STAGE, int GM = 0, int WD = 0>
 __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
                                               const R *__restrict__ r0, const double *__restrict__ gP1,
                                               double *__restrict__ eoh, R *__restrict__ eom)
@@ -1193,6 +1274,9 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     const R rL = r0[ff * T + L], rR = Rc >= 0 ? r0[ff * T + Rc] : rL;
     const R wf0 = fmin(R(1), fmin(rL, rR));
     const R wf = (double)wf0 < W_ONE ? wf0 : R(1);
+    // wet/dry: at an edge of this layer's front band (r0 of its own field 0 on either side) the
+    // evolution is of first order: the sides' states alone, no slopes, no acceleration
+    const bool order1 = WD && (r0[(1 - ff) * T + L] == R(0) || (Rc >= 0 && r0[(1 - ff) * T + Rc] == R(0)));
     SideL<R> side[2];
     double h64[2];
 #pragma unroll
@@ -1231,7 +1315,10 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
             ay = -G * dfy;
         }
         SideL<R> &q = side[s];
-        const R h = (R)hh, ih = div_(R(1), h);
+        // wet/dry: a side at or below h_dry is a vacuum (every term of it an exact zero)
+        const bool vac = WD && !(hh > p.h_dry);
+        if (vac) h64[s] = 0.0;
+        const R h = vac ? R(0) : (R)hh, ih = vac ? R(0) : div_(R(1), h);
         q.h = h;
         q.ih = ih;
         q.U = (mx * nx + my * ny) * ih;
@@ -1248,6 +1335,11 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
         q.mtt = dmt_x * tx + dmt_y * ty;
         q.pn = ax * nx + ay * ny;
         q.pt = ax * tx + ay * ty;
+        if (order1) {
+            q.hn = q.ht = q.en = q.et = R(0);
+            q.mnn = q.mnt = q.mtn = q.mtt = R(0);
+            q.pn = q.pt = R(0);
+        }
     }
     if (Rc == -1) {  // wall: mirror image of the left side
         side[1] = side[0];
@@ -1269,15 +1361,18 @@ __global__ void __launch_bounds__(256) k_flux(MeshDev m, Phys p, GpRecs<R> rec,
     }
     const double hbase = 0.5 * (h64[0] + h64[1]);
     // single-valued bottom slope in the local frame (zero normal part at walls by construction)
-    const R gBn = lay == 0 ? gBx * nx + gBy * ny : R(0), gBt = lay == 0 ? gBx * tx + gBy * ty : R(0);
+    const R gBn = (lay == 0 && !order1) ? gBx * nx + gBy * ny : R(0);
+    const R gBt = (lay == 0 && !order1) ? gBx * tx + gBy * ty : R(0);
     R F0[3], Ft[3], Wb[3], Wbt[3];
-    gks_point<R, AM>(side[0], side[1], hbase, gBn, gBt, G, (R)p.eps, (R)p.eps_num, dt, F0, Ft, Wb, Wbt);
+    const bool dry = gks_point<R, AM, WD>(side[0], side[1], hbase, gBn, gBt, G, (R)p.eps, (R)p.eps_num, dt, F0, Ft,
+                                          Wb, Wbt, order1, p.h_dry);
     if (Rc == -1) {  // no mass crosses a wall
         F0[0] = 0;
         Ft[0] = 0;
     }
     // FP64 hydrostatic pieces: interface thickness and 1/2 G hb^2, averaged over the two points
-    const double hb = hbase + (double)Wb[0];
+    // (both zero at a dry interface)
+    const double hb = dry ? 0.0 : hbase + (double)Wb[0];
     double P = 0.5 * p.G * hb * hb, H = hb, Hc = hbase;
     P = 0.5 * (P + __shfl_xor(P, 1));
     H = 0.5 * (H + __shfl_xor(H, 1));
@@ -1402,6 +1497,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         return;
     }
     double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}}, hs[2] = {0, 0}, hts[2] = {0, 0};
+    // smallest acceptable new thickness, exclusive: 0, or -h_dry with wet/dry layers
+    const double hneg = p.h_dry > 0 ? -p.h_dry : 0.0;
     double GC[2][2] = {{0, 0}}, GCt[2][2] = {{0, 0}};  // [0] lower, [1] upper: central thicknesses
 #pragma unroll
     for (int k = 0; k < 3; k++) {
@@ -1514,8 +1611,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = ws;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)ws;
-            if (v == 0) bad |= !(ws > 0);
-            else if (v == 3) bad |= !(ws - (w - h1) > 0);  // w - h1: the cell's bottom mean
+            // a thickness <= 0 is bad, or with wet/dry layers one below -h_dry (a dry cell may hold
+            // a rounding residue)
+            if (v == 0) bad |= !(ws > hneg);
+            else if (v == 3) bad |= !(ws - (w - h1) > hneg);  // w - h1: the cell's bottom mean
             else msum += ws;
             Wc[v * T + c] = w + dt * L[v] + (dt * dt / 6.0) * Lt[v];
 #pragma unroll
@@ -1535,8 +1634,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
                 Whout[(v == 3 ? TG : 0) + c] = wn;
             else
                 Wmout[mom_slot(v) * TG + c] = (R)wn;
-            if (v == 0) bad |= !(wn > 0);
-            else if (v == 3) bad |= !(wn - m.Bbar[c] > 0);
+            if (v == 0) bad |= !(wn > hneg);
+            else if (v == 3) bad |= !(wn - m.Bbar[c] > hneg);
             else msum += wn;
 #pragma unroll
             for (int d = 0; d < 2; d++)
@@ -1572,10 +1671,11 @@ __device__ inline double wave_speed(const MeshDev &m, const Phys &p, const doubl
 {
     const int64_t TG = m.T + m.NG;
     const double h2 = Wh[c], h1 = Wh[TG + c] - m.Bbar[c];
-    const double u2 = Wm[c] / h2, v2 = Wm[TG + c] / h2;
-    const double u1 = Wm[2 * TG + c] / h1, v1 = Wm[3 * TG + c] / h1;
-    const double s1 = sqrt(u1 * u1 + v1 * v1) + sqrt(p.G * h1);
-    const double s2 = sqrt(u2 * u2 + v2 * v2) + sqrt(p.G * h2);
+    // velocities desingularised in thin layers (wet/dry; m / h otherwise), a dry cell may hold -0
+    const double u2 = wd_velocity(h2, Wm[c], p.h_dry), v2 = wd_velocity(h2, Wm[TG + c], p.h_dry);
+    const double u1 = wd_velocity(h1, Wm[2 * TG + c], p.h_dry), v1 = wd_velocity(h1, Wm[3 * TG + c], p.h_dry);
+    const double s1 = sqrt(u1 * u1 + v1 * v1) + sqrt(p.G * fmax(h1, 0.0));
+    const double s2 = sqrt(u2 * u2 + v2 * v2) + sqrt(p.G * fmax(h2, 0.0));
     return fmax(s1, s2);
 }
 

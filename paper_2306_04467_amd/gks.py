@@ -55,7 +55,8 @@ class Params(ctypes.Structure):
     _fields_ = [("G", ctypes.c_double), ("chi", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("eps", ctypes.c_double), ("eps_num", ctypes.c_double), ("t_end", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("linear", ctypes.c_int32), ("alpha_mode", ctypes.c_int32),
-                ("src_order", ctypes.c_int32), ("grad_mode", ctypes.c_int32)]
+                ("src_order", ctypes.c_int32), ("grad_mode", ctypes.c_int32),
+                ("h_dry", ctypes.c_double)]
 
 
 ALPHA_MODES = {"reading": 0, "paper": 1}
@@ -214,9 +215,9 @@ class Mesh:
 
 
 def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False,
-                alpha_mode="reading", src_order=2, grad_mode="continuous"):
+                alpha_mode="reading", src_order=2, grad_mode="continuous", h_dry=0.0):
     return Params(G, chi, cfl, eps, eps_num, t_end, PRECISIONS[precision], int(linear), ALPHA_MODES[alpha_mode],
-                  int(src_order), GRAD_MODES[grad_mode])
+                  int(src_order), GRAD_MODES[grad_mode], float(h_dry))
 
 
 class State:
@@ -243,16 +244,20 @@ class State:
 
     @classmethod
     def from_scenario(cls, mesh, sc, precision="fp64", linear=False, t_end=0.0, alpha_mode="reading",
-                      src_order=2, grad_mode="continuous", **kw):
+                      src_order=2, grad_mode="continuous", h_dry=None, **kw):
+        """h_dry: the wet/dry threshold, by default the scenario's own (0 where it has none)."""
+        if h_dry is None:
+            h_dry = getattr(sc, "h_dry", 0.0)
         p = make_params(G=sc.G, chi=sc.chi, cfl=sc.cfl, t_end=t_end, precision=precision, linear=linear,
-                        alpha_mode=alpha_mode, src_order=src_order, grad_mode=grad_mode)
+                        alpha_mode=alpha_mode, src_order=src_order, grad_mode=grad_mode, h_dry=h_dry)
         return cls(mesh, sc.W0, sc.gradW0, params=p, **kw)
 
     @classmethod
     def from_scenarios(cls, batch_mesh, scs, precision="fp64", linear=False, src_order=2, grad_mode="continuous",
                        **kw):
         ps = [make_params(G=s.G, chi=s.chi, cfl=s.cfl, t_end=s.t_end if s.t_end < 1e8 else 0.0,
-                          precision=precision, linear=linear, src_order=src_order, grad_mode=grad_mode)
+                          precision=precision, linear=linear, src_order=src_order, grad_mode=grad_mode,
+                          h_dry=getattr(s, "h_dry", 0.0))
               for s in scs]
         W0 = np.concatenate([s.W0 for s in scs], axis=1)
         gW0 = np.concatenate([s.gradW0 for s in scs], axis=2)

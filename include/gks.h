@@ -50,7 +50,8 @@ typedef enum {
     GKS_EDEVICE = 3,      /* a HIP call failed */
     GKS_EMESH = 4,        /* malformed mesh (index out of range, inverted or degenerate triangle,
                              edge shared by more than two triangles, unpaired periodic edge) */
-    GKS_ENONFINITE = 5,   /* non-finite value or non-positive layer thickness in the state */
+    GKS_ENONFINITE = 5,   /* non-finite value or non-positive layer thickness in the state
+                             (at or below -h_dry with wet/dry layers) */
     GKS_EUNSUPPORTED = 6  /* option not compiled into this library */
 } gks_status;
 
@@ -145,7 +146,7 @@ gks_status gks_mesh_scenario(const gks_mesh *mesh, int32_t s, int64_t *first_cel
  * (1 for a single mesh); G, cfl, eps, eps_num, precision and linear must agree across scenarios,
  * chi and t_end may differ.  W0 [6][n_tri], gradW0 [6][2][n_tri]: cell averages and cell-averaged
  * gradients at t = 0.  `stream` is a hipStream_t (NULL = null stream).  Returns GKS_ENONFINITE if
- * a thickness is <= 0 or a value is not finite. */
+ * a thickness is <= 0 (< 0 with h_dry > 0) or a value is not finite. */
 gks_status gks_state_init(const gks_mesh *mesh, const gks_params *params, const double *W0,
                           const double *gradW0, void *stream, gks_state **out);
 void gks_state_destroy(gks_state *st);
@@ -205,7 +206,8 @@ gks_status gks_debug_bounds(int32_t reset, int32_t *violations);
 
 /* Non-finite detection (a diagnostic of the cell update, Sec. 3.3): every cell update records on
  * the device, without a host round trip, the smallest cell index whose new state has a
- * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B).  gks_state_check
+ * non-finite value or a layer thickness <= 0 (h2, or h1 = (h1 + B) - B; with h_dry > 0 a
+ * thickness at or below -h_dry: a dry cell may hold a rounding residue).  gks_state_check
  * synchronises and returns GKS_ENONFINITE with *first_bad = that cell (index into the
  * concatenated cells of a batch), or GKS_OK with *first_bad = -1 (first_bad may be NULL).  The
  * synchronising calls gks_state_read, gks_state_time, gks_state_mass, gks_state_diagnostics and

@@ -699,7 +699,9 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     ReconOut<R> out;
     ReconComb<R> comb;
     if (valid) recon_cell<R>(m, p, lin, r0, v, thick, c, q, a, out, comb);
-    if (p.h_dry > 0 && valid && wd_band(m, p, Wh, v, c)) {
+    // wet/dry layers exclude the indicator and the higher-order coupling (the library rejects the
+    // combinations), so only the plain instance carries the band test and its registers
+    if (IND == 0 && SRC == 0 && p.h_dry > 0 && valid && wd_band(m, p, Wh, v, c)) {
         // front band: the layer's cell average, thickness constant (the lower layer's level follows
         // the bottom), momentum the thickness times the desingularised velocity; r0 = 0 marks it
         const R *vt = tab<R>(m.vtx);

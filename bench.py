@@ -274,13 +274,13 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_run(sc, n_steps, src_order=2):
+def oracle_run(sc, n_steps, src_order=2, grad_mode="continuous"):
     """The FP64 oracle on all host cores for n_steps CFL steps: (states after step 1 and after the
     last step, the step sizes, wall seconds, threads)."""
     import oracle
 
     om = oracle.Mesh.from_scenario(sc)
-    p = oracle.params_of(sc, src_order=src_order)
+    p = oracle.params_of(sc, src_order=src_order, grad_mode=grad_mode)
     threads = oracle.load().om_max_threads()
     W, gW = sc.W0, sc.gradW0
     dts, first = [], None
@@ -294,12 +294,12 @@ def oracle_run(sc, n_steps, src_order=2):
     return first, W, dts, time.time() - tc, threads, om, p
 
 
-def gpu_errors(mesh, sc, prec, dts, W1, Wn, indicator=None, src_order=2):
+def gpu_errors(mesh, sc, prec, dts, W1, Wn, indicator=None, src_order=2, grad_mode="continuous"):
     """rel-L1 of the GPU path after the first and after all steps, stepping with the oracle's step
     sizes (explicit stage-0 steps)."""
     from paper_2306_04467_amd import State
 
-    st = State.from_scenario(mesh, sc, precision=prec, src_order=src_order)
+    st = State.from_scenario(mesh, sc, precision=prec, src_order=src_order, grad_mode=grad_mode)
     if indicator is not None:
         st.indicator(*indicator)
     a = sc_area(sc)
@@ -466,6 +466,104 @@ def run_src4(sc, mesh, res, steps, warmup, with_error):
     return out
 
 
+def run_grad_mode(sc, mesh, res, steps, warmup, with_error):
+    """The discontinuous interface values of the gradient update (grad_mode 1) on the headline
+    workload: both precisions timed beside the continuous reading, and the FP64 error after 20
+    steps against the oracle in the same mode."""
+    from paper_2306_04467_amd import State
+
+    out = {"workload": "the headline workload with discontinuous interface values in the gradient update"}
+    for prec in ("fp64", "fp32"):
+        st = State.from_scenario(mesh, sc, precision=prec, grad_mode="discontinuous")
+        tune(st)
+        ms = timed_steps(st, steps, warmup)
+        v = sc.n_tri * 2 * steps / (ms / 1e3)
+        out[prec] = {"value": round(v, 1), "unit": "triangle-stage/s", "ms_per_step": round(ms / steps, 5)}
+        if prec in res:
+            out[prec]["relative_to_continuous"] = round(v / res[prec][1], 4)
+        st.profile(True)
+        st.step(2)
+        prof = st.profile_read()
+        st.profile(False)
+        out[prec]["kernel_ms"] = {kk: round(pv[0] / pv[1], 5) for kk, pv in prof.items() if pv[1]}
+        st.close()
+        log(f"grad_mode {prec}: {v / 1e9:.3f} G tri-stage/s {json.dumps(out[prec])}")
+    if with_error:
+        W1, Wn, dts, tc, threads, _, _ = oracle_run(sc, 20, grad_mode="discontinuous")
+        out["errors_vs_oracle"] = {"fp64": gpu_errors(mesh, sc, "fp64", dts, W1, Wn, grad_mode="discontinuous"),
+                                   "oracle_s": round(tc, 1), "oracle_threads": threads}
+        log(f"grad_mode errors: {json.dumps(out['errors_vs_oracle'])}")
+    return out
+
+
+def run_wet_dry(with_error):
+    """Wet/dry layers (h_dry > 0) on the paper's dry-bed cases: the two-layer dam break with a dry
+    upper bed at the paper's fine cell size 1/400 to t = 0.08, and the breached dam over a dry bed
+    (406,000 triangles) to t = 7.2, both precisions, each step with its CFL step size, replayed
+    from a graph: throughput over the steps to the end time (the first step, which captures the
+    graph, at the mean rate of the others), steps, smallest thickness, mass change.  Errors: the dam break
+    after 20 steps against the oracle, Ritter's exact solution at cell 1/100 on the GPU."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2306_04467_amd import Mesh, State
+
+    out = {}
+    cases = (("dam_break_dry_upper", workloads.dam_break_dry(400, chi=1.0)),
+             ("breached_dam_dry_bed", workloads.dam_break_breach("dry", n=400)))
+    for name, sc in cases:
+        mesh = Mesh.from_scenario(sc)
+        a = sc_area(sc)
+        m0 = [(a * sc.W0[q]).sum() for q in (0, 3)]
+        rec = {"n_tri": sc.n_tri, "t_end": sc.t_end, "h_dry": sc.h_dry}
+        for prec in ("fp64", "fp32"):
+            # the number of steps to t_end first (one step at a time), then exactly that many steps
+            # of a fresh state timed as one graph replay each
+            st = State.from_scenario(mesh, sc, precision=prec, t_end=sc.t_end)
+            n = 0
+            while st.time()[0] < sc.t_end and n < 100000:
+                st.step(1)
+                n += 1
+            st.close()
+            st = State.from_scenario(mesh, sc, precision=prec, t_end=sc.t_end)
+            st.batch_step(1)  # capture the graph outside the timed region
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            st.batch_step(n - 1)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) * n / (n - 1)
+            W, _, t = st.read()
+            st.close()
+            dm = max(abs((a * W[q]).sum() - m0[k]) / m0[k] for k, q in enumerate((0, 3)))
+            rec[prec] = {"value": round(sc.n_tri * 2 * n / (ms / 1e3), 1), "unit": "triangle-stage/s",
+                         "steps": n, "ms": round(ms, 2), "t": t, "min_thickness": float(W[[0, 3]].min()),
+                         "rel_mass_change": float(dm)}
+            log(f"wet/dry {name} {prec}: {json.dumps(rec[prec])}")
+        out[name] = rec
+    if with_error:
+        sc = cases[0][1]
+        W1, Wn, dts, tc, threads, _, _ = oracle_run(sc, 20)
+        out["dam_break_dry_upper"]["errors_vs_oracle"] = {
+            "fp64": gpu_errors(Mesh.from_scenario(sc), sc, "fp64", dts, W1, Wn),
+            "fp32": gpu_errors(Mesh.from_scenario(sc), sc, "fp32", dts, W1, Wn),
+            "oracle_s": round(tc, 1), "oracle_threads": threads}
+    sc = workloads.ritter_channel(200, layer="lower")
+    st = State.from_scenario(Mesh.from_scenario(sc), sc, t_end=sc.t_end)
+    st.step(2000)
+    W, _, t = st.read()
+    st.close()
+    a = sc_area(sc)
+    ex = sc.exact(t)
+    out["ritter_exact"] = {"n_tri": sc.n_tri, "t": t,
+                           "rel_l1_h": float((a * np.abs(W[3] - ex[3])).sum() / (a * ex[3]).sum()),
+                           "rel_l1_hu": float((a * np.abs(W[4] - ex[4])).sum() / (a * np.abs(ex[4])).sum())}
+    log(f"wet/dry Ritter: {json.dumps(out['ritter_exact'])}")
+    return out
+
+
 def he_init(seed, n_in=44, n_h=64):
     """Initial indicator parameters: He-normal weights, zero biases (seeded)."""
     import numpy as np
@@ -575,6 +673,8 @@ def main():
                     help="skip the 999,698-triangle dam break (timed in both precisions)")
     ap.add_argument("--no-src4", dest="src4", action="store_false",
                     help="skip the higher-order layer coupling leg on the headline workload")
+    ap.add_argument("--no-options", dest="options", action="store_false",
+                    help="skip the legs of the discontinuous gradient values and the wet/dry layers")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-profile", action="store_true", help="skip the event-timed kernel pass")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -641,6 +741,10 @@ def main():
                                "roofline": r32, "kernels": k32}
     if args.src4:
         extra["higher_order_coupling"] = run_src4(sc, mesh, res, args.steps, args.warmup, not args.no_cpu_baseline)
+    if args.options:
+        extra["discontinuous_gradient_values"] = run_grad_mode(sc, mesh, res, args.steps, args.warmup,
+                                                               not args.no_cpu_baseline)
+        extra["wet_dry"] = run_wet_dry(not args.no_cpu_baseline)
     if args.c3:
         extra["dam_break_1M"] = run_c3(args.steps, args.warmup, not args.no_cpu_baseline)
     trained = train_indicator() if (args.ensemble > 0 or args.indicator_n > 0) else None

@@ -214,3 +214,27 @@ def test_wet_dry_parameters_checked(gks):
     with pytest.raises(gks.GksError) as ei:
         gks.State.from_scenarios(bm, scs)
     assert ei.value.code == gks.GKS_EINVAL
+
+
+@pytest.mark.parametrize("case", ["dam_dry_fine", "breach_dry_full"])
+def test_wet_dry_full_size_step_parity(gks, case):
+    """The timed wet/dry workloads at full size: the paper's dam break at its fine cell size 1/400
+    (160,000 triangles) and the breached dam over a dry bed (406,000 triangles); one S2O4 step with
+    the CFL step, then a second, every cell against the oracle."""
+    sc = w.dam_break_dry(400, chi=1.0) if case == "dam_dry_fine" else w.dam_break_breach("dry", n=400)
+    print(f"[wd] full size {case} T={sc.n_tri}", flush=True)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc)
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    Wr, gWr = sc.W0, sc.gradW0
+    for k in range(2):
+        dt = st.step(1, want_dt=True)
+        dref = o.dt(om, p, Wr)
+        assert abs(dt - dref) <= 1e-8 * dref
+        Wr, gWr = o.step(om, p, dt, Wr, gWr)
+    W, gW, _ = st.read()
+    e, g = _errs(W, gW, Wr, gWr)
+    print(f"   state {e:.2e} grad {g:.2e} min h {W[[0, 3]].min():.1e}", flush=True)
+    assert e < 2 * TOL_FP64 and g < 20 * TOL_FP64
+    assert W[[0, 3]].min() >= 0.0

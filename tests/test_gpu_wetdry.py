@@ -238,3 +238,25 @@ def test_wet_dry_full_size_step_parity(gks, case):
     print(f"   state {e:.2e} grad {g:.2e} min h {W[[0, 3]].min():.1e}", flush=True)
     assert e < 2 * TOL_FP64 and g < 20 * TOL_FP64
     assert W[[0, 3]].min() >= 0.0
+
+
+@pytest.mark.parametrize("grad_mode,alpha_mode", [("discontinuous", "reading"), ("continuous", "paper"),
+                                                  ("discontinuous", "paper")])
+@pytest.mark.parametrize("case", ["dam_dry_chi02", "breach_wet"])
+def test_wet_dry_with_the_other_options(gks, case, grad_mode, alpha_mode):
+    """Wet/dry layers together with the discontinuous gradient values and the paper's alpha
+    constants (the flux instances that combine them): three steps against the oracle in the same
+    modes at the FP64 bound."""
+    sc = CASES[case]()
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, grad_mode=grad_mode, alpha_mode=alpha_mode)
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, grad_mode=grad_mode, alpha_mode=alpha_mode)
+    Wr, gWr = sc.W0, sc.gradW0
+    for _ in range(3):
+        dt = st.step(1, want_dt=True)
+        Wr, gWr = o.step(om, p, dt, Wr, gWr)
+    W, gW, _ = st.read()
+    e, g = _errs(W, gW, Wr, gWr)
+    print(f"[wd] {case} {grad_mode} {alpha_mode}: state {e:.2e} grad {g:.2e}", flush=True)
+    assert e < 3 * TOL_FP64 and g < 30 * TOL_FP64

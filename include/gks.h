@@ -189,7 +189,8 @@ gks_status gks_state_mass_noalloc(const gks_state *st, int32_t s, double mass[2]
 /* Per-step diagnostics of scenario s (0 <= s < n_scenarios; synchronising), from device
  * reductions over its cells: out[0] time t, out[1] last step size, out[2] and out[3] the layer
  * masses as gks_state_mass (upper h2, lower h1), out[4] and out[5] the largest speed |hU|/h of the
- * upper and the lower layer, out[6] and out[7] the spread (max - min) of the lower level
+ * upper and the lower layer (with h_dry > 0 desingularised in layers thinner than 1000 h_dry, as
+ * in the time step: a dry cell contributes 0), out[6] and out[7] the spread (max - min) of the lower level
  * eta1 = h1 + B and of the surface eta2 = eta1 + h2.  For a lake at rest (Sec. 3.2, the
  * well-balance property) out[4..7] are its residual: zero up to rounding.  GKS_ENONFINITE as for
  * the other synchronising queries (outputs filled first). */

@@ -897,10 +897,10 @@ gks_status gks_state_diagnostics(const gks_state *s, int32_t scen, double out[8]
         HIP_OK(hipMemcpyAsync(mpart.data(), s->part, mpart.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         if (s->prec == GKS_FP64)
             hipLaunchKernelGGL(gks::k_diag_partial<double>, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[b],
-                               (const double *)s->Wm[b], c0, c1, s->part);
+                               (const double *)s->Wm[b], c0, c1, s->p.h_dry, s->part);
         else
             hipLaunchKernelGGL(gks::k_diag_partial<float>, dim3(nb), dim3(256), 0, s->stream, s->md, s->Wh[b],
-                               (const float *)s->Wm[b], c0, c1, s->part);
+                               (const float *)s->Wm[b], c0, c1, s->p.h_dry, s->part);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpyAsync(dpart.data(), s->part, dpart.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         double sc[2];

@@ -1786,12 +1786,13 @@ __global__ void __launch_bounds__(256) k_mass_partial(MeshDev m, const double *_
 
 // Per-step diagnostics of a scenario's cells [c0, c1) (Sec. 3.2's well-balance property: a lake
 // at rest keeps U = 0 and both levels flat): per block the largest speed |h U| / h of each layer
-// and the largest and smallest levels eta1 = h1 + B and eta2 = eta1 + h2, as six maxima (the
-// minima negated); the host takes the maxima over the blocks.  Grid-stride over the cells.
+// (desingularised in thin layers when h_dry > 0, as in the time step) and the largest and smallest
+// levels eta1 = h1 + B and eta2 = eta1 + h2, as six maxima (the minima negated); the host takes
+// the maxima over the blocks.  Grid-stride over the cells.
 template <typename R>
 __global__ void __launch_bounds__(256) k_diag_partial(MeshDev m, const double *__restrict__ Wh,
                                                       const R *__restrict__ Wm, int64_t c0, int64_t c1,
-                                                      double *__restrict__ part)
+                                                      double h_dry, double *__restrict__ part)
 {
     __shared__ double sh[6][256];
     const int64_t TG = m.T + m.NG;
@@ -1799,8 +1800,8 @@ __global__ void __launch_bounds__(256) k_diag_partial(MeshDev m, const double *_
     for (int64_t c = c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < c1; c += (int64_t)gridDim.x * blockDim.x) {
         const double h2 = Wh[c], e1 = Wh[TG + c], h1 = e1 - m.Bbar[c];
         const double m2x = Wm[c], m2y = Wm[TG + c], m1x = Wm[2 * TG + c], m1y = Wm[3 * TG + c];
-        v[0] = fmax(v[0], sqrt(m2x * m2x + m2y * m2y) / h2);
-        v[1] = fmax(v[1], sqrt(m1x * m1x + m1y * m1y) / h1);
+        v[0] = fmax(v[0], wd_velocity(h2, sqrt(m2x * m2x + m2y * m2y), h_dry));
+        v[1] = fmax(v[1], wd_velocity(h1, sqrt(m1x * m1x + m1y * m1y), h_dry));
         v[2] = fmax(v[2], e1);
         v[3] = fmax(v[3], -e1);
         v[4] = fmax(v[4], e1 + h2);

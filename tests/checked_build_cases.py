@@ -20,6 +20,9 @@ def cases():
         "free": (w.free_outflow(10), {}),
         "dam_fp32": (w.dam_break(12, seed=5), {"precision": "fp32"}),
         "src4": (w.smooth_jittered(10), {"src_order": 4}),
+        "grad_mode": (w.dam_break(10, seed=6), {"grad_mode": "discontinuous"}),
+        "wet_dry": (w.dam_break_dry(16, chi=0.2), {}),
+        "wet_dry_breach": (w.dam_break_breach("dry", n=12), {"grad_mode": "discontinuous"}),
     }
 
 

@@ -102,16 +102,22 @@ def timed_steps(st, steps, warmup, graph=False):
 
 
 def source_hash():
-    """sha256 prefix over the kernel sources (names and bytes), as written into the profiles."""
+    """sha256 prefix over the kernel sources, as written into the profiles: file names and the code
+    with its comments, trailing blanks and blank lines removed (a comment edit changes no kernel)."""
     import hashlib
+    import re
 
     d = os.path.join(ROOT, "paper_2306_04467_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".h", ".hip", ".cpp")):
             h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(d, f), encoding="utf-8") as fh:
+                text = fh.read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            lines = [ln.rstrip() for ln in text.splitlines()]
+            h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -1221,10 +1221,6 @@ __host__ __device__ inline bool gks_point(const SideL<R> &sl, const SideL<R> &sr
     return false;
 }
 
-// one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
-// STAGE 1 (the second stage) writes only what the second update reads: the mass fluxes, the time
-// derivatives, the interface thicknesses and the coupling's Gauss-point thicknesses and rates; the
-// momentum fluxes, the hydrostatic terms and the interface momenta keep the first stage's values.
 // Time derivative of one side's own state (h, m.n, m.t in the local frame) from the shallow-water
 // equations on that side's data: minus the derivative of the normal and tangential fluxes plus
 // h times the acceleration; the pressure term takes the slope of the level (eta1 for the lower
@@ -1238,6 +1234,10 @@ __device__ inline void side_rate(const SideL<R> &q, R G, R *o)
     o[2] = -(U * q.mtn + V * q.mnn - U * V * q.hn) - (R(2) * V * q.mtt - V * V * q.ht + G * h * q.et) + h * q.pt;
 }
 
+// one thread per (edge, Gauss point, layer); the two Gauss points of an edge are adjacent lanes
+// STAGE 1 (the second stage) writes only what the second update reads: the mass fluxes, the time
+// derivatives, the interface thicknesses and the coupling's Gauss-point thicknesses and rates; the
+// momentum fluxes, the hydrostatic terms and the interface momenta keep the first stage's values.
 // GM = 1: the discontinuous reading of the gradient update: besides the fluxes, each side's own
 // state and time derivative, averaged over the edge's two Gauss points (left side in the rows of
 // the interface state, right side in eoh rows 6-7 and eom rows 24-33)

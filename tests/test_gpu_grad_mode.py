@@ -168,3 +168,24 @@ def test_full_size_headline_step_parity_discontinuous(gks):
     e, g = state_err(W, Wr), grad_err(gW, gWr, Wr)
     print(f"   state err {e.max():.2e} grad err {g.max():.2e}", flush=True)
     assert e.max() < TOL_FP64 and g.max() < 10 * TOL_FP64, (e, g)
+
+
+@pytest.mark.parametrize("kw", [{"src_order": 4}, {"alpha_mode": "paper"}, {"src_order": 4, "alpha_mode": "paper"}])
+@pytest.mark.parametrize("case", ["dam", "jittered"])
+def test_discontinuous_gradient_values_with_the_other_options(gks, case, kw):
+    """The discontinuous gradient values together with the higher-order coupling and the paper's
+    alpha constants (the kernel instances that combine them): three steps against the oracle in
+    the same modes at the FP64 bound."""
+    sc = _case(case)
+    m = gks.Mesh.from_scenario(sc)
+    st = gks.State.from_scenario(m, sc, grad_mode=GM, **kw)
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, grad_mode=GM, **kw)
+    Wr, gWr = sc.W0, sc.gradW0
+    for _ in range(3):
+        dt = st.step(1, want_dt=True)
+        Wr, gWr = o.step(om, p, dt, Wr, gWr)
+    W, gW, _ = st.read()
+    e, g = state_err(W, Wr).max(), grad_err(gW, gWr, Wr).max()
+    print(f"[grad] {case} {kw}: state {e:.2e} grad {g:.2e}", flush=True)
+    assert e < 3 * TOL_FP64 and g < 30 * TOL_FP64

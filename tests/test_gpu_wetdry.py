@@ -260,3 +260,27 @@ def test_wet_dry_with_the_other_options(gks, case, grad_mode, alpha_mode):
     e, g = _errs(W, gW, Wr, gWr)
     print(f"[wd] {case} {grad_mode} {alpha_mode}: state {e:.2e} grad {g:.2e}", flush=True)
     assert e < 3 * TOL_FP64 and g < 30 * TOL_FP64
+
+
+def test_dry_strip_on_the_periodic_lattice(gks):
+    """A strip of upper layer over a uniform lower one on the periodic lattice, dry elsewhere, to
+    t = 0.02: the GPU run equals the oracle's at the FP64 bound and keeps the lattice's invariance
+    under translation by one cell in y."""
+    from tests.test_oracle_wetdry import _dry_strip_lattice, _y_shift_partner
+
+    sc, c, h = _dry_strip_lattice()
+    st = gks.State.from_scenario(gks.Mesh.from_scenario(sc), sc, t_end=sc.t_end)
+    om = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc)
+    Wr, gWr = sc.W0, sc.gradW0
+    n = 0
+    while st.time()[0] < sc.t_end:
+        dt = st.step(1, want_dt=True)
+        Wr, gWr = o.step(om, p, dt, Wr, gWr)
+        n += 1
+    W, gW, _ = st.read()
+    e, g = _errs(W, gW, Wr, gWr)
+    partner = _y_shift_partner(c, h)
+    print(f"[wd] dry strip {n} steps: state {e:.2e} grad {g:.2e}", flush=True)
+    assert e < n * TOL_FP64 and g < n * TOL_FP64 * 10
+    assert np.abs(W - W[:, partner]).max() < 1e-13

@@ -179,3 +179,45 @@ def test_breached_dam_runs_to_the_papers_time(kind):
     for q in (0, 3):
         U = np.array([o.cell_velocity(W[q, c], W[q + 1, c], sc.h_dry) for c in range(W.shape[1])])
         assert np.abs(U).max() < bound
+
+
+def _dry_strip_lattice(n=40):
+    """A strip of upper layer (0.25 < x < 0.5) over a uniform lower layer on the periodic
+    right-triangle lattice of [0, 1]^2, dry elsewhere: data that depend on x only."""
+    xy, tri, L = w.periodic_square(n, 1.0)
+    c = xy[tri].mean(axis=1)
+    T = tri.shape[0]
+    W0 = np.zeros((6, T))
+    W0[3] = 0.357
+    W0[0] = np.where((c[:, 0] > 0.25) & (c[:, 0] < 0.5), 1.0, 0.0)
+    sc = w.Scenario("dry_strip", xy, tri, np.zeros(xy.shape[0]), "periodic", L, G, 0.98, 0.3, 0.02, W0,
+                    np.zeros((6, 2, T)), h_dry=1e-6)
+    return sc, c, 1.0 / n
+
+
+def _y_shift_partner(c, h):
+    """Index of the cell one lattice spacing further in y (periodic) for every cell."""
+    key = {(round(x / h * 6), round(y / h * 6) % round(6 / h)): i for i, (x, y) in enumerate(c)}
+    return np.array([key[(round(x / h * 6), round((y + h) / h * 6) % round(6 / h))] for x, y in c])
+
+
+def test_dry_strip_keeps_the_lattice_translation_invariance():
+    """Wet/dry reading on data that depend on x only: the solution keeps the periodic lattice's
+    invariance under translation by one cell in y (the vacuum sides, the front band and the dry
+    interfaces treat translated cells alike), and it stays symmetric about the strip's centre line
+    x = 0.375 in the thickness (the lattice's point reflection maps the strip onto itself)."""
+    sc, c, h = _dry_strip_lattice()
+    _, W, gW, t, n, hmin = _run(sc)
+    assert t == pytest.approx(0.02) and hmin >= 0.0
+    partner = _y_shift_partner(c, h)
+    assert np.abs(W - W[:, partner]).max() < 1e-13
+    assert np.abs(gW - gW[:, :, partner]).max() < 1e-11
+    assert (W[0][(c[:, 0] > 0.5) & (c[:, 0] < 0.6)] > 1e-3).any()   # the strip spreads right
+    assert (W[0][(c[:, 0] > 0.15) & (c[:, 0] < 0.25)] > 1e-3).any()  # and left
+    # point reflection through (0.375, 0.5): thicknesses equal, x-momenta opposite
+    k = round(6 / h)
+    key = {(round(x / h * 6) % k, round(y / h * 6) % k): i for i, (x, y) in enumerate(c)}
+    mirror = np.array([key[(round((0.75 - x) / h * 6) % k, round((1.0 - y) / h * 6) % k)] for x, y in c])
+    for q in (0, 3):
+        assert np.abs(W[q] - W[q][mirror]).max() < 1e-13
+        assert np.abs(W[q + 1] + W[q + 1][mirror]).max() < 1e-13

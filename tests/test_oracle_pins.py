@@ -1048,3 +1048,23 @@ def test_continuous_interface_values_keep_the_order_on_the_accuracy_problem():
     for v in range(2):
         order = math.log2(e[16][v] / e[64][v]) / 2
         assert 2.0 < order < 3.0, (v, e, order)
+
+
+def test_discontinuous_gradient_values_keep_the_lattice_translation_invariance():
+    """The paper's first Riemann problem (Sec. 4) on the periodic right-triangle lattice depends on x
+    only; with the discontinuous gradient values the solution keeps the lattice's invariance under
+    translation by one cell in y, state and gradients."""
+    n = 40
+    sc = w.riemann_exchange(n)
+    mesh = o.Mesh.from_scenario(sc)
+    p = o.params_of(sc, grad_mode="discontinuous")
+    W, gW = sc.W0.copy(), sc.gradW0.copy()
+    for _ in range(10):
+        W, gW = o.step(mesh, p, o.dt(mesh, p, W), W, gW)
+    c = sc.node_xy[sc.tri].mean(axis=1)
+    h, k = 1.0 / n, 6 * n
+    key = {(round(x / h * 6) % k, round(y / h * 6) % k): i for i, (x, y) in enumerate(c)}
+    partner = np.array([key[(round(x / h * 6) % k, round((y + h) / h * 6) % k)] for x, y in c])
+    assert np.abs(W - W[:, partner]).max() < 1e-13
+    assert np.abs(gW - gW[:, :, partner]).max() < 1e-11
+    assert np.abs(W[0] - sc.W0[0]).max() > 1e-3  # the jump has moved

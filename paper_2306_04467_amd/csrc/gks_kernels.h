@@ -580,9 +580,9 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
     // features and hidden activations (with IND); then the block's 32 x 6 Gauss-point records
     // (heads, then tails), each array written out as one contiguous span
     constexpr int NR = RECON_CELLS * 6;
-    // the operator is staged in two parts (rows of coefficients 0..4, then 5..8), both loaded at
-    // once into registers, so that the LDS holds only the larger part
-    constexpr int ROWS1 = 5 * 17, ROWS2 = 153 - ROWS1;
+    // the operator is staged in two parts (rows of coefficients 0..4, then the other 153 - ROWS1
+    // rows of 5..8), both loaded at once into registers, so that the LDS holds only the larger part
+    constexpr int ROWS1 = 5 * 17;
     constexpr int MBYTES = ROWS1 * RECON_CELLS * (int)sizeof(R);
     constexpr int OBYTES = NR * (int)(sizeof(GpHead<R>) + sizeof(GpTail<R>));
     constexpr int IBYTES = IND == 1 ? RECON_CELLS * (FB + HB) * 2 + 4 * RECON_CELLS * 8 + RECON_CELLS : 0;
@@ -850,7 +850,7 @@ __global__ void k_hhat(MeshDev m, Phys p, const GpHead<R> *__restrict__ head, co
 {
     int64_t e = xcd_block() * blockDim.x + threadIdx.x;
     if (e >= m.E) return;
-    const int64_t T = m.T, E = m.E;
+    const int64_t E = m.E;
     const int32_t L = GKS_IX(m.eL[e], m.T), Rc = m.eR[e] >= 0 ? GKS_IX(m.eR[e], m.T) : m.eR[e],
                   sl = m.eslot[e];
     if (!need[L] && (Rc < 0 || !need[Rc])) return;  // no plane gradient uses this edge

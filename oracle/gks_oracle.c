@@ -955,6 +955,9 @@ static void reconstruct_cell(const om_mesh *m, int c, const double *W, const dou
             }
             int band = 0;
             for (int l = 0; l < 4; l++) band |= hk[l] < OM_THIN * h_dry || hk[l] < OM_FRONT * hmax;
+            /* the lower layer thinner than the bottom's rise across the cell: its shoreline lies
+             * inside the cell (a partially flooded cell) */
+            if (o == 3) band |= hbar < h * sqrt(m->Bx[c] * m->Bx[c] + m->By[c] * m->By[c]);
             if (!band) continue;
             double Uc = om_cell_velocity(hbar, q[0][o + 1], h_dry), Vc = om_cell_velocity(hbar, q[0][o + 2], h_dry);
             for (int p = 0; p < 6; p++) {

@@ -53,9 +53,12 @@ typedef struct {
                         paper gives no treatment, this is a reading): 0 (off) the scheme as above;
                         > 0 a layer thickness at or below h_dry is dry.  A dry side of an interface
                         carries no particles (vacuum), an interface whose equilibrium thickness is
-                        at or below h_dry passes nothing, and a layer thinner than OM_THIN h_dry in
-                        a cell is reconstructed as its constant cell average with the cell's
-                        desingularised velocity (om_cell_velocity), at first order */
+                        at or below h_dry passes nothing, and in a layer's front band (the cell or
+                        a face neighbour thinner than OM_THIN h_dry or than OM_FRONT times the
+                        thickest of the four, or the lower layer thinner than the bottom's rise
+                        across the cell) the layer is reconstructed as its constant cell average
+                        with the cell's desingularised velocity (om_cell_velocity) and evolves at
+                        first order in space and time */
 } om_params;
 
 /* The two-stage fourth-order time stepping (S2O4, Sec. 3.3, Eq. SWE-fully-discrete) on n values:
@@ -93,9 +96,9 @@ void om_lsq_matrix(const om_mesh *m, int c, double *M);
 /* Smallest sine of the angle between the two centroid offsets of a plane candidate of the
  * nonlinear reconstruction (a sub-stencil {0, i, j}); flatter sub-stencils are not candidates. */
 #define OM_PLANE_SINE_MIN 0.2
-/* a layer thinner than OM_THIN h_dry in a cell is reconstructed at first order (h_dry > 0) */
+/* the front band of a layer (h_dry > 0): the cell or a face neighbour thinner than OM_THIN h_dry
+ * or than OM_FRONT times the thickest of the four (see h_dry) */
 #define OM_THIN 1000.0
-/* ... or thinner than OM_FRONT times the thickest of the cell and its face neighbours */
 #define OM_FRONT 0.3
 
 /* Reconstruction of all six variables in cell c (with eta1 = h1 + B in place of h1) at the cell's
@@ -120,8 +123,8 @@ void om_gks_point_mode(const double *sideL, const double *sideR, double G, doubl
 void om_gks_point_integrated(const double *sideL, const double *sideR, double G, double delta,
                              double tau, double *F);
 /* Velocity of a layer with cell-average thickness h and momentum component m: m / h where h is at
- * least h_dry (or h_dry is 0); below it the desingularised form sqrt(2) h m / sqrt(h^4 + h_dry^4)
- * (Kurganov and Petrova 2007), which tends to zero with h. */
+ * least hs = OM_THIN h_dry (or h_dry is 0); below it the desingularised form
+ * sqrt(2) h m / sqrt(h^4 + hs^4) (Kurganov and Petrova 2007), which tends to zero with h. */
 double om_cell_velocity(double h, double m, double h_dry);
 /* The evolution at one Gauss point with wet/dry sides (h_dry as in om_params): a side whose
  * thickness is at or below zero is a vacuum (the caller zeroes a dry side's record), and an

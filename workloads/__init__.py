@@ -24,6 +24,7 @@ from .scenarios import (  # noqa: F401
     dam_break_dry,
     ritter_channel,
     dam_break_breach,
+    dry_bump_dam_break,
     COMPONENTS,
 )
 from .configs import CONFIGS, build as build_config, spec as config_spec  # noqa: F401,E402

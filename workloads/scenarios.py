@@ -372,6 +372,24 @@ def ritter_channel(n: int = 200, layer: str = "lower", seed: int = 20230608, h0:
                     W0, np.zeros((6, 2, T)), exact=exact, h_dry=h_dry)
 
 
+def dry_bump_dam_break(n: int = 100, seed: int = 20230610, chi: float = 0.98, h_dry: float = 1e-6,
+                       cfl: float = 0.3, t_end: float = 0.5, G: float = 9.81) -> Scenario:
+    """A lower layer running over dry land: the bottom of the headline workload (Gaussian bump 0.5
+    high at the centre of [0,1]^2, jittered mesh, walls), the lower layer's level 0.45 for x < 0.3
+    and 0.3 beyond, so that the bump's top stands dry, the upper layer 0.2 thick everywhere, at
+    rest; the lower layer thickness max(level - B, 0) by cell."""
+    xy, tri = jittered_square(n, seed)
+    node_B = _bump(xy)
+    Bm, _, _ = _p1_bottom(xy, tri, node_B)
+    c = xy[tri].mean(axis=1)
+    T = tri.shape[0]
+    W0 = np.zeros((6, T))
+    W0[0] = 0.2
+    W0[3] = np.maximum(np.where(c[:, 0] < 0.3, 0.45, 0.3) - Bm, 0.0)
+    return Scenario(f"dry_bump_dam_break_n{n}", xy, tri, node_B, "wall", None, G, chi, cfl, t_end, W0,
+                    np.zeros((6, 2, T)), h_dry=h_dry)
+
+
 def dam_break_breach(kind: str = "dry", n: int = 80, seed: int = 20230609, chi: float = 0.98, h_dry: float = 1e-6,
                      cfl: float = 0.3, t_end: float = 7.2, G: float = 9.81) -> Scenario:
     """A stand-in for the paper's 2-D dam break in an irregular domain (Sec. 4): a dam of width 10

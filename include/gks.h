@@ -110,7 +110,8 @@ typedef struct {
                            be 0.  A side of an interface at or below h_dry is a vacuum, an
                            interface whose equilibrium thickness is at or below h_dry passes
                            nothing, and in a layer's front band (the cell or a face neighbour
-                           thinner than 1000 h_dry or than 0.3 times the thickest of the four) the
+                           thinner than 1000 h_dry or than 0.3 times the thickest of the four, or
+                           the lower layer thinner than the bottom's rise across the cell) the
                            layer is reconstructed as its cell average with the cell's velocity
                            desingularised below 1000 h_dry, and evolves at first order in space
                            and time.  Must agree across a batch; needs src_order 2 and no learned

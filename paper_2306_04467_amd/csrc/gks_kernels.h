@@ -66,8 +66,9 @@ constexpr double W_ONE = 1.0 - 1e-12;
 // there): a side of an interface whose thickness is at or below h_dry is a vacuum, an interface
 // whose equilibrium thickness is at or below h_dry passes nothing, and the front band of a layer --
 // the cells where the layer, in the cell or in one of its face neighbours, is thinner than
-// WD_THIN h_dry or than WD_FRONT times the thickest of the four -- is reconstructed at first order
-// and evolves at first order in space and time.  Below WD_THIN h_dry a cell's velocity is
+// WD_THIN h_dry or than WD_FRONT times the thickest of the four, and the cells where the lower
+// layer is thinner than the bottom's rise across the cell -- is reconstructed at first order and
+// evolves at first order in space and time.  Below WD_THIN h_dry a cell's velocity is
 // desingularised (Kurganov and Petrova 2007).
 constexpr double WD_THIN = 1000.0, WD_FRONT = 0.3;
 
@@ -567,6 +568,12 @@ __device__ inline bool wd_band(const MeshDev &m, const Phys &p, const double *__
     bool band = false;
 #pragma unroll
     for (int l = 0; l < 4; l++) band = band || hk[l] < thin || hk[l] < WD_FRONT * hmax;
+    // the lower layer thinner than the bottom's rise across the cell (scale sqrt(2 area)): its
+    // shoreline lies inside the cell (a partially flooded cell)
+    if (lower) {
+        const double gx = m.gB[c], gy = m.gB[T + c];
+        band = band || hk[0] < sqrt(2.0 * m.area[c]) * sqrt(gx * gx + gy * gy);
+    }
     return band;
 }
 

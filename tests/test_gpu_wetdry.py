@@ -42,6 +42,7 @@ CASES = {
     "breach_dry": lambda: w.dam_break_breach("dry", n=24),
     "breach_wet": lambda: w.dam_break_breach("wet", n=24),
     "absent_upper": _absent_upper,
+    "dry_bump": lambda: w.dry_bump_dam_break(24),
 }
 
 
@@ -93,12 +94,12 @@ def test_wet_dry_steps_match_oracle(gks, case, nsteps):
     assert W[[0, 3]].min() > -1e-6
 
 
-@pytest.mark.parametrize("case", ["dam_dry_chi1", "dam_dry_chi02", "breach_dry"])
+@pytest.mark.parametrize("case", ["dam_dry_chi1", "dam_dry_chi02", "breach_dry", "dry_bump"])
 def test_wet_dry_run_to_end_time_matches_oracle(gks, case):
-    """Whole runs to the paper's end times (t = 0.08 for the two-layer dam break, 7.2 for the
-    breached dam): the device keeps every thickness above -h_dry (the non-finite / negative flag is
-    never raised), both layers' mass to round-off, and the final state within 1e-9 (relative L1) of
-    the oracle's run."""
+    """Whole runs to the end times (t = 0.08 for the paper's two-layer dam break, 7.2 for the
+    breached dam, 0.5 for the lower layer running over the dry-topped bump): the device keeps every
+    thickness above -h_dry (the non-finite / negative flag is never raised), both layers' mass to
+    round-off, and the final state within 1e-9 (relative L1) of the oracle's run."""
     sc = CASES[case]()
     print(f"[wd] {case} to t={sc.t_end}", flush=True)
     m = gks.Mesh.from_scenario(sc)

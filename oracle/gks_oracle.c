@@ -21,6 +21,9 @@
 #define NS 10       /* stencil cells (Sec. 3.4, Eq. Recons-stencil) */
 #define NROW 17     /* 9 averages + 2 x 4 gradients */
 #define NDOF 9      /* a_1 .. a_9 */
+/* Loops over fewer cells or edges than this run on one thread: on small meshes the threads
+ * cost more than the work.  Every iteration is independent, so the count changes no result. */
+#define OMP_MIN_ITEMS 4096
 
 /* ----------------------------------------------------------------------------------------- */
 /* affine maps x -> R x + t: periodic translations and wall mirror images of cells             */
@@ -538,7 +541,7 @@ om_mesh *om_mesh_new(const double *node_xy, int nn, const int *tri, int nt, cons
         }
     }
     m->M = (double *)malloc(sizeof(double) * (size_t)nt * NDOF * NROW);
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) if(nt >= OMP_MIN_ITEMS)
     for (int c = 0; c < nt; c++) build_lsq(m, c);
     return m;
 }
@@ -1381,7 +1384,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     double *grd = (double *)malloc(sizeof(double) * (size_t)T * 72);
     double *r0 = (double *)malloc(sizeof(double) * (size_t)T * 6);
     double *corr = src4 ? (double *)malloc(sizeof(double) * (size_t)T * 8) : NULL;
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) if(T >= OMP_MIN_ITEMS)
     for (int c = 0; c < T; c++)
         reconstruct_cell(m, c, W, gW, p->linear, p->G, p->h_dry, val + (size_t)c * 36, grd + (size_t)c * 72, r0 + (size_t)c * 6,
                          src4 ? corr + (size_t)c * 8 : NULL);
@@ -1393,7 +1396,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     /* 2. interface modelling of the heights that drive the layer forces (Sec. 2.3):
      *    field 0 = eta1 = h1 + B with layer-1 velocities, field 1 = h2 with layer-2 velocities */
     double *hmid = (double *)malloc(sizeof(double) * (size_t)E * 2);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if(E >= OMP_MIN_ITEMS)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
         int kL = m->e_lk[2 * e], kR = m->e_lk[2 * e + 1];
@@ -1422,7 +1425,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     }
     /* gradient of the plane through the three edge-centre values of each cell */
     double *gP1 = (double *)malloc(sizeof(double) * (size_t)T * 4);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if(T >= OMP_MIN_ITEMS)
     for (int c = 0; c < T; c++) {
         for (int f = 0; f < 2; f++) {
             double hk[3];
@@ -1434,7 +1437,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     /* 3. gas-kinetic evolution at every Gauss point of every edge, both layers */
     double *eo = (double *)malloc(sizeof(double) * (size_t)E * 2 * 2 * 26);
 #define EO(e, g, layer) (eo + (((size_t)(e) * 2 + (g)) * 2 + (layer)) * 26)
-#pragma omp parallel for schedule(dynamic, 256)
+#pragma omp parallel for schedule(dynamic, 256) if(E >= OMP_MIN_ITEMS)
     for (int e = 0; e < E; e++) {
         int L = m->e_cell[2 * e], R = m->e_cell[2 * e + 1];
         int kL = m->e_lk[2 * e], kR = m->e_lk[2 * e + 1];
@@ -1576,7 +1579,7 @@ int om_operator_src(const om_mesh *m, const om_params *p, double dt, const doubl
     }
 
     /* 4. cell gather: flux divergence, Green-Gauss gradients of the interface values, sources */
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if(T >= OMP_MIN_ITEMS)
     for (int c = 0; c < T; c++) {
         double LF[6] = {0}, LFt[6] = {0}, GG[6][2] = {{0}}, GGt[6][2] = {{0}};
         double hsum[6] = {0}, htsum[6] = {0};
@@ -1749,7 +1752,7 @@ void om_mass(const om_mesh *m, const double *W, double *mass)
 
 void om_features(const om_mesh *m, double G, const double *W, const double *gW, double *X)
 {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if(m->nt >= OMP_MIN_ITEMS)
     for (int c = 0; c < m->nt; c++) {
         double q[NS][NV], gq[NS][NV][2];
         for (int l = 0; l < NS; l++) {

@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 import json
 import os
+import sys
 
 import numpy as np
 
@@ -210,8 +211,11 @@ class Mesh:
             load().gks_mesh_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        self.close()
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module's globals may already be gone; the process's end frees
+        # the device memory then
+        if not _finalizing():
+            self.close()
 
 
 def make_params(G=9.81, chi=0.98, cfl=0.3, eps=0.05, eps_num=5.0, t_end=0.0, precision="fp64", linear=False,
@@ -409,8 +413,11 @@ class State:
             load().gks_state_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        self.close()
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module's globals may already be gone; the process's end frees
+        # the device memory then
+        if not _finalizing():
+            self.close()
 
 
 class Trainer:
@@ -475,5 +482,8 @@ class Trainer:
             load().gks_trainer_destroy(self._h)
             self._h = None
 
-    def __del__(self):
-        self.close()
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the module's globals may already be gone; the process's end frees
+        # the device memory then
+        if not _finalizing():
+            self.close()

@@ -20,6 +20,7 @@ precisions; and the FP64 arithmetic of the flux kernel against the vector ALU pe
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -349,6 +350,64 @@ def cpu_baseline_and_errors(sc, res, precs, n_steps=20):
     return cpu, errs
 
 
+def split_by_triangles(scs, parts=2):
+    """Scenario indices in `parts` groups of near-equal triangle counts (largest first, each to the
+    lightest group so far)."""
+    groups, load = [[] for _ in range(parts)], [0] * parts
+    for i in sorted(range(len(scs)), key=lambda i: -scs[i].n_tri):
+        g = load.index(min(load))
+        groups[g].append(i)
+        load[g] += scs[i].n_tri
+    return [sorted(g) for g in groups]
+
+
+def run_ensemble_two_streams(scs, steps, warmup):
+    """The same ensemble as two half-batches of equal triangle count, each a state of its own on its
+    own stream and replayed from its own graph: the GPU then runs one half's memory-bound kernels
+    beside the other's arithmetic-bound ones.  Timed from one event on the current stream, which both
+    streams wait on, to one recorded after both are joined back."""
+    import torch
+
+    from paper_2306_04467_amd import Mesh, State
+
+    T = sum(s.n_tri for s in scs)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    states = []
+    for g, strm in zip(split_by_triangles(scs), streams):
+        part = [scs[i] for i in g]
+        meshes = [Mesh.from_scenario(s) for s in part]
+        bm = Mesh.batch(meshes)
+        for m in meshes:
+            m.close()
+        st = State.from_scenarios(bm, part, precision="fp32", stream=ctypes.c_void_p(strm.cuda_stream))
+        tune(st)
+        states.append((st, bm))
+    for st, _ in states:
+        st.batch_step(warmup)
+    torch.cuda.synchronize()
+    main = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(main)
+    for strm in streams:
+        strm.wait_event(e0)
+    for _ in range(steps):
+        for st, _ in states:
+            st.batch_step(1)
+    for strm in streams:
+        main.wait_stream(strm)
+    e1.record(main)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = T * 2 * steps / (ms / 1e3)
+    log(f"ensemble fp32 graph, two half-batches on two streams: {steps} steps {ms:.2f} ms, "
+        f"{value / 1e9:.3f} G tri-stage/s")
+    for st, bm in states:
+        st.close()
+        bm.close()
+    return {"value": round(value, 1), "ms_per_step": round(ms / steps, 5),
+            "launch": "two states of equal triangle count, one HIP graph each, on two streams"}
+
+
 def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
     import numpy as np
 
@@ -374,6 +433,7 @@ def run_ensemble(n_scen, steps, warmup, with_error, indicator=None):
            "steps": steps, "n_scenarios": n_scen, "n_tri": T, "precision": "fp32-mixed",
            "launch": "one HIP graph replay per step (all scenarios, both stages)", "threads_per_block": shapes}
     st.close()
+    out["two_streams"] = run_ensemble_two_streams(scs, steps, warmup)
     if indicator is not None:
         # the same batch with the learned indicator fused into the reconstruction
         P, thr = indicator

@@ -132,6 +132,43 @@ def test_batch_graph_replay_matches_eager_steps(gks):
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_two_batches_on_two_streams_match_the_whole_batch(gks, precision):
+    """An ensemble split into two batch states on two streams, their graph replays interleaved so
+    that the GPU may run both at once, gives every scenario the state the whole batch gives it, bit
+    for bit: the states share no device memory."""
+    import ctypes
+
+    import torch
+
+    scs = [w.lake_at_rest(40, seed=41, chi=0.93, perturb=3e-3), w.dam_break(50, seed=42, chi=0.97),
+           w.lake_at_rest(45, seed=43, chi=0.91, perturb=1e-2), w.dam_break(35, seed=44, chi=0.95)]
+    bm = gks.Mesh.batch([gks.Mesh.from_scenario(sc) for sc in scs])
+    whole = gks.State.from_scenarios(bm, scs, precision=precision)
+    whole.batch_step(7)
+    Ww, gWw, _ = whole.read()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    parts = []
+    for idx, strm in zip(([0, 2], [1, 3]), streams):
+        sub = [scs[i] for i in idx]
+        m = gks.Mesh.batch([gks.Mesh.from_scenario(sc) for sc in sub])
+        st = gks.State.from_scenarios(m, sub, precision=precision, stream=ctypes.c_void_p(strm.cuda_stream))
+        parts.append((idx, m, st))
+    for _ in range(7):
+        for _, _, st in parts:
+            st.batch_step(1)
+    torch.cuda.synchronize()
+    for idx, m, st in parts:
+        W, gW, _ = st.read()
+        for j, i in enumerate(idx):
+            c0, n = bm.scenario_range(i)
+            d0, dn = m.scenario_range(j)
+            assert dn == n
+            assert np.array_equal(W[:, d0:d0 + n], Ww[:, c0:c0 + n]), i
+            assert np.array_equal(gW[:, :, d0:d0 + n], gWw[:, :, c0:c0 + n]), i
+            assert st.time(j) == whole.time(i), i
+
+
 def test_scenarios_stop_at_their_end_times(gks):
     """A scenario that reaches its t_end stays unchanged by later steps while the others go on:
     the finished one equals its own single run stopped at t_end, bit for bit."""

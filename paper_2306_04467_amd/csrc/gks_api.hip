@@ -325,6 +325,20 @@ void dt_any(gks_state *s, hipStream_t st)
         launch_dt<float>(s, st);
 }
 
+// The least-squares operators as the reconstruction reads them: block-major, each block of
+// RECON_CELLS cells holding its 153 rows of RECON_CELLS entries as one contiguous span
+// ([ceil(T / RECON_CELLS)][153][RECON_CELLS], the last block padded with zeros), so that a block's
+// operators stream in as one piece.  The host mesh keeps them row-major [153][T].
+std::vector<double> operators_block_major(const gks::HostMesh &h)
+{
+    const int64_t T = h.nt, C = gks::RECON_CELLS, nb = (T + C - 1) / C;
+    std::vector<double> out((size_t)(nb * 153 * C), 0.0);
+    for (int64_t b = 0; b < nb; b++)
+        for (int64_t j = 0; j < 153; j++)
+            for (int64_t l = 0; l < C && b * C + l < T; l++) out[(size_t)((b * 153 + j) * C + l)] = h.M[(size_t)(j * T + b * C + l)];
+    return out;
+}
+
 gks_status upload_mesh(gks_mesh *m)
 {
     const gks::HostMesh &h = m->host;
@@ -355,7 +369,10 @@ gks_status upload_mesh(gks_mesh *m)
     up(h.scell, &d.scell);
     up(h.cand, &d.cand);
     const double *M = nullptr, *hs = nullptr, *vtx = nullptr, *nbc = nullptr, *en = nullptr, *egB = nullptr;
-    up(h.M, &M);
+    {
+        const std::vector<double> Mb = operators_block_major(h);
+        up(Mb, &M);
+    }
     up(h.hs, &hs);
     up(h.vtx, &vtx);
     up(h.nbc, &nbc);
@@ -404,7 +421,7 @@ gks_status ensure_f32(gks_mesh *m)
     gks::MeshDev &d = m->d32;
     hipError_t e = hipSuccess;
     std::vector<void *> &o = m->owned;
-    if (e == hipSuccess) e = upload_f32(h.M, &d.M, o);
+    if (e == hipSuccess) e = upload_f32(operators_block_major(h), &d.M, o);
     if (e == hipSuccess) e = upload_f32(h.hs, &d.hs, o);
     if (e == hipSuccess) e = upload_f32(h.vtx, &d.vtx, o);
     if (e == hipSuccess) e = upload_f32(h.nbc, &d.nbc, o);

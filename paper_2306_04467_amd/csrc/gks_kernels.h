@@ -32,7 +32,8 @@ struct MeshDev {
     int32_t S;                      // number of scenarios (independent meshes) in this mesh
     // FP64 tables
     const double *area, *Bbar, *gB, *fl, *gg, *eBgp, *gR, *sdxmin;
-    // tables in the bulk precision (double or float copies)
+    // tables in the bulk precision (double or float copies); M, the least-squares operators, is
+    // block-major [ceil(T / RECON_CELLS)][153][RECON_CELLS]
     const void *M, *hs, *vtx, *nbc, *en, *egB;
     const float *igeo;              // [6][T] indicator geometry
     const uint8_t *cand;            // [T] plane candidates of the nonlinear reconstruction (bits 0..2)
@@ -616,8 +617,8 @@ __global__ void __launch_bounds__(192) k_recon(MeshDev m, Phys p, const double *
         R buf[IT];
 #pragma unroll
         for (int it = 0; it < IT; it++) {
-            const int i = (int)threadIdx.x + 192 * it, j = i / RECON_CELLS, l = i % RECON_CELLS;
-            buf[it] = (i < NM && l < ncell) ? M[(int64_t)j * T + c0 + l] : R(0);
+            const int i = (int)threadIdx.x + 192 * it, l = i % RECON_CELLS;
+            buf[it] = (i < NM && l < ncell) ? M[c0 * 153 + i] : R(0);  // block-major operators
         }
 #pragma unroll
         for (int it = 0; it < IT; it++) {
